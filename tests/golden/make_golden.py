@@ -1,0 +1,73 @@
+"""Write tests/golden/config_values.json: expected results of the full-size
+workloads, computed by the CPU oracle only (oracle/) on inputs from workloads/.
+
+    python tests/golden/make_golden.py [--threads T] [--only KEY ...]
+
+Config 2 (two sets of about 2^20 spheres, 5.5e11 pair tests each) takes tens of
+minutes on 8 cores; the others take seconds to minutes.  Existing keys are kept
+unless recomputed.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+import workloads as w  # noqa: E402
+
+OUT = os.path.join(HERE, "config_values.json")
+
+
+def compute(key, threads):
+    if key == "config1_count":
+        return oracle.count_i32(*w.config1().arrays(), threads=threads)
+    if key == "config2_even_count":
+        return oracle.count_i32(*w.config2(2 ** 20).arrays(), threads=threads)
+    if key == "config2_odd_count":
+        return oracle.count_i32(*w.config2(2 ** 20 - 1).arrays(), threads=threads)
+    if key == "config3_energy_total":
+        return oracle.energy_total(*w.config3().arrays(), np.float32(1e-4), threads=threads)
+    if key == "config4_counts":
+        b = w.config4()
+        c = oracle.count_i32_batched(*b.objs.arrays(), b.offsets, threads=threads)
+        return {"total": int(c.sum()),
+                "sha256_le_u64": hashlib.sha256(c.astype("<u8").tobytes()).hexdigest(),
+                "first16": [int(v) for v in c[:16]]}
+    raise KeyError(key)
+
+
+KEYS = ["config1_count", "config4_counts", "config3_energy_total", "config2_odd_count",
+        "config2_even_count"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--only", nargs="*", default=None)
+    a = ap.parse_args()
+    data = {}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            data = json.load(f)
+    data.setdefault("_about", "Expected values of the full-size workloads, written by "
+                    "tests/golden/make_golden.py from the CPU oracle only.")
+    for key in (a.only or KEYS):
+        t = time.time()
+        data[key] = compute(key, a.threads)
+        print(f"{key}: {data[key]}  ({time.time() - t:.1f} s, "
+              f"{oracle.threads(a.threads)} threads)", flush=True)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+            f.write("\n")
+
+
+if __name__ == "__main__":
+    main()
