@@ -1,0 +1,181 @@
+"""Benchmark of the balanced all-pairs collision count on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+One step is one call of the hot path on the headline workload: the exact
+collision count of one set of N = 2^20 int32 spheres (centres uniform in
+[0, 2^24)^3, radii uniform in [1, 2^14], seed 2), 549 755 289 600 pair tests,
+inputs resident in device memory.  The timed region is bracketed by stream
+synchronisation; per-step durations come from HIP events recorded on the
+stream the kernels run on.  Prints one JSON line.
+
+Secondary lines of the same run (odd N, the float32 energy, the small set) are
+reported under "secondary"; the CPU oracle timed on a bounded sample of the
+same workload is reported under "cpu_baseline".
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs, 64 lanes per CU per cycle of VALU issue, 2.4 GHz peak engine clock
+N_CU = 256
+VALU_LANES_PER_CU = 64
+SCLK_HZ = 2.4e9
+VALU_PEAK = N_CU * VALU_LANES_PER_CU * SCLK_HZ          # lane-operations per second
+# Algorithmic VALU work per pair test of each kernel (lane-operations):
+#   exact int32 count, Gram form: 4 fused multiply-adds + 1 compare
+#   float32 energy per pair: 3 sub + 3 fma + 1 rsqrt (half rate: 2) + 2 adds
+C_ALG = {"count_i32": 5, "energy_f32": 10}
+PLAIN_DEF_OPS = 12   # operations of the plain definition per pair (either kind)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record()
+        fn()
+        ends[k].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return ms, wall
+
+
+def cpu_baseline(sample_n):
+    import oracle
+    import workloads as w
+    s = w.config2(2 ** 20)
+    arrs = [a[:sample_n].copy() for a in s.arrays()]
+    threads = oracle.threads(0)
+    t = time.perf_counter()
+    oracle.count_i32(*arrs, threads=0)
+    dt = time.perf_counter() - t
+    pairs = sample_n * (sample_n - 1) // 2
+    return {"value": pairs / dt / 1e9, "unit": "G pair tests/s", "cores": threads,
+            "kind": "oracle", "seconds": dt,
+            "sample": f"plain i<j loop over the first {sample_n} spheres of the N=2^20 "
+                      f"set ({pairs} pair tests), {threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=180_000)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
+              "(the path has no multi-GPU mode in this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1901_11204_amd as P
+    import workloads as w
+
+    P.lib()
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+
+    # headline workload
+    n = 2 ** 20
+    s = w.config2(n)
+    x, y, z, r = (torch.from_numpy(v).to(dev) for v in s.arrays())
+    out = torch.empty(1, dtype=torch.int64, device=dev)
+    pairs = n * (n - 1) // 2
+    log(f"[bench] count_i32 N={n}: {a.warmup} warmup + {a.steps} timed steps")
+    ms, wall = timed_steps(lambda: P.pairs_count_i32(x, y, z, r, out), a.steps, a.warmup)
+    ms_step = float(np.mean(ms))
+    value = pairs / (ms_step * 1e-3) / 1e9
+    achieved = pairs / (ms_step * 1e-3) * C_ALG["count_i32"]
+    count = int(out.item())
+
+    rec = {
+        "metric": "pair tests/sec (G pairs/s) and % of VALU peak; batched vs single-set on 1 GPU",
+        "value": value,
+        "unit": "G pair tests/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32 in, f64 exact predicate, u64 count",
+        "data": "synthetic (seeded uniform spheres)",
+        "config": {"workload": "single set, N=2^20 int32 spheres, centres in [0,2^24)^3, "
+                               "radii in [1,2^14], seed 2; exact collision count",
+                   "n": n, "pair_tests": pairs, "parallelism": "single GPU"},
+        "result": {"count": count},
+        "timing": {"ms_min": float(np.min(ms)), "ms_median": float(np.median(ms)),
+                   "ms_max": float(np.max(ms)), "wall_s": wall},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                     "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                     "per_pair_ops": C_ALG["count_i32"],
+                     "plain_definition_frac": pairs / (ms_step * 1e-3) * PLAIN_DEF_OPS / VALU_PEAK},
+    }
+
+    if not a.no_secondary:
+        sec = {}
+        n2 = 2 ** 20 - 1
+        s2 = w.config2(n2)
+        t2 = [torch.from_numpy(v).to(dev) for v in s2.arrays()]
+        p2 = n2 * (n2 - 1) // 2
+        log(f"[bench] count_i32 N={n2}")
+        ms2, _ = timed_steps(lambda: P.pairs_count_i32(*t2, out), max(3, a.steps // 2), 1)
+        m2 = float(np.mean(ms2))
+        sec["count_i32_odd_2^20-1"] = {"ms": m2, "G_pairs_per_s": p2 / m2 / 1e6,
+                                       "valu_frac": p2 / (m2 * 1e-3) * C_ALG["count_i32"] / VALU_PEAK,
+                                       "count": int(out.item())}
+        del t2
+        s1 = w.config1()
+        t1 = [torch.from_numpy(v).to(dev) for v in s1.arrays()]
+        p1 = 4096 * 4095 // 2
+        log("[bench] count_i32 N=4096")
+        ms1, _ = timed_steps(lambda: P.pairs_count_i32(*t1, out), 50, 5)
+        m1 = float(np.median(ms1))
+        sec["count_i32_4096"] = {"ms": m1, "G_pairs_per_s": p1 / m1 / 1e6, "count": int(out.item())}
+        p3 = w.config3()
+        t3 = [torch.from_numpy(v).to(dev) for v in p3.arrays()]
+        n3 = p3.n
+        E = torch.empty(n3, dtype=torch.float64, device=dev)
+        tot = torch.empty(1, dtype=torch.float64, device=dev)
+        pp3 = n3 * (n3 - 1) // 2
+        log(f"[bench] energy_f32 N={n3}")
+        ms3, _ = timed_steps(lambda: P.pairs_energy_f32(*t3, 1e-4, E, tot), max(3, a.steps // 2), 1)
+        m3 = float(np.mean(ms3))
+        sec["energy_f32_2^18"] = {"ms": m3, "G_pairs_per_s": pp3 / m3 / 1e6,
+                                  "valu_frac": pp3 / (m3 * 1e-3) * C_ALG["energy_f32"] / VALU_PEAK,
+                                  "total": float(tot.item())}
+        ms3b, _ = timed_steps(lambda: P.pairs_energy_f32(*t3, 1e-4, None, tot), max(3, a.steps // 2), 1)
+        m3b = float(np.mean(ms3b))
+        sec["energy_f32_2^18_total_only"] = {"ms": m3b, "G_pairs_per_s": pp3 / m3b / 1e6}
+        rec["secondary"] = sec
+
+    if not a.no_cpu_baseline:
+        log(f"[bench] cpu baseline: oracle on {a.cpu_sample} spheres")
+        rec["cpu_baseline"] = cpu_baseline(a.cpu_sample)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

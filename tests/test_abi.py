@@ -1,0 +1,70 @@
+"""The C ABI library on the CPU: it loads, exports every function that
+include/pairs.h declares, and rejects bad arguments before touching a device.
+No computation runs here (there is no GPU in this environment)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1901_11204_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pairs.h")
+
+OK, INVALID, DOMAIN, HIP, NOMEM, WORKSPACE, NODEV = 0, -1, -2, -3, -4, -5, -6
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pairs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for must in ["pairs_count_i32", "pairs_count_f32", "pairs_energy_f32"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_function():
+    L = ctypes.CDLL(P.lib_path())
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = P.lib()
+    for code in [OK, INVALID, DOMAIN, HIP, NOMEM, WORKSPACE, NODEV]:
+        s = L.pairs_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert L.pairs_status_string(12345).decode() == "unknown status"
+
+
+def fake(k):
+    # non-null host addresses that are never dereferenced: every call below
+    # fails its argument check or finds no device before any device access
+    return ctypes.c_void_p(0x1000 * (k + 1))
+
+
+def test_invalid_arguments_are_rejected_on_the_host():
+    L = P.lib()
+    x, y, z, r, out = (fake(k) for k in range(5))
+    assert L.pairs_count_i32(x, y, z, r, -1, out, 0, None) == INVALID
+    assert L.pairs_count_i32(x, y, z, r, 10, None, 0, None) == INVALID
+    assert L.pairs_count_i32(None, y, z, r, 10, out, 0, None) == INVALID
+    assert L.pairs_count_i32(x, y, z, r, 10, out, 0x80, None) == INVALID
+    assert L.pairs_count_i32(x, y, z, r, (1 << 30) + 1, out, 0, None) == INVALID
+    assert L.pairs_count_f32(x, y, z, None, 10, out, 0, None) == INVALID
+    assert L.pairs_energy_f32(x, y, z, 10, 0.0, None, out, 0, None) == INVALID
+    assert L.pairs_energy_f32(x, y, z, 10, float("nan"), None, out, 0, None) == INVALID
+    assert L.pairs_energy_f32(x, y, z, 10, 1e-4, None, None, 0, None) == INVALID
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES", None) is None and
+                    os.path.exists("/dev/kfd"), reason="a device may be present")
+def test_no_device_is_reported():
+    L = P.lib()
+    x, y, z, r, out = (fake(k) for k in range(5))
+    assert L.pairs_count_i32(x, y, z, r, 10, out, 0, None) == NODEV
+    assert L.pairs_energy_f32(x, y, z, 10, 1e-4, None, out, 0, None) == NODEV

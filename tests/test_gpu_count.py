@@ -1,0 +1,140 @@
+"""GPU parity of the collision counts against the CPU oracle (bit-exact)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1901_11204_amd as P
+import workloads as w
+from gpu_util import announce, dev
+
+pytestmark = pytest.mark.gpu
+
+# sizes around every tile edge of the three single-set shapes (64, 256 and 512
+# rows per wave), ragged tails, both parities, and the shape switches
+SIZES = [0, 1, 2, 3, 4, 5, 6, 7, 63, 64, 65, 66, 127, 128, 129, 255, 256, 257, 511, 512, 513,
+         1000, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193, 8194,
+         12345, 16383, 16384, 16385, 30001, 65535, 65536, 65537, 65538]
+
+
+def dense_i32(n, seed):
+    # many collisions: centres in a 48-cube, radii 0..6
+    return w.spheres_i32(n, seed, 48, 6, radius_lo=0)
+
+
+def sparse_i32(n, seed):
+    return w.spheres_i32(n, seed, 2 ** 16, 2 ** 9)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_count_i32_matches_oracle(n):
+    for kind, gen in (("dense", dense_i32), ("sparse", sparse_i32)):
+        s = gen(n, 1000 + n)
+        announce("count_i32", kind, n)
+        expect = oracle.count_i32(*s.arrays())
+        got = P.count_i32(*dev(*s.arrays()))
+        assert got == expect, (kind, n)
+
+
+def test_count_i32_config1():
+    s = w.config1()
+    announce("count_i32 config1")
+    assert P.count_i32(*dev(*s.arrays())) == oracle.count_i32(*s.arrays())
+
+
+def test_count_i32_domain_edges():
+    L = 2 ** 24
+    rng = np.random.default_rng(5)
+    n = 3001
+    x, y, z = (rng.integers(-L, L, n, endpoint=True).astype(np.int32) for _ in range(3))
+    r = rng.integers(0, L, n, endpoint=True).astype(np.int32)
+    # pin a few objects to the extreme corners
+    x[:4] = [-L, L, -L, L]
+    y[:4] = [-L, L, L, -L]
+    z[:4] = [L, -L, -L, L]
+    r[:4] = [L, L, 0, L]
+    announce("count_i32 domain edges", n)
+    assert P.count_i32(*dev(x, y, z, r), validate=True) == oracle.count_i32(x, y, z, r)
+    # touching and one-apart pairs at full span
+    for gap, expect in ((0, 1), (1, 0)):
+        a = np.array([-L, L], np.int32)
+        zero = np.zeros(2, np.int32)
+        rr = np.array([L, L - gap], np.int32)
+        assert P.count_i32(*dev(a, zero, zero, rr)) == expect
+
+
+def test_count_i32_validate_rejects_out_of_domain():
+    import torch
+    s = sparse_i32(100, 3)
+    x = s.x.copy()
+    x[17] = 2 ** 24 + 1
+    t = dev(x, s.y, s.z, s.r)
+    with pytest.raises(P.PairsError) as e:
+        P.count_i32(*t, validate=True)
+    assert e.value.status == -2
+    r = s.r.copy()
+    r[3] = -1
+    with pytest.raises(P.PairsError):
+        P.count_i32(*dev(s.x, s.y, s.z, r), validate=True)
+    torch.cuda.synchronize()
+
+
+def test_count_i32_invariances_and_partition():
+    s = dense_i32(5000, 77)
+    x, y, z, r = s.arrays()
+    c = P.count_i32(*dev(x, y, z, r))
+    perm = np.random.default_rng(0).permutation(len(x))
+    assert P.count_i32(*dev(x[perm], y[perm], z[perm], r[perm])) == c
+    assert P.count_i32(*dev(x - 1000, y + 5, z, r)) == c
+    for split in (1, 64, 1777, 4999):
+        a = [v[:split] for v in (x, y, z, r)]
+        b = [v[split:] for v in (x, y, z, r)]
+        cross = oracle.cross_count_i32(a, b)
+        assert P.count_i32(*dev(*a)) + P.count_i32(*dev(*b)) + cross == c
+    assert all(P.count_i32(*dev(x, y, z, r)) == c for _ in range(3))
+
+
+def golden():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "config_values.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("n,key", [(2 ** 20, "config2_even_count"),
+                                   (2 ** 20 - 1, "config2_odd_count")])
+def test_count_i32_config2_full_size(n, key):
+    g = golden()
+    if key not in g:
+        pytest.skip(f"{key} not yet in tests/golden/config_values.json")
+    s = w.config2(n)
+    announce("count_i32 config2", n)
+    assert P.count_i32(*dev(*s.arrays())) == g[key]
+
+
+F32_SIZES = [0, 1, 2, 3, 64, 65, 127, 129, 511, 513, 1000, 4096, 8193, 20011]
+
+
+@pytest.mark.parametrize("n", F32_SIZES)
+def test_count_f32_matches_oracle(n):
+    rng = np.random.default_rng(n)
+    # unit cube, radius 0.05: a few percent of pairs hit
+    x, y, z = (rng.random(n, dtype=np.float32) for _ in range(3))
+    r = np.full(n, np.float32(0.05))
+    announce("count_f32", n)
+    assert P.count_f32(*dev(x, y, z, r)) == oracle.count_f32(x, y, z, r)
+    # per-object radii and a subnormal-scale cluster
+    r2 = rng.random(n, dtype=np.float32) * np.float32(0.1)
+    xs = (x * np.float32(1e-38)).astype(np.float32)
+    assert P.count_f32(*dev(x, y, z, r2)) == oracle.count_f32(x, y, z, r2)
+    rs = (r2 * np.float32(1e-38)).astype(np.float32)
+    assert P.count_f32(*dev(xs, y * 0, z * 0, rs)) == oracle.count_f32(xs, y * 0, z * 0, rs)
+
+
+def test_count_f32_validate_rejects_nonfinite():
+    n = 50
+    x = np.zeros(n, np.float32)
+    x[7] = np.inf
+    z = np.zeros(n, np.float32)
+    with pytest.raises(P.PairsError):
+        P.count_f32(*dev(x, z, z, z), validate=True)
