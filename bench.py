@@ -29,8 +29,11 @@ SCLK_HZ = 2.4e9
 VALU_PEAK = N_CU * VALU_LANES_PER_CU * SCLK_HZ          # lane-operations per second
 # Algorithmic VALU work per pair test of each kernel (lane-operations):
 #   exact int32 count, Gram form: 4 fused multiply-adds + 1 compare
-#   float32 energy per pair: 3 sub + 3 fma + 1 rsqrt (half rate: 2) + 2 adds
-C_ALG = {"count_i32": 5, "energy_f32": 10}
+#   float32 energy with per-object sums: 3 sub + 3 fma + 1 rsqrt + 2 adds
+#   float32 energy with the pinned collision count: 3 sub + 1 mul + 2 fma
+#     (pinned squared distance) + add, mul, compare (radius test) + add
+#     (softening) + rsqrt + add
+C_ALG = {"count_i32": 5, "energy_f32": 9, "energy_count_f32": 12}
 PLAIN_DEF_OPS = 12   # operations of the plain definition per pair (either kind)
 
 
@@ -72,6 +75,60 @@ def cpu_baseline(sample_n):
                       f"set ({pairs} pair tests), {threads} OpenMP threads"}
 
 
+def bench_batched(P, w, torch, np, dev, steps):
+    """Batched lines: the binned int32 batch (one persistent launch through a
+    plan, and the unplanned call), and the float32 repeated-step loop captured
+    in one HIP graph of 100 steps."""
+    out = {}
+    b = w.config4()
+    x, y, z, r = (torch.from_numpy(v).to(dev) for v in b.objs.arrays())
+    sizes = np.diff(b.offsets)
+    pairs = int((sizes * (sizes - 1) // 2).sum())
+    counts = torch.empty(b.n_sets, dtype=torch.int64, device=dev)
+    plan = P.Plan(P.KIND_COUNT_I32, b.offsets)
+    log(f"[bench] batched count_i32: {b.n_sets} sets, {pairs} pair tests")
+    ms, _ = timed_steps(lambda: plan.execute((x, y, z, r), (counts,)), max(5, steps), 2)
+    m = float(np.mean(ms))
+    out["count_i32_binned_200k_sets"] = {
+        "workload": "200000 sets, sizes lognormal(4,1.2) clipped to [2,8192], seed 5",
+        "pair_tests": pairs, "ms": m, "G_pairs_per_s": pairs / m / 1e6,
+        "valu_frac": pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK,
+        "n_tasks": plan.info()["n_tasks"], "total_count": int(counts.sum().item())}
+    toff = torch.from_numpy(b.offsets).to(dev)
+    ws = torch.empty(P.pairs_batched_workspace_size(b.n_sets, b.n_total), dtype=torch.uint8,
+                     device=dev)
+    ms, _ = timed_steps(lambda: P.pairs_count_i32_batched(x, y, z, r, toff, counts, ws),
+                        max(5, steps), 2)
+    m = float(np.mean(ms))
+    out["count_i32_binned_200k_sets_unplanned"] = {"ms": m, "G_pairs_per_s": pairs / m / 1e6}
+    plan.close()
+    del x, y, z, r, ws
+
+    b5 = w.config5()
+    x, y, z, r = (torch.from_numpy(v).to(dev) for v in b5.objs.arrays())
+    sizes = np.diff(b5.offsets)
+    pairs5 = int((sizes * (sizes - 1) // 2).sum())
+    nsteps = 100
+    E = torch.empty(nsteps * b5.n_sets, dtype=torch.float64, device=dev)
+    C = torch.empty(nsteps * b5.n_sets, dtype=torch.int64, device=dev)
+    plan5 = P.Plan(P.KIND_ENERGY_F32, b5.offsets)
+    g = plan5.capture_steps(x, y, z, r, seed=6, sigma=1e-3, first_step=0, n_steps=nsteps,
+                            eps2=1e-4, energy=E, counts=C)
+    log(f"[bench] graph of {nsteps} steps: {b5.n_sets} sets, {pairs5} pair tests per step")
+    ms, _ = timed_steps(lambda: g.launch(), 3, 1)
+    m = float(np.mean(ms)) / nsteps
+    ms_j, _ = timed_steps(lambda: P.pairs_jitter_f32(x, y, z, 6, 0, 1e-3), 20, 2)
+    out["energy_count_f32_graph_100_steps"] = {
+        "workload": "50000 sets, sizes lognormal(5,1) clipped to [2,4096], seed 6; "
+                    "per step: jitter + per-set energy and pinned-fp32 count (r=0.01)",
+        "pair_tests_per_step": pairs5, "ms_per_step": m, "G_pairs_per_s": pairs5 / m / 1e6,
+        "valu_frac": pairs5 / (m * 1e-3) * C_ALG["energy_count_f32"] / VALU_PEAK,
+        "jitter_ms": float(np.mean(ms_j))}
+    g.close()
+    plan5.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,7 +136,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=180_000)
+    ap.add_argument("--cpu-sample", type=int, default=420_000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (HBM counter scale)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
@@ -95,6 +154,15 @@ def main():
     P.lib()
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+
+    if a.calibrate_copy:
+        nbytes = a.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        ms, _ = timed_steps(lambda: dst.copy_(src), a.steps, a.warmup)
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "ms": float(np.mean(ms)),
+                          "GB_per_s": 2 * nbytes / (float(np.mean(ms)) * 1e-3) / 1e9}), flush=True)
+        return
 
     # headline workload
     n = 2 ** 20
@@ -170,6 +238,7 @@ def main():
         m3b = float(np.mean(ms3b))
         sec["energy_f32_2^18_total_only"] = {"ms": m3b, "G_pairs_per_s": pp3 / m3b / 1e6}
         rec["secondary"] = sec
+        rec["batched"] = bench_batched(P, w, torch, np, dev, a.steps)
 
     if not a.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {a.cpu_sample} spheres")

@@ -67,9 +67,22 @@ enum {
 #define PAIRS_I32_COORD_LIMIT (1 << 24)
 #define PAIRS_I32_RADIUS_LIMIT (1 << 24)
 
-/* Largest number of objects in one set (single-set calls and each set of a
- * batch): row and partner indices are 32-bit inside the kernels. */
+/* Largest number of objects in one set of a single-set call: row and
+ * partner indices are 32-bit inside the kernels. */
 #define PAIRS_MAX_SET_SIZE ((int64_t)1 << 30)
+
+/* Largest number of objects in one set of a batch. */
+#define PAIRS_MAX_BATCH_SET_SIZE ((int64_t)1 << 24)
+
+/* Kinds of batched work (plans). */
+enum {
+    PAIRS_KIND_COUNT_I32 = 1, /* per-set exact int32 collision counts */
+    PAIRS_KIND_COUNT_F32 = 2, /* per-set pinned-binary32 collision counts */
+    PAIRS_KIND_ENERGY_F32 = 3 /* per-set potential totals, optionally with counts */
+};
+
+typedef struct pairs_plan_s *pairs_plan_t;
+typedef struct pairs_graph_s *pairs_graph_t;
 
 /* ------------------------------------------------------------ single set -- */
 
@@ -116,6 +129,132 @@ pairs_status_t pairs_count_f32(const float *x, const float *y, const float *z,
 pairs_status_t pairs_energy_f32(const float *x, const float *y, const float *z, int64_t n,
                                 float eps2, double *d_energy, double *d_total,
                                 unsigned flags, pairs_stream_t stream);
+
+/* --------------------------------------------------------------- batches -- */
+/*
+ * A batch is a CSR list of independent sets (the pruned sets that a spatial
+ * partition or a bounding-volume hierarchy produces, paper Sections 1 and 6):
+ * set s owns objects [offsets[s], offsets[s+1]) of the object arrays, with
+ * offsets[0] = 0, offsets non-decreasing, offsets[n_sets] = n_total and every
+ * set at most PAIRS_MAX_BATCH_SET_SIZE objects.  Each set is the single-set
+ * problem above; all sets are processed by one persistent kernel launch.
+ *
+ * Unplanned calls take the offsets in device memory (d_offsets, int64
+ * [n_sets + 1]) and a caller workspace of at least
+ * pairs_batched_workspace_size() bytes (device memory, 256-byte aligned, not
+ * shared with a concurrent call).  They schedule the work on the device and
+ * never wait for the host.  Offsets that break the rules above give undefined
+ * per-set results (never an access outside the arrays) unless
+ * PAIRS_FLAG_VALIDATE is given, which returns PAIRS_ERR_INVALID_ARG for bad
+ * offsets and PAIRS_ERR_DOMAIN for bad values.
+ */
+pairs_status_t pairs_batched_workspace_size(int64_t n_sets, int64_t n_total, size_t *bytes);
+
+/* d_counts[s] = collision count of set s (the pairs_count_i32 predicate). */
+pairs_status_t pairs_count_i32_batched(const int32_t *x, const int32_t *y, const int32_t *z,
+                                       const int32_t *r, const int64_t *d_offsets,
+                                       int64_t n_sets, int64_t n_total, uint64_t *d_counts,
+                                       void *d_ws, size_t ws_bytes, unsigned flags,
+                                       pairs_stream_t stream);
+
+/* d_counts[s] = collision count of set s (the pairs_count_f32 predicate). */
+pairs_status_t pairs_count_f32_batched(const float *x, const float *y, const float *z,
+                                       const float *r, const int64_t *d_offsets,
+                                       int64_t n_sets, int64_t n_total, uint64_t *d_counts,
+                                       void *d_ws, size_t ws_bytes, unsigned flags,
+                                       pairs_stream_t stream);
+
+/* d_set_energy[s] = sum over the pairs of set s of 1/sqrt(d^2 + eps2) (double;
+ * relative error at most 1e-6 per set), and, if r is not NULL, d_set_counts[s]
+ * = the set's pinned-binary32 collision count.  r and d_set_counts are both
+ * NULL or both non-NULL.  With r given, e uses fl(d2 + eps2) with d2 the
+ * pinned squared distance. */
+pairs_status_t pairs_energy_f32_batched(const float *x, const float *y, const float *z,
+                                        const float *r, const int64_t *d_offsets,
+                                        int64_t n_sets, int64_t n_total, float eps2,
+                                        double *d_set_energy, uint64_t *d_set_counts, void *d_ws,
+                                        size_t ws_bytes, unsigned flags, pairs_stream_t stream);
+
+/* ----------------------------------------------------------------- plans -- */
+/*
+ * A plan fixes the set sizes of a batch (h_offsets: HOST int64[n_sets + 1],
+ * same rules as above, checked on the host) and precomputes its schedule: a
+ * task table ordered so that the tasks of the largest sets run first.  The
+ * plan owns that table and a device copy of the offsets (allocated by create,
+ * freed by destroy) on the device current at create.  The task table must
+ * have fewer than 2^31 entries (PAIRS_ERR_INVALID_ARG otherwise).
+ *
+ * execute enqueues the batch on `stream` with no allocation and no host
+ * wait, so it may be captured into a HIP graph.  in[] and out[] by kind:
+ *   PAIRS_KIND_COUNT_I32: in = {x, y, z, r} (int32),  out = {counts (uint64[n_sets])}
+ *   PAIRS_KIND_COUNT_F32: in = {x, y, z, r} (float),  out = {counts}
+ *   PAIRS_KIND_ENERGY_F32: in = {x, y, z, r or NULL} (float),
+ *                          out = {energy (double[n_sets]), counts or NULL}
+ * eps2 is used by PAIRS_KIND_ENERGY_F32 only.  A plan must not execute on two
+ * streams at once.
+ */
+pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_sets,
+                                 pairs_plan_t *plan);
+pairs_status_t pairs_plan_execute(pairs_plan_t plan, const void *const *in, void *const *out,
+                                  float eps2, pairs_stream_t stream);
+pairs_status_t pairs_plan_info(pairs_plan_t plan, int64_t *n_sets, int64_t *n_total,
+                               int64_t *n_tasks);
+pairs_status_t pairs_plan_destroy(pairs_plan_t plan);
+
+/* ------------------------------------------------------- repeated steps -- */
+/*
+ * Per-step perturbation of moving objects (paper, Introduction: objects in
+ * motion whose interactions are recomputed every small time step).  Object k
+ * (global index first_index + k, below 2^32) gets, per axis a, the
+ * zero-mean perturbation of standard deviation sigma
+ *   delta = fl32(fl32(S) * c),  c = fl32(sigma / sqrt((4/3)(2^48 - 1))),
+ *   S = 2 (w0>>8 + w1>>8 + w2>>8 + w3>>8) - 4 (2^24 - 1)
+ * where w = Philox4x32-10 (Salmon et al., SC 2011) of the counter
+ * (global index, step, a, 0) under the key (seed low 32 bits, seed high 32
+ * bits); then x = fl32(x + delta).  S is an Irwin-Hall(4) variate, an
+ * approximation of a normal variate bounded at about 3.46 standard
+ * deviations; every step is exactly rounded, so the result is reproducible
+ * bit for bit.  Coordinates are updated in place.
+ */
+pairs_status_t pairs_jitter_f32(float *x, float *y, float *z, int64_t n, uint64_t seed,
+                                uint32_t step, float sigma, int64_t first_index,
+                                pairs_stream_t stream);
+
+/*
+ * Captures n_steps repeated steps of an energy plan into one HIP graph: for
+ * k = 0 .. n_steps-1, jitter all plan objects with step first_step + k, then
+ * execute the plan into row k of d_energy (double[n_steps][n_sets]) and, if r
+ * is not NULL, of d_counts (uint64[n_steps][n_sets]).  Launching the graph
+ * runs all steps with no host involvement; positions accumulate across steps
+ * and launches.  The graph keeps the pointers given here.
+ */
+pairs_status_t pairs_plan_capture_steps(pairs_plan_t plan, float *x, float *y, float *z,
+                                        const float *r, uint64_t seed, float sigma,
+                                        uint32_t first_step, int n_steps, float eps2,
+                                        double *d_energy, uint64_t *d_counts,
+                                        pairs_graph_t *graph);
+pairs_status_t pairs_graph_launch(pairs_graph_t graph, pairs_stream_t stream);
+pairs_status_t pairs_graph_destroy(pairs_graph_t graph);
+
+/* ---------------------------------------------------------- introspection -- */
+/*
+ * Host-only: the wave tasks of a single set of n objects for the tile shape
+ * (rows_per_lane in {1, 2, 4, 8}, chunk a positive multiple of 64).  Task k is
+ * written as out[3k] = first row ra, out[3k+1] = u0, out[3k+2] = u1: rows
+ * [ra, ra + 64*rows_per_lane) evaluate their balanced-assignment partners
+ * (row + s) mod n for every virtual partner u = row + s in [u0, u1).
+ * *n_tasks receives the task count; out may be NULL to query it only.
+ */
+pairs_status_t pairs_debug_task_ranges(int n, int rows_per_lane, int chunk, int32_t *out,
+                                       int64_t capacity, int64_t *n_tasks);
+
+/* ---------------------------------------------------------------- errors -- */
+
+/* Static text for a status code. */
+const char *pairs_status_string(pairs_status_t status);
+
+/* hipError_t of the last failing HIP call on the calling thread. */
+int pairs_last_hip_error(void);
 
 #ifdef __cplusplus
 }

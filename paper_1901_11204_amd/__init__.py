@@ -16,7 +16,11 @@ import os
 
 __all__ = [
     "PairsError", "lib", "lib_path", "FLAG_VALIDATE",
+    "KIND_COUNT_I32", "KIND_COUNT_F32", "KIND_ENERGY_F32",
     "pairs_count_i32", "pairs_count_f32", "pairs_energy_f32",
+    "pairs_batched_workspace_size", "pairs_count_i32_batched", "pairs_count_f32_batched",
+    "pairs_energy_f32_batched", "pairs_jitter_f32", "pairs_debug_task_ranges",
+    "Plan", "Graph",
     "count_i32", "count_f32", "energy_f32",
 ]
 
@@ -25,6 +29,7 @@ _LIB_PATH = os.path.join(_HERE, "libpairs.so")
 _lib = None
 
 FLAG_VALIDATE = 1
+KIND_COUNT_I32, KIND_COUNT_F32, KIND_ENERGY_F32 = 1, 2, 3
 
 _STATUS = {
     0: "ok", -1: "invalid argument", -2: "input outside the exact domain",
@@ -53,11 +58,34 @@ _u32 = ctypes.c_uint32
 _f32 = ctypes.c_float
 
 
+_sz = ctypes.c_size_t
+_u64 = ctypes.c_uint64
+_int = ctypes.c_int
+
+
 def _declare(L):
     sig = {
         "pairs_count_i32": [_vp, _vp, _vp, _vp, _i64, _vp, _u32, _vp],
         "pairs_count_f32": [_vp, _vp, _vp, _vp, _i64, _vp, _u32, _vp],
         "pairs_energy_f32": [_vp, _vp, _vp, _i64, _f32, _vp, _vp, _u32, _vp],
+        "pairs_batched_workspace_size": [_i64, _i64, ctypes.POINTER(_sz)],
+        "pairs_count_i32_batched": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _sz, _u32,
+                                    _vp],
+        "pairs_count_f32_batched": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _sz, _u32,
+                                    _vp],
+        "pairs_energy_f32_batched": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f32, _vp, _vp, _vp,
+                                     _sz, _u32, _vp],
+        "pairs_plan_create": [_int, _vp, _i64, ctypes.POINTER(_vp)],
+        "pairs_plan_execute": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _f32, _vp],
+        "pairs_plan_info": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                            ctypes.POINTER(_i64)],
+        "pairs_plan_destroy": [_vp],
+        "pairs_jitter_f32": [_vp, _vp, _vp, _i64, _u64, _u32, _f32, _i64, _vp],
+        "pairs_plan_capture_steps": [_vp, _vp, _vp, _vp, _vp, _u64, _f32, _u32, _int, _f32, _vp,
+                                     _vp, ctypes.POINTER(_vp)],
+        "pairs_graph_launch": [_vp, _vp],
+        "pairs_graph_destroy": [_vp],
+        "pairs_debug_task_ranges": [_int, _int, _int, _vp, _i64, ctypes.POINTER(_i64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -142,6 +170,186 @@ def pairs_energy_f32(x, y, z, eps2: float, energy, total, flags: int = 0, stream
         _require((energy,), torch.float64, n, "pairs_energy_f32 energy")
     _check(lib().pairs_energy_f32(_ptr(x), _ptr(y), _ptr(z), n, float(eps2), _ptr(energy),
                                   _ptr(total), flags, _stream(stream)), "pairs_energy_f32")
+
+
+def pairs_batched_workspace_size(n_sets: int, n_total: int) -> int:
+    """Bytes of device workspace an unplanned batched call needs."""
+    b = _sz(0)
+    _check(lib().pairs_batched_workspace_size(n_sets, n_total, ctypes.byref(b)),
+           "pairs_batched_workspace_size")
+    return int(b.value)
+
+
+def _batch_checks(x, tensors, dtype, offsets, what):
+    import torch
+    n_total = int(x.shape[0])
+    _require(tensors, dtype, n_total, what)
+    if offsets.dtype != torch.int64 or offsets.device.type != "cuda" or offsets.dim() != 1 \
+            or not offsets.is_contiguous():
+        raise ValueError(f"{what}: offsets must be a contiguous int64 device tensor")
+    return n_total, int(offsets.shape[0]) - 1
+
+
+def _workspace(ws, n_sets, n_total, device):
+    import torch
+    need = pairs_batched_workspace_size(n_sets, n_total)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+    return ws, int(ws.numel() * ws.element_size())
+
+
+def pairs_count_i32_batched(x, y, z, r, offsets, counts, ws=None, flags: int = 0,
+                            stream=None) -> None:
+    """Per-set exact collision counts of a CSR batch into counts (int64[n_sets],
+    read as uint64).  ws: device workspace (allocated here if None)."""
+    import torch
+    n_total, n_sets = _batch_checks(x, (x, y, z, r), torch.int32, offsets,
+                                    "pairs_count_i32_batched")
+    _require((counts,), torch.int64, n_sets, "pairs_count_i32_batched counts")
+    ws, nbytes = _workspace(ws, n_sets, n_total, x.device)
+    _check(lib().pairs_count_i32_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(r), _ptr(offsets),
+                                         n_sets, n_total, _ptr(counts), _ptr(ws), nbytes, flags,
+                                         _stream(stream)), "pairs_count_i32_batched")
+
+
+def pairs_count_f32_batched(x, y, z, r, offsets, counts, ws=None, flags: int = 0,
+                            stream=None) -> None:
+    """Per-set pinned-binary32 collision counts of a CSR batch."""
+    import torch
+    n_total, n_sets = _batch_checks(x, (x, y, z, r), torch.float32, offsets,
+                                    "pairs_count_f32_batched")
+    _require((counts,), torch.int64, n_sets, "pairs_count_f32_batched counts")
+    ws, nbytes = _workspace(ws, n_sets, n_total, x.device)
+    _check(lib().pairs_count_f32_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(r), _ptr(offsets),
+                                         n_sets, n_total, _ptr(counts), _ptr(ws), nbytes, flags,
+                                         _stream(stream)), "pairs_count_f32_batched")
+
+
+def pairs_energy_f32_batched(x, y, z, r, offsets, eps2, energy, counts=None, ws=None,
+                             flags: int = 0, stream=None) -> None:
+    """Per-set potential totals (float64[n_sets]) and, if r is given, per-set
+    pinned-binary32 collision counts (int64[n_sets])."""
+    import torch
+    tens = (x, y, z) if r is None else (x, y, z, r)
+    n_total, n_sets = _batch_checks(x, tens, torch.float32, offsets, "pairs_energy_f32_batched")
+    _require((energy,), torch.float64, n_sets, "pairs_energy_f32_batched energy")
+    if counts is not None:
+        _require((counts,), torch.int64, n_sets, "pairs_energy_f32_batched counts")
+    ws, nbytes = _workspace(ws, n_sets, n_total, x.device)
+    _check(lib().pairs_energy_f32_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(r), _ptr(offsets),
+                                          n_sets, n_total, float(eps2), _ptr(energy),
+                                          _ptr(counts), _ptr(ws), nbytes, flags,
+                                          _stream(stream)), "pairs_energy_f32_batched")
+
+
+def pairs_jitter_f32(x, y, z, seed: int, step: int, sigma: float, first_index: int = 0,
+                     stream=None) -> None:
+    """One in-place perturbation step of float32 positions (see include/pairs.h)."""
+    import torch
+    n = int(x.shape[0])
+    _require((x, y, z), torch.float32, n, "pairs_jitter_f32")
+    _check(lib().pairs_jitter_f32(_ptr(x), _ptr(y), _ptr(z), n, seed, step, float(sigma),
+                                  first_index, _stream(stream)), "pairs_jitter_f32")
+
+
+def pairs_debug_task_ranges(n: int, rows_per_lane: int, chunk: int):
+    """Host-only: the (first row, u0, u1) of every wave task of a set of n objects."""
+    import numpy as np
+    cnt = _i64(0)
+    _check(lib().pairs_debug_task_ranges(n, rows_per_lane, chunk, None, 0, ctypes.byref(cnt)),
+           "pairs_debug_task_ranges")
+    out = np.zeros((int(cnt.value), 3), dtype=np.int32)
+    _check(lib().pairs_debug_task_ranges(n, rows_per_lane, chunk, out.ctypes.data_as(_vp),
+                                         int(cnt.value), ctypes.byref(cnt)),
+           "pairs_debug_task_ranges")
+    return out
+
+
+class Plan:
+    """A precomputed batched schedule (pairs_plan_create); h_offsets is a host
+    int64 array of n_sets + 1 offsets."""
+
+    def __init__(self, kind: int, h_offsets):
+        import numpy as np
+        off = np.ascontiguousarray(h_offsets, dtype=np.int64)
+        self.kind = kind
+        self.n_sets = int(off.shape[0]) - 1
+        self.n_total = int(off[-1]) if off.shape[0] else 0
+        h = _vp()
+        _check(lib().pairs_plan_create(kind, off.ctypes.data_as(_vp), self.n_sets,
+                                       ctypes.byref(h)), "pairs_plan_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        a, b, c = _i64(0), _i64(0), _i64(0)
+        _check(lib().pairs_plan_info(self._h, ctypes.byref(a), ctypes.byref(b),
+                                     ctypes.byref(c)), "pairs_plan_info")
+        return {"n_sets": a.value, "n_total": b.value, "n_tasks": c.value}
+
+    def execute(self, inputs, outputs, eps2: float = 0.0, stream=None) -> None:
+        """inputs = (x, y, z, r or None); outputs = (counts,) or (energy, counts or None)."""
+        ins = (_vp * 4)(*[None if t is None else t.data_ptr() for t in inputs])
+        outs = (_vp * 2)(*[None if t is None else t.data_ptr() for t in outputs] +
+                         [None] * (2 - len(outputs)))
+        _check(lib().pairs_plan_execute(self._h, ins, outs, float(eps2), _stream(stream)),
+               "pairs_plan_execute")
+
+    def capture_steps(self, x, y, z, r, seed: int, sigma: float, first_step: int,
+                      n_steps: int, eps2: float, energy, counts=None):
+        """Graph of n_steps (jitter, execute) steps; energy is float64[n_steps * n_sets]."""
+        import torch
+        _require((x, y, z) if r is None else (x, y, z, r), torch.float32, self.n_total,
+                 "Plan.capture_steps")
+        need = n_steps * self.n_sets
+        if energy.dtype != torch.float64 or energy.numel() < need or not energy.is_contiguous():
+            raise ValueError(f"Plan.capture_steps: energy must hold {need} float64 values")
+        if (counts is None) != (r is None):
+            raise ValueError("Plan.capture_steps: give both r and counts or neither")
+        if counts is not None and (counts.dtype != torch.int64 or counts.numel() < need
+                                   or not counts.is_contiguous()):
+            raise ValueError(f"Plan.capture_steps: counts must hold {need} int64 values")
+        g = _vp()
+        _check(lib().pairs_plan_capture_steps(self._h, _ptr(x), _ptr(y), _ptr(z), _ptr(r), seed,
+                                              float(sigma), first_step, n_steps, float(eps2),
+                                              _ptr(energy), _ptr(counts), ctypes.byref(g)),
+               "pairs_plan_capture_steps")
+        return Graph(g)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pairs_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured HIP graph of repeated steps (pairs_plan_capture_steps)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def launch(self, stream=None) -> None:
+        _check(lib().pairs_graph_launch(self._h, _stream(stream)), "pairs_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pairs_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # Convenience forms that allocate their outputs.

@@ -64,8 +64,8 @@ struct Tiling {
         }
         t.nblocks = (b.n + t.rows - 1) / t.rows;
         // a block's virtual partners span [ra+1, rlast + steps(rlast)]:
-        // at most rows - 1 + steps(0) values
-        int64_t span = (int64_t)t.rows - 1 + b.steps(0);
+        // at most min(rows, n) - 1 + steps(0) values
+        int64_t span = (int64_t)(t.rows < b.n ? t.rows : b.n) - 1 + b.steps(0);
         t.nchunks = (int)((span + U - 1) / U);
         return t;
     }

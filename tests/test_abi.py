@@ -68,3 +68,41 @@ def test_no_device_is_reported():
     x, y, z, r, out = (fake(k) for k in range(5))
     assert L.pairs_count_i32(x, y, z, r, 10, out, 0, None) == NODEV
     assert L.pairs_energy_f32(x, y, z, 10, 1e-4, None, out, 0, None) == NODEV
+
+
+def test_batched_argument_errors_on_the_host():
+    L = P.lib()
+    x, y, z, r, off, out, ws = (fake(k) for k in range(7))
+    need = P.pairs_batched_workspace_size(10, 100)
+    assert need > 0
+    assert L.pairs_count_i32_batched(x, y, z, r, off, 10, 100, out, ws, need - 1, 0,
+                                     None) == WORKSPACE
+    assert L.pairs_count_i32_batched(x, y, z, r, off, 10, 100, out, None, need, 0,
+                                     None) == WORKSPACE
+    assert L.pairs_count_i32_batched(x, y, z, r, None, 10, 100, out, ws, need, 0,
+                                     None) == INVALID
+    assert L.pairs_count_i32_batched(x, y, z, r, off, -1, 100, out, ws, need, 0, None) == INVALID
+    # energies: r and counts must be both given or both absent
+    assert L.pairs_energy_f32_batched(x, y, z, r, off, 10, 100, 1e-4, out, None, ws, need, 0,
+                                      None) == INVALID
+    assert L.pairs_energy_f32_batched(x, y, z, None, off, 10, 100, 0.0, out, None, ws, need, 0,
+                                      None) == INVALID
+
+
+def test_plan_argument_errors_on_the_host():
+    import numpy as np
+    L = P.lib()
+    h = ctypes.c_void_p()
+    bad = np.array([0, 5, 3], np.int64)
+    assert L.pairs_plan_create(1, bad.ctypes.data_as(ctypes.c_void_p), 2,
+                               ctypes.byref(h)) == INVALID
+    assert L.pairs_plan_create(9, bad.ctypes.data_as(ctypes.c_void_p), 2,
+                               ctypes.byref(h)) == INVALID
+    start = np.array([1, 5], np.int64)
+    assert L.pairs_plan_create(1, start.ctypes.data_as(ctypes.c_void_p), 1,
+                               ctypes.byref(h)) == INVALID
+    assert L.pairs_plan_execute(None, None, None, 0.0, None) == INVALID
+    assert L.pairs_graph_launch(None, None) == INVALID
+    assert L.pairs_plan_destroy(None) == OK
+    assert L.pairs_jitter_f32(x_ := fake(0), fake(1), fake(2), 10, 1, 0, -1.0, 0,
+                              None) == INVALID
