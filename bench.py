@@ -59,6 +59,28 @@ def timed_steps(fn, steps, warmup):
     return ms, wall
 
 
+def valu_probe(torch):
+    """Lane-operations per second of each probe pattern, as a fraction of the
+    256 CU x 64 lane x 2.4 GHz issue peak."""
+    import ctypes
+    from paper_1901_11204_amd import build as B
+    L = ctypes.CDLL(B.PROBE_LIB)
+    L.valu_probe_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]
+    names = ctypes.c_char_p.in_dll(L, "valu_probe_names").value.decode().split(",")
+    blocks = torch.cuda.get_device_properties(0).multi_processor_count * 16
+    out = {"blocks": blocks, "threads_per_block": 256}
+    for k, name in enumerate(names):
+        ms, ops = ctypes.c_double(), ctypes.c_double()
+        rc = L.valu_probe_run(k, blocks, ctypes.byref(ms), ctypes.byref(ops))
+        if rc != 0:
+            raise RuntimeError(f"valu probe {name}: hipError {rc}")
+        rate = ops.value / (ms.value * 1e-3)
+        out[name] = {"ms": ms.value, "T_lane_ops_per_s": rate / 1e12,
+                     "frac_of_peak": rate / VALU_PEAK}
+    return out
+
+
 def cpu_baseline(sample_n):
     import oracle
     import workloads as w
@@ -139,6 +161,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=420_000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter scale)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only measure the VALU issue rate of the kernels' instruction patterns")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
@@ -154,6 +178,10 @@ def main():
     P.lib()
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+
+    if a.valu_probe:
+        print(json.dumps(valu_probe(torch)), flush=True)
+        return
 
     if a.calibrate_copy:
         nbytes = a.calibrate_copy << 20

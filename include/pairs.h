@@ -236,6 +236,29 @@ pairs_status_t pairs_plan_capture_steps(pairs_plan_t plan, float *x, float *y, f
 pairs_status_t pairs_graph_launch(pairs_graph_t graph, pairs_stream_t stream);
 pairs_status_t pairs_graph_destroy(pairs_graph_t graph);
 
+/* ------------------------------------------------------------ tile shapes -- */
+/*
+ * Tile shapes of the kernels, chosen per size class.  One wave handles
+ * 64 * rows_per_lane consecutive rows of a set against a chunk of at most
+ * `chunk` virtual partners.  Entry c of a table applies to sets with
+ * n > min_n[c] that no earlier entry takes; the last entry takes the rest.
+ * Entries are listed from the largest sets down (min_n strictly decreasing),
+ * rows_per_lane is 1, 2, 4 or 8, chunk a multiple of 64 in [64, 2^24].
+ * Tables are per kind (PAIRS_KIND_*) and per mode (batched = 0: single-set
+ * calls, 1: batched calls and plans).  A plan keeps the table of its
+ * creation.  set(NULL) restores the defaults.  Results never depend on the
+ * shapes; only the speed does.
+ */
+typedef struct {
+    int32_t count;            /* entries used, 1..4 */
+    int32_t min_n[4];
+    int32_t rows_per_lane[4];
+    int32_t chunk[4];
+} pairs_shape_table_t;
+
+pairs_status_t pairs_get_shapes(int kind, int batched, pairs_shape_table_t *out);
+pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t *table);
+
 /* ---------------------------------------------------------- introspection -- */
 /*
  * Host-only: the wave tasks of a single set of n objects for the tile shape

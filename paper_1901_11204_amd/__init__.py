@@ -20,7 +20,7 @@ __all__ = [
     "pairs_count_i32", "pairs_count_f32", "pairs_energy_f32",
     "pairs_batched_workspace_size", "pairs_count_i32_batched", "pairs_count_f32_batched",
     "pairs_energy_f32_batched", "pairs_jitter_f32", "pairs_debug_task_ranges",
-    "Plan", "Graph",
+    "Plan", "Graph", "ShapeTable", "pairs_get_shapes", "pairs_set_shapes",
     "count_i32", "count_f32", "energy_f32",
 ]
 
@@ -63,6 +63,12 @@ _u64 = ctypes.c_uint64
 _int = ctypes.c_int
 
 
+class ShapeTable(ctypes.Structure):
+    """pairs_shape_table_t: up to 4 (min_n, rows_per_lane, chunk) entries."""
+    _fields_ = [("count", ctypes.c_int32), ("min_n", ctypes.c_int32 * 4),
+                ("rows_per_lane", ctypes.c_int32 * 4), ("chunk", ctypes.c_int32 * 4)]
+
+
 def _declare(L):
     sig = {
         "pairs_count_i32": [_vp, _vp, _vp, _vp, _i64, _vp, _u32, _vp],
@@ -86,6 +92,8 @@ def _declare(L):
         "pairs_graph_launch": [_vp, _vp],
         "pairs_graph_destroy": [_vp],
         "pairs_debug_task_ranges": [_int, _int, _int, _vp, _i64, ctypes.POINTER(_i64)],
+        "pairs_get_shapes": [_int, _int, ctypes.POINTER(ShapeTable)],
+        "pairs_set_shapes": [_int, _int, ctypes.POINTER(ShapeTable)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -107,7 +115,25 @@ def lib():
         L = ctypes.CDLL(_LIB_PATH)
         _declare(L)
         _lib = L
+        _apply_tuned_shapes()
     return _lib
+
+
+def _apply_tuned_shapes():
+    """Apply the tile shapes of a tuning cache (PAIRS_TUNE_CACHE, else
+    tuned_shapes.json beside this file) when one exists for this device."""
+    path = os.environ.get("PAIRS_TUNE_CACHE") or os.path.join(_HERE, "tuned_shapes.json")
+    if not os.path.exists(path):
+        return
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return
+        from . import autotune
+        autotune.load_cache(path, apply=True)
+    except Exception as e:  # a bad cache only costs speed
+        import warnings
+        warnings.warn(f"tile-shape cache {path} not applied: {e}")
 
 
 def _check(status: int, where: str):
@@ -263,6 +289,26 @@ def pairs_debug_task_ranges(n: int, rows_per_lane: int, chunk: int):
                                          int(cnt.value), ctypes.byref(cnt)),
            "pairs_debug_task_ranges")
     return out
+
+
+def pairs_get_shapes(kind: int, batched: bool):
+    """The tile-shape table as a list of (min_n, rows_per_lane, chunk)."""
+    t = ShapeTable()
+    _check(lib().pairs_get_shapes(kind, int(bool(batched)), ctypes.byref(t)), "pairs_get_shapes")
+    return [(t.min_n[c], t.rows_per_lane[c], t.chunk[c]) for c in range(t.count)]
+
+
+def pairs_set_shapes(kind: int, batched: bool, entries) -> None:
+    """Set the tile-shape table from (min_n, rows_per_lane, chunk) entries,
+    largest sets first; None restores the defaults."""
+    if entries is None:
+        _check(lib().pairs_set_shapes(kind, int(bool(batched)), None), "pairs_set_shapes")
+        return
+    t = ShapeTable()
+    t.count = len(entries)
+    for c, (lo, k, u) in enumerate(entries):
+        t.min_n[c], t.rows_per_lane[c], t.chunk[c] = int(lo), int(k), int(u)
+    _check(lib().pairs_set_shapes(kind, int(bool(batched)), ctypes.byref(t)), "pairs_set_shapes")
 
 
 class Plan:

@@ -1,0 +1,175 @@
+"""Tile-shape autotuner.
+
+The kernels tile each set into wave tasks of 64*K rows against chunks of U
+virtual partners; the best (K, U) depends on the set sizes (small sets waste
+lanes on the two band edges of a row block, large K amortises the partner
+staging over more rows).  Shapes are chosen per size class (include/pairs.h,
+pairs_shape_table_t).  This module times candidate tables on a workload, keeps
+the fastest, and stores the choices in a JSON cache keyed by device
+architecture, kind and mode:
+
+    python -m paper_1901_11204_amd.autotune --workload binned-int32 --out cache.json
+
+The binding applies a cache at load time when PAIRS_TUNE_CACHE names one, or
+when tuned_shapes.json exists next to this file.  Results never depend on the
+shapes, only the speed does.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+from . import (KIND_COUNT_F32, KIND_COUNT_I32, KIND_ENERGY_F32, Plan, pairs_get_shapes,
+               pairs_set_shapes)
+
+ROWS = (1, 2, 4, 8)
+CHUNKS = (128, 256, 512, 1024, 2048, 4096, 8192)
+KIND_NAMES = {KIND_COUNT_I32: "count_i32", KIND_COUNT_F32: "count_f32",
+              KIND_ENERGY_F32: "energy_f32"}
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_shapes.json")
+
+
+def arch() -> str:
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def _time(fn, reps: int = 3, warmup: int = 1) -> float:
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / reps
+
+
+def time_batched(kind, table, offsets, inputs, outputs, eps2=1e-4, reps=3) -> float:
+    """Milliseconds of one plan execution of the batch under `table`."""
+    pairs_set_shapes(kind, True, table)
+    plan = Plan(kind, offsets)
+    try:
+        return _time(lambda: plan.execute(inputs, outputs, eps2), reps)
+    finally:
+        plan.close()
+
+
+def tune_batched(kind, offsets, inputs, outputs, eps2=1e-4, start=None, rounds=1, log=print):
+    """Coordinate descent over the (K, U) of each size class of a batch,
+    largest class first; the class boundaries of `start` stay fixed."""
+    table = [tuple(e) for e in (start or pairs_get_shapes(kind, True))]
+    best = time_batched(kind, table, offsets, inputs, outputs, eps2)
+    log(f"start {table}: {best:.3f} ms")
+    for _ in range(rounds):
+        for c in range(len(table)):
+            for k in ROWS:
+                for u in CHUNKS:
+                    if (k, u) == table[c][1:]:
+                        continue
+                    cand = list(table)
+                    cand[c] = (table[c][0], k, u)
+                    ms = time_batched(kind, cand, offsets, inputs, outputs, eps2)
+                    if ms < best:
+                        best, table = ms, cand
+                        log(f"  class {c} -> K={k} U={u}: {ms:.3f} ms")
+    pairs_set_shapes(kind, True, table)
+    return table, best
+
+
+def tune_single(kind, n_values, make_call, start=None, log=print):
+    """For each size n (largest first) pick the (K, U) with the fastest
+    single-set call; make_call(n) returns a zero-argument callable."""
+    entries = []
+    for i, n in enumerate(sorted(n_values, reverse=True)):
+        call = make_call(n)
+        best = None
+        for k in ROWS:
+            for u in CHUNKS:
+                lo = (sorted(n_values, reverse=True)[i + 1] if i + 1 < len(n_values) else 0)
+                pairs_set_shapes(kind, False, entries + [(lo, k, u)])
+                ms = _time(call)
+                if best is None or ms < best[0]:
+                    best = (ms, k, u)
+        lo = sorted(n_values, reverse=True)[i + 1] if i + 1 < len(n_values) else 0
+        entries.append((lo, best[1], best[2]))
+        log(f"n={n}: K={best[1]} U={best[2]} {best[0]:.3f} ms")
+    pairs_set_shapes(kind, False, entries)
+    return entries
+
+
+def load_cache(path=None, apply=True):
+    """Read a cache and apply the entries that match this device."""
+    path = path or os.environ.get("PAIRS_TUNE_CACHE") or DEFAULT_CACHE
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        data = json.load(f)
+    if apply:
+        try:
+            a = arch()
+        except Exception:
+            return data
+        for key, entry in data.get("tables", {}).items():
+            d_arch, kind_name, mode = key.split("/")
+            if d_arch != a:
+                continue
+            kind = {v: k for k, v in KIND_NAMES.items()}[kind_name]
+            pairs_set_shapes(kind, mode == "batched", [tuple(e) for e in entry["table"]])
+    return data
+
+
+def save_cache(path, kind, batched, table, note, ms):
+    data = {"tables": {}}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    key = f"{arch()}/{KIND_NAMES[kind]}/{'batched' if batched else 'single'}"
+    data.setdefault("tables", {})[key] = {"table": [list(e) for e in table], "workload": note,
+                                          "ms": ms, "when": time.strftime("%Y-%m-%d")}
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+        f.write("\n")
+
+
+def main(argv=None):
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import workloads as w
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=["binned-int32", "particles-f32"],
+                    default="binned-int32")
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--rounds", type=int, default=1)
+    a = ap.parse_args(argv)
+    dev = torch.device("cuda", 0)
+    if a.workload == "binned-int32":
+        b = w.config4()
+        ins = tuple(torch.from_numpy(v).to(dev) for v in b.objs.arrays())
+        outs = (torch.empty(b.n_sets, dtype=torch.int64, device=dev),)
+        kind, note = KIND_COUNT_I32, "200000 binned int32 sets, lognormal(4,1.2) sizes, seed 5"
+    else:
+        b = w.config5()
+        ins = tuple(torch.from_numpy(v).to(dev) for v in b.objs.arrays())
+        outs = (torch.empty(b.n_sets, dtype=torch.float64, device=dev),
+                torch.empty(b.n_sets, dtype=torch.int64, device=dev))
+        kind, note = KIND_ENERGY_F32, "50000 float32 sets, lognormal(5,1) sizes, seed 6, r=0.01"
+    table, ms = tune_batched(kind, b.offsets, ins, outs, rounds=a.rounds,
+                             log=lambda *m: print(*m, flush=True))
+    save_cache(a.out, kind, True, table, note, ms)
+    print(json.dumps({"kind": KIND_NAMES[kind], "table": table, "ms": ms}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

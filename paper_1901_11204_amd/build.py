@@ -12,6 +12,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpairs.so")
 SOURCES = [os.path.join(CSRC, "pairs.hip")]
+PROBE_LIB = os.path.join(PKG, "libvaluprobe.so")
+PROBE_SOURCES = [os.path.join(CSRC, "valu_probe.hip")]
 ARCH = "gfx950"
 
 
@@ -20,24 +22,30 @@ def hipcc() -> str:
     return p
 
 
-def build_cmd(out: str, extra=()):
+def build_cmd(out: str, extra=(), sources=None):
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
             # packed FP32 instructions are kept out of every kernel
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             # hardware float atomics; IEEE semantics without contraction
             "-munsafe-fp-atomics", "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero",
-            "-I", INCLUDE, "-I", CSRC, *extra, "-o", out, *SOURCES]
+            "-I", INCLUDE, "-I", CSRC, *extra, "-o", out, *(sources or SOURCES)]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = build_cmd(tmp)
+def _compile(lib, sources, verbose):
+    tmp = lib + ".tmp"
+    cmd = build_cmd(tmp, sources=sources)
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libpairs.so and the VALU issue-rate probe library."""
+    _compile(LIB, SOURCES, verbose)
+    _compile(PROBE_LIB, PROBE_SOURCES, verbose)
     return LIB
 
 

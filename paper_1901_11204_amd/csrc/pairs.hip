@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -62,18 +63,47 @@ struct ClassTable {
     }
 };
 
-ClassTable default_classes() {
+ClassTable make_table(int count, const int *lo, const int *K, const int *U) {
     ClassTable t;
-    t.count = 4;
-    const int lo[4] = {4096, 1024, 256, 0};
-    const int K[4] = {8, 4, 2, 1};
-    const int U[4] = {2048, 1024, 512, 256};
-    for (int c = 0; c < 4; ++c) {
-        t.lo[c] = lo[c];
-        t.K[c] = K[c];
-        t.U[c] = U[c];
+    t.count = count;
+    for (int c = 0; c < kMaxClasses; ++c) {
+        t.lo[c] = c < count ? lo[c] : 0;
+        t.K[c] = c < count ? K[c] : 1;
+        t.U[c] = c < count ? U[c] : 64;
     }
     return t;
+}
+
+// Default tile shapes by kind (index kind - 1) for single sets and batches.
+ClassTable default_table(int kind, bool batched) {
+    (void)kind;
+    if (batched) {
+        const int lo[4] = {4096, 1024, 256, 0}, K[4] = {8, 4, 2, 1},
+                  U[4] = {2048, 1024, 512, 256};
+        return make_table(4, lo, K, U);
+    }
+    const int lo[3] = {65536, 8192, 0}, K[3] = {8, 4, 1}, U[3] = {8192, 1024, 256};
+    return make_table(3, lo, K, U);
+}
+
+std::mutex g_shape_mutex;
+ClassTable g_shapes[3][2];
+bool g_shapes_set[3][2];
+
+ClassTable shapes(int kind, bool batched) {
+    std::lock_guard<std::mutex> lock(g_shape_mutex);
+    return g_shapes_set[kind - 1][batched] ? g_shapes[kind - 1][batched]
+                                           : default_table(kind, batched);
+}
+
+bool valid_table(const ClassTable &t) {
+    if (t.count < 1 || t.count > kMaxClasses) return false;
+    for (int c = 0; c < t.count; ++c) {
+        if (t.K[c] != 1 && t.K[c] != 2 && t.K[c] != 4 && t.K[c] != 8) return false;
+        if (t.U[c] < 64 || t.U[c] % 64 != 0 || t.U[c] > (1 << 24)) return false;
+        if (t.lo[c] < 0 || (c > 0 && t.lo[c] >= t.lo[c - 1])) return false;
+    }
+    return true;
 }
 
 // Set s of a CSR batch, clipped to [0, n_total) so that malformed offsets can
@@ -194,17 +224,18 @@ __global__ __launch_bounds__(kBlock) void k_energy(const float *__restrict__ x,
 
 // ---------------------------------------------------------- batched kernels --
 
-// Task source of a plan: a host-built table of (set, local task index).
-struct TableSource {
-    const int2 *tasks;
-    int64_t ntasks;
-    __device__ int64_t total() const { return ntasks; }
-    __device__ void decode(int64_t t, int64_t *set, int *local) const {
-        int2 e = tasks[t];
-        *set = e.x;
-        *local = e.y;
-    }
+// One wave task of a plan, resolved on the host: set s (objects
+// [base, base + n)), rows [ra, ra + 64K), virtual partners [u0, u1).
+struct TaskDesc {
+    int64_t base;
+    int32_t set;
+    int32_t n;
+    int32_t ra;
+    int32_t u0;
+    int32_t u1;
+    int32_t K;
 };
+static_assert(sizeof(TaskDesc) == 32, "one 32-byte scalar load per task");
 
 // Task source of an unplanned call: per-class exclusive prefix sums of the
 // per-set task counts (coff[c][s], s = 0..n_sets) and the class bases.
@@ -330,8 +361,52 @@ __device__ __forceinline__ void batched_task(const BatchIO &io, int64_t base, co
     }
 }
 
-template <int KindV, typename Source>
-__global__ __launch_bounds__(kBlock) void k_batched(BatchIO io, Source src, ClassTable ct) {
+// Runs one task with the compiled shape K (only shapes up to KMAX are compiled
+// into a kernel, which keeps its register count, and so its occupancy, to
+// what the largest shape it serves needs).
+template <int KindV, int KMAX>
+__device__ __forceinline__ void run_task(const BatchIO &io, int64_t base, const Band &band,
+                                         int ra, int u0, int u1, int64_t set, int K, void *win) {
+    if (KMAX >= 8 && K == 8)
+        batched_task<(KMAX >= 8 ? 8 : 1), KindV>(io, base, band, ra, u0, u1, set, win);
+    else if (KMAX >= 4 && K == 4)
+        batched_task<(KMAX >= 4 ? 4 : 1), KindV>(io, base, band, ra, u0, u1, set, win);
+    else if (KMAX >= 2 && K == 2)
+        batched_task<(KMAX >= 2 ? 2 : 1), KindV>(io, base, band, ra, u0, u1, set, win);
+    else if (K == 1)
+        batched_task<1, KindV>(io, base, band, ra, u0, u1, set, win);
+}
+
+// Plans: wave w runs the tasks descs[wave_start[w] .. wave_start[w+1]), a list
+// balanced across the waves on the host; the next descriptor is fetched while
+// the current task runs.
+template <int KindV, int KMAX>
+__global__ __launch_bounds__(kBlock) void k_batched_plan(BatchIO io,
+                                                         const TaskDesc *__restrict__ descs,
+                                                         const int32_t *__restrict__ wave_start,
+                                                         int64_t n_waves) {
+    __shared__ __align__(16) unsigned char lds[kWavesPerBlock * kLdsBytes];
+    const int wave = wave_id();
+    void *win = lds + wave * kLdsBytes;
+    const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    if (w >= n_waves) return;
+    int i = wave_start[w];
+    const int e = wave_start[w + 1];
+    if (i >= e) return;
+    TaskDesc next = descs[i];
+    for (; i < e; ++i) {
+        const TaskDesc d = next;
+        if (i + 1 < e) next = descs[i + 1];
+        const Band band = Band::of(d.n);
+        run_task<KindV, KMAX>(io, d.base, band, d.ra, d.u0, d.u1, d.set, d.K, win);
+    }
+}
+
+// Unplanned calls: tasks decoded from the device-built prefix sums, taken by
+// the waves with a grid stride.
+template <int KindV, int KMAX>
+__global__ __launch_bounds__(kBlock) void k_batched_scan(BatchIO io, ScanSource src,
+                                                         ClassTable ct) {
     __shared__ __align__(16) unsigned char lds[kWavesPerBlock * kLdsBytes];
     const int wave = wave_id();
     void *win = lds + wave * kLdsBytes;
@@ -352,12 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_batched(BatchIO io, Source src, Clas
         int ra, u0, u1;
         task_range(band, til, local / til.nchunks, local % til.nchunks, &ra, &u0, &u1);
         if (u0 >= u1) continue;
-        switch (ct.K[c]) {
-            case 8: batched_task<8, KindV>(io, base, band, ra, u0, u1, set, win); break;
-            case 4: batched_task<4, KindV>(io, base, band, ra, u0, u1, set, win); break;
-            case 2: batched_task<2, KindV>(io, base, band, ra, u0, u1, set, win); break;
-            default: batched_task<1, KindV>(io, base, band, ra, u0, u1, set, win); break;
-        }
+        run_task<KindV, KMAX>(io, base, band, ra, u0, u1, set, ct.K[c], win);
     }
 }
 
@@ -535,10 +605,10 @@ struct Shape {
     int U;
 };
 
-Shape single_set_shape(int64_t n) {
-    if (n <= 8192) return {1, 256};
-    if (n <= 65536) return {4, 1024};
-    return {8, 8192};
+Shape single_set_shape(int kind, int64_t n) {
+    const ClassTable t = shapes(kind, false);
+    const int c = t.class_of((int)n);
+    return {t.K[c], t.U[c]};
 }
 
 int64_t single_blocks(int n, int K, int U) {
@@ -571,42 +641,71 @@ void launch_energy(const float *x, const float *y, const float *z, int n, int U,
         k_energy<K, false><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
 }
 
-// Resident blocks of one persistent batched kernel on the current device.
-template <int KindV, typename Source>
-int64_t persistent_blocks(const DeviceState *st) {
+int max_rows(const ClassTable &ct) {
+    int m = 1;
+    for (int c = 0; c < ct.count; ++c) m = std::max(m, ct.K[c]);
+    return m;
+}
+
+// Resident blocks of a kernel on the current device.
+template <typename Kern>
+int64_t resident_blocks(const DeviceState *st, Kern kern) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<KindV, Source>, kBlock,
-                                                     0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess ||
         per_cu <= 0)
         per_cu = 1;
     return (int64_t)per_cu * (st->n_cu > 0 ? st->n_cu : 1);
 }
 
-template <typename Source>
-pairs_status_t launch_batched(int kind, const BatchIO &io, const Source &src,
-                              const ClassTable &ct, int64_t max_tasks, hipStream_t s) {
+// Calls f with the plan kernel of (kind, kmax).
+template <typename F>
+void with_plan_kernel(int kind, int kmax, F f) {
+#define PAIRS_PLAN_K(KV, KM) f(k_batched_plan<KV, KM>)
+    switch (kind * 16 + kmax) {
+        case kCountI32 * 16 + 1: PAIRS_PLAN_K(kCountI32, 1); break;
+        case kCountI32 * 16 + 2: PAIRS_PLAN_K(kCountI32, 2); break;
+        case kCountI32 * 16 + 4: PAIRS_PLAN_K(kCountI32, 4); break;
+        case kCountI32 * 16 + 8: PAIRS_PLAN_K(kCountI32, 8); break;
+        case kCountF32 * 16 + 1: PAIRS_PLAN_K(kCountF32, 1); break;
+        case kCountF32 * 16 + 2: PAIRS_PLAN_K(kCountF32, 2); break;
+        case kCountF32 * 16 + 4: PAIRS_PLAN_K(kCountF32, 4); break;
+        case kCountF32 * 16 + 8: PAIRS_PLAN_K(kCountF32, 8); break;
+        case kEnergyF32 * 16 + 1: PAIRS_PLAN_K(kEnergyF32, 1); break;
+        case kEnergyF32 * 16 + 2: PAIRS_PLAN_K(kEnergyF32, 2); break;
+        case kEnergyF32 * 16 + 4: PAIRS_PLAN_K(kEnergyF32, 4); break;
+        default: PAIRS_PLAN_K(kEnergyF32, 8); break;
+    }
+#undef PAIRS_PLAN_K
+}
+
+template <typename F>
+void with_scan_kernel(int kind, int kmax, F f) {
+#define PAIRS_SCAN_K(KV, KM) f(k_batched_scan<KV, KM>)
+    switch (kind * 16 + kmax) {
+        case kCountI32 * 16 + 1: PAIRS_SCAN_K(kCountI32, 1); break;
+        case kCountI32 * 16 + 2: PAIRS_SCAN_K(kCountI32, 2); break;
+        case kCountI32 * 16 + 4: PAIRS_SCAN_K(kCountI32, 4); break;
+        case kCountI32 * 16 + 8: PAIRS_SCAN_K(kCountI32, 8); break;
+        case kCountF32 * 16 + 1: PAIRS_SCAN_K(kCountF32, 1); break;
+        case kCountF32 * 16 + 2: PAIRS_SCAN_K(kCountF32, 2); break;
+        case kCountF32 * 16 + 4: PAIRS_SCAN_K(kCountF32, 4); break;
+        case kCountF32 * 16 + 8: PAIRS_SCAN_K(kCountF32, 8); break;
+        case kEnergyF32 * 16 + 1: PAIRS_SCAN_K(kEnergyF32, 1); break;
+        case kEnergyF32 * 16 + 2: PAIRS_SCAN_K(kEnergyF32, 2); break;
+        case kEnergyF32 * 16 + 4: PAIRS_SCAN_K(kEnergyF32, 4); break;
+        default: PAIRS_SCAN_K(kEnergyF32, 8); break;
+    }
+#undef PAIRS_SCAN_K
+}
+
+pairs_status_t launch_scan(int kind, const BatchIO &io, const ScanSource &src,
+                           const ClassTable &ct, hipStream_t s) {
     DeviceState *st;
     PAIRS_TRY(device_state(&st));
-    int64_t blocks;
-    switch (kind) {
-        case kCountI32: blocks = persistent_blocks<kCountI32, Source>(st); break;
-        case kCountF32: blocks = persistent_blocks<kCountF32, Source>(st); break;
-        default: blocks = persistent_blocks<kEnergyF32, Source>(st); break;
-    }
-    if (max_tasks >= 0)
-        blocks = std::min(blocks, (max_tasks + kWavesPerBlock - 1) / kWavesPerBlock);
-    if (blocks <= 0) return PAIRS_OK;
-    switch (kind) {
-        case kCountI32:
-            k_batched<kCountI32, Source><<<(unsigned)blocks, kBlock, 0, s>>>(io, src, ct);
-            break;
-        case kCountF32:
-            k_batched<kCountF32, Source><<<(unsigned)blocks, kBlock, 0, s>>>(io, src, ct);
-            break;
-        default:
-            k_batched<kEnergyF32, Source><<<(unsigned)blocks, kBlock, 0, s>>>(io, src, ct);
-            break;
-    }
+    with_scan_kernel(kind, max_rows(ct), [&](auto kern) {
+        const int64_t blocks = resident_blocks(st, kern);
+        kern<<<(unsigned)blocks, kBlock, 0, s>>>(io, src, ct);
+    });
     PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;
 }
@@ -625,11 +724,14 @@ pairs_status_t batched_common(int kind, const BatchIO &io, int64_t n_sets, void 
     int64_t *bases = (int64_t *)p;
     p += align256(sizeof(int64_t) * (kMaxClasses + 1));
     int64_t *coff = (int64_t *)p;
-    const ClassTable ct = default_classes();
+    const ClassTable ct = shapes(kind == kCountI32   ? PAIRS_KIND_COUNT_I32
+                                 : kind == kCountF32 ? PAIRS_KIND_COUNT_F32
+                                                     : PAIRS_KIND_ENERGY_F32,
+                                 true);
     k_batch_schedule<<<1, kSchedThreads, 0, s>>>(io.off, n_sets, io.n_total, ct, coff, bases);
     PAIRS_HIP_CHECK(hipGetLastError());
     ScanSource src{bases, coff, n_sets, ct.count};
-    return launch_batched(kind, io, src, ct, -1, s);
+    return launch_scan(kind, io, src, ct, s);
 }
 
 pairs_status_t batched_args(const void *x, const void *y, const void *z,
@@ -653,8 +755,11 @@ struct pairs_plan_s {
     int64_t n_total;
     int64_t ntasks;
     ClassTable classes;
+    int kmax;          // largest rows-per-lane of the table
+    int64_t n_waves;   // waves the task lists were balanced over
     int64_t *d_offsets;
-    int2 *d_tasks;
+    TaskDesc *d_descs;      // wave-major task descriptors
+    int32_t *d_wave_start;  // [n_waves + 1]
 };
 
 struct pairs_graph_s {
@@ -679,9 +784,10 @@ pairs_status_t pairs_count_i32(const int32_t *x, const int32_t *y, const int32_t
     if (flags & PAIRS_FLAG_VALIDATE) PAIRS_TRY(validate_i32(x, y, z, r, n, s));
     PAIRS_TRY(fill_u64(d_count, 1, 0, s));
     if (n < 2) return PAIRS_OK;
-    Shape sh = single_set_shape(n);
+    Shape sh = single_set_shape(PAIRS_KIND_COUNT_I32, n);
     switch (sh.K) {
         case 1: launch_count_i32<1>(x, y, z, r, (int)n, sh.U, d_count, s); break;
+        case 2: launch_count_i32<2>(x, y, z, r, (int)n, sh.U, d_count, s); break;
         case 4: launch_count_i32<4>(x, y, z, r, (int)n, sh.U, d_count, s); break;
         default: launch_count_i32<8>(x, y, z, r, (int)n, sh.U, d_count, s); break;
     }
@@ -701,9 +807,10 @@ pairs_status_t pairs_count_f32(const float *x, const float *y, const float *z, c
     if (flags & PAIRS_FLAG_VALIDATE) PAIRS_TRY(validate_f32(x, y, z, r, n, s));
     PAIRS_TRY(fill_u64(d_count, 1, 0, s));
     if (n < 2) return PAIRS_OK;
-    Shape sh = single_set_shape(n);
+    Shape sh = single_set_shape(PAIRS_KIND_COUNT_F32, n);
     switch (sh.K) {
         case 1: launch_count_f32<1>(x, y, z, r, (int)n, sh.U, d_count, s); break;
+        case 2: launch_count_f32<2>(x, y, z, r, (int)n, sh.U, d_count, s); break;
         case 4: launch_count_f32<4>(x, y, z, r, (int)n, sh.U, d_count, s); break;
         default: launch_count_f32<8>(x, y, z, r, (int)n, sh.U, d_count, s); break;
     }
@@ -725,9 +832,10 @@ pairs_status_t pairs_energy_f32(const float *x, const float *y, const float *z, 
     PAIRS_TRY(fill_f64(d_total, 1, 0.0, s));
     PAIRS_TRY(fill_f64(d_energy, n, 0.0, s));
     if (n < 2) return PAIRS_OK;
-    Shape sh = single_set_shape(n);
+    Shape sh = single_set_shape(PAIRS_KIND_ENERGY_F32, n);
     switch (sh.K) {
         case 1: launch_energy<1>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
+        case 2: launch_energy<2>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
         case 4: launch_energy<4>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
         default: launch_energy<8>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
     }
@@ -820,35 +928,94 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
     }
     int dev;
     PAIRS_TRY(current_device(&dev));
-    const ClassTable ct = default_classes();
-    // tasks of class 0 (largest sets) first, then class 1, ...
-    std::vector<int64_t> per_class(ct.count, 0);
+    DeviceState *st;
+    PAIRS_TRY(device_state(&st));
+    const ClassTable ct = shapes(kind, true);
+    const int kmax = max_rows(ct);
+    const int kk = kind == PAIRS_KIND_COUNT_I32 ? kCountI32
+                   : kind == PAIRS_KIND_COUNT_F32 ? kCountF32 : kEnergyF32;
+    int64_t n_waves = 0;
+    with_plan_kernel(kk, kmax, [&](auto kern) { n_waves = resident_blocks(st, kern) * kWavesPerBlock; });
+
+    // every task with its cost in VALU issue slots (per 64-partner group: 5
+    // instructions per row slice in a row block's core, 7 at the band edges)
+    std::vector<TaskDesc> tasks;
+    std::vector<int64_t> cost;
     for (int64_t s = 0; s < n_sets; ++s) {
-        int n = (int)(h_offsets[s + 1] - h_offsets[s]);
+        const int n = (int)(h_offsets[s + 1] - h_offsets[s]);
         if (n < 2) continue;
-        int c = ct.class_of(n);
-        per_class[c] += ct.tasks(n, c);
+        const int c = ct.class_of(n);
+        const Band band = Band::of(n);
+        const Tiling til = Tiling::of(band, ct.K[c], ct.U[c]);
+        for (int b = 0; b < til.nblocks; ++b)
+            for (int ch = 0; ch < til.nchunks; ++ch) {
+                int ra, u0, u1;
+                task_range(band, til, b, ch, &ra, &u0, &u1);
+                if (u0 >= u1) continue;
+                TaskDesc d;
+                d.base = h_offsets[s];
+                d.set = (int32_t)s;
+                d.n = n;
+                d.ra = ra;
+                d.u0 = u0;
+                d.u1 = u1;
+                d.K = ct.K[c];
+                const int rlast = std::min(ra + 64 * d.K, n) - 1;
+                const int core_lo = rlast + 1, core_hi = ra + band.steps(ra);
+                int64_t w = 600;
+                for (int g0 = u0; g0 < u1; g0 += 64) {
+                    const int gn = std::min(64, u1 - g0);
+                    const bool full = g0 >= core_lo && g0 + gn - 1 <= core_hi;
+                    w += 40 + (full ? 64 * 5 : gn * 7) * (int64_t)d.K;
+                }
+                try {
+                    tasks.push_back(d);
+                    cost.push_back(w);
+                } catch (const std::bad_alloc &) {
+                    return PAIRS_ERR_NO_MEMORY;
+                }
+            }
     }
-    int64_t ntasks = 0;
-    std::vector<int64_t> cursor(ct.count, 0);
-    for (int c = 0; c < ct.count; ++c) {
-        cursor[c] = ntasks;
-        ntasks += per_class[c];
-    }
+    const int64_t ntasks = (int64_t)tasks.size();
     if (ntasks >= INT32_MAX) return PAIRS_ERR_INVALID_ARG;
-    std::vector<int2> table;
-    try {
-        table.resize((size_t)ntasks);
-    } catch (const std::bad_alloc &) {
-        return PAIRS_ERR_NO_MEMORY;
+    if (n_waves < 1) n_waves = 1;
+    n_waves = std::min<int64_t>(n_waves, std::max<int64_t>(ntasks, 1));
+
+    // longest processing time first: each task, largest first, goes to the
+    // wave with the least work so far
+    std::vector<int32_t> order((size_t)ntasks);
+    for (int64_t k = 0; k < ntasks; ++k) order[(size_t)k] = (int32_t)k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return cost[(size_t)a] > cost[(size_t)b]; });
+    std::vector<int32_t> owner((size_t)ntasks);
+    std::vector<int32_t> per_wave((size_t)n_waves, 0);
+    {
+        typedef std::pair<int64_t, int32_t> Load;  // (work, wave)
+        std::vector<Load> heap;
+        heap.reserve((size_t)n_waves);
+        for (int64_t w = 0; w < n_waves; ++w) heap.push_back(Load(0, (int32_t)w));
+        auto cmp = [](const Load &a, const Load &b) { return a > b; };  // min-heap
+        for (int64_t k = 0; k < ntasks; ++k) {
+            std::pop_heap(heap.begin(), heap.end(), cmp);
+            Load &l = heap.back();
+            const int32_t t = order[(size_t)k];
+            owner[(size_t)t] = l.second;
+            per_wave[(size_t)l.second]++;
+            l.first += cost[(size_t)t];
+            std::push_heap(heap.begin(), heap.end(), cmp);
+        }
     }
-    for (int64_t s = 0; s < n_sets; ++s) {
-        int n = (int)(h_offsets[s + 1] - h_offsets[s]);
-        if (n < 2) continue;
-        int c = ct.class_of(n);
-        int64_t m = ct.tasks(n, c);
-        for (int64_t l = 0; l < m; ++l) table[(size_t)cursor[c]++] = make_int2((int)s, (int)l);
+    std::vector<int32_t> wave_start((size_t)n_waves + 1, 0);
+    for (int64_t w = 0; w < n_waves; ++w) wave_start[(size_t)w + 1] = wave_start[(size_t)w] + per_wave[(size_t)w];
+    std::vector<TaskDesc> laid((size_t)ntasks);
+    {
+        std::vector<int32_t> cur(wave_start.begin(), wave_start.end() - 1);
+        for (int64_t k = 0; k < ntasks; ++k) {  // largest first within each wave
+            const int32_t t = order[(size_t)k];
+            laid[(size_t)cur[(size_t)owner[(size_t)t]]++] = tasks[(size_t)t];
+        }
     }
+
     pairs_plan_s *p = new (std::nothrow) pairs_plan_s();
     if (!p) return PAIRS_ERR_NO_MEMORY;
     p->kind = kind;
@@ -857,19 +1024,29 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
     p->n_total = h_offsets[n_sets];
     p->ntasks = ntasks;
     p->classes = ct;
+    p->kmax = kmax;
+    p->n_waves = n_waves;
     p->d_offsets = nullptr;
-    p->d_tasks = nullptr;
+    p->d_descs = nullptr;
+    p->d_wave_start = nullptr;
     hipError_t e = hipMalloc(&p->d_offsets, sizeof(int64_t) * (size_t)(n_sets + 1));
-    if (e == hipSuccess && ntasks > 0) e = hipMalloc(&p->d_tasks, sizeof(int2) * (size_t)ntasks);
+    if (e == hipSuccess)
+        e = hipMalloc(&p->d_wave_start, sizeof(int32_t) * (size_t)(n_waves + 1));
+    if (e == hipSuccess && ntasks > 0)
+        e = hipMalloc(&p->d_descs, sizeof(TaskDesc) * (size_t)ntasks);
     if (e == hipSuccess)
         e = hipMemcpy(p->d_offsets, h_offsets, sizeof(int64_t) * (size_t)(n_sets + 1),
                       hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_wave_start, wave_start.data(), sizeof(int32_t) * (size_t)(n_waves + 1),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess && ntasks > 0)
-        e = hipMemcpy(p->d_tasks, table.data(), sizeof(int2) * (size_t)ntasks,
+        e = hipMemcpy(p->d_descs, laid.data(), sizeof(TaskDesc) * (size_t)ntasks,
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         if (p->d_offsets) hipFree(p->d_offsets);
-        if (p->d_tasks) hipFree(p->d_tasks);
+        if (p->d_wave_start) hipFree(p->d_wave_start);
+        if (p->d_descs) hipFree(p->d_descs);
         delete p;
         g_last_hip_error = e;
         return e == hipErrorOutOfMemory ? PAIRS_ERR_NO_MEMORY : PAIRS_ERR_HIP;
@@ -918,11 +1095,16 @@ pairs_status_t pairs_plan_execute(pairs_plan_t plan, const void *const *in, void
         PAIRS_TRY(fill_u64(io.counts, plan->n_sets, 0, s));
     }
     if (plan->ntasks == 0) return PAIRS_OK;
-    TableSource src{plan->d_tasks, plan->ntasks};
-    int kind = plan->kind == PAIRS_KIND_COUNT_I32   ? kCountI32
-               : plan->kind == PAIRS_KIND_COUNT_F32 ? kCountF32
-                                                    : kEnergyF32;
-    return launch_batched(kind, io, src, plan->classes, plan->ntasks, s);
+    const int kind = plan->kind == PAIRS_KIND_COUNT_I32   ? kCountI32
+                     : plan->kind == PAIRS_KIND_COUNT_F32 ? kCountF32
+                                                          : kEnergyF32;
+    const int64_t blocks = (plan->n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    with_plan_kernel(kind, plan->kmax, [&](auto kern) {
+        kern<<<(unsigned)blocks, kBlock, 0, s>>>(io, plan->d_descs, plan->d_wave_start,
+                                                  plan->n_waves);
+    });
+    PAIRS_HIP_CHECK(hipGetLastError());
+    return PAIRS_OK;
 }
 
 pairs_status_t pairs_plan_destroy(pairs_plan_t plan) {
@@ -931,7 +1113,8 @@ pairs_status_t pairs_plan_destroy(pairs_plan_t plan) {
     hipGetDevice(&cur);
     hipSetDevice(plan->device);
     if (plan->d_offsets) hipFree(plan->d_offsets);
-    if (plan->d_tasks) hipFree(plan->d_tasks);
+    if (plan->d_descs) hipFree(plan->d_descs);
+    if (plan->d_wave_start) hipFree(plan->d_wave_start);
     hipSetDevice(cur);
     delete plan;
     return PAIRS_OK;
@@ -1021,6 +1204,34 @@ pairs_status_t pairs_graph_destroy(pairs_graph_t graph) {
     hipGraphExecDestroy(graph->exec);
     hipGraphDestroy(graph->graph);
     delete graph;
+    return PAIRS_OK;
+}
+
+pairs_status_t pairs_get_shapes(int kind, int batched, pairs_shape_table_t *out) {
+    if (!out || kind < PAIRS_KIND_COUNT_I32 || kind > PAIRS_KIND_ENERGY_F32)
+        return PAIRS_ERR_INVALID_ARG;
+    const ClassTable t = shapes(kind, batched != 0);
+    out->count = t.count;
+    for (int c = 0; c < 4; ++c) {
+        out->min_n[c] = t.lo[c];
+        out->rows_per_lane[c] = t.K[c];
+        out->chunk[c] = t.U[c];
+    }
+    return PAIRS_OK;
+}
+
+pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t *table) {
+    if (kind < PAIRS_KIND_COUNT_I32 || kind > PAIRS_KIND_ENERGY_F32) return PAIRS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_shape_mutex);
+    if (!table) {
+        g_shapes_set[kind - 1][batched != 0] = false;
+        return PAIRS_OK;
+    }
+    if (table->count < 1 || table->count > kMaxClasses) return PAIRS_ERR_INVALID_ARG;
+    ClassTable t = make_table(table->count, table->min_n, table->rows_per_lane, table->chunk);
+    if (!valid_table(t)) return PAIRS_ERR_INVALID_ARG;
+    g_shapes[kind - 1][batched != 0] = t;
+    g_shapes_set[kind - 1][batched != 0] = true;
     return PAIRS_OK;
 }
 

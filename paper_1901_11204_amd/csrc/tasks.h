@@ -4,12 +4,11 @@
 // balanced assignment of one set (band.h) held in registers, K rows per lane
 // in lane-major order (row ra + 64k + lane), swept against a chunk [u0, u1)
 // of virtual partners that are staged 64 at a time into a wave-private LDS
-// window and read back as wave-uniform broadcasts.  For a fixed u the rows
-// that own the pair (row, u mod n) are the contiguous range
-// [first_row(u), u-1] (band.h), so inside a row block's core every lane is
-// valid, and at the two band edges a lane-range mask selects them.  Padding
-// rows and padding partners carry values (infinities) for which the predicate
-// is false or the potential exactly zero, so they need no mask.
+// window and read back as wave-uniform broadcasts.  Row i evaluates the
+// virtual partner u iff i < u <= i + steps(i) (band.h).  Inside a row block's
+// core that holds for every lane; at the two band edges each lane tests it.
+// Padding rows and padding partners carry values (infinities) for which the
+// predicate is false or the potential exactly zero.
 //
 // Objects of the set are x[base + k], k in [0, n).
 #pragma once
@@ -48,6 +47,11 @@ __device__ __forceinline__ void gram_features(int32_t xi, int32_t yi, int32_t zi
 // LDS window of one wave: 5 arrays of 64 doubles.
 constexpr int kCountI32Lds = 5 * kWave;
 
+// Row i evaluates the virtual partner u iff i < u <= i + steps(i).
+__device__ __forceinline__ bool owns(int u, int i, int steps) {
+    return (unsigned)(u - 1 - i) < (unsigned)steps;
+}
+
 __device__ __forceinline__ int64_t partner_index(int64_t base, const Band &band, int u) {
     return base + (u >= band.n ? u - band.n : u);
 }
@@ -59,17 +63,21 @@ __device__ uint32_t count_i32_task(const int32_t *__restrict__ px, const int32_t
                                    double *__restrict__ win) {
     const int lane = lane_id();
     double xr[K], yr[K], zr[K], rr[K], nh[K];
+    int row[K], nsteps[K];  // row index and its step count (0 for padding rows)
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         int i = ra + kWave * k + lane;
+        row[k] = i;
         if (i < band.n) {
             int64_t g = base + i;
             double h;
             gram_features(px[g], py[g], pz[g], pr[g], xr[k], yr[k], zr[k], rr[k], h);
             nh[k] = -h;
+            nsteps[k] = band.steps(i);
         } else {
             xr[k] = yr[k] = zr[k] = rr[k] = 0.0;
             nh[k] = -INFINITY;  // never hits
+            nsteps[k] = 0;
         }
     }
     const int rlast = min(ra + kWave * K, band.n) - 1;
@@ -122,19 +130,15 @@ __device__ uint32_t count_i32_task(const int32_t *__restrict__ px, const int32_t
         } else {
             for (int t = 0; t < gn; ++t) {
                 const int u = g0 + t;
-                const int first = max(band.first_row(u), ra);
                 const double jx = win[t], jy = win[kWave + t], jz = win[2 * kWave + t],
                              jr = win[3 * kWave + t], jh = win[4 * kWave + t];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const int b = ra + kWave * k;
-                    const uint64_t m = lane_range(first - b, u - 1 - b);
-                    if (m == 0) continue;
                     double v = __builtin_fma(xr[k], jx, nh[k]);
                     v = __builtin_fma(yr[k], jy, v);
                     v = __builtin_fma(zr[k], jz, v);
                     v = __builtin_fma(rr[k], jr, v);
-                    cnt += count_bits_masked(v >= jh, m);
+                    cnt += count_bits(v >= jh && owns(u, row[k], nsteps[k]));
                 }
             }
         }
@@ -170,15 +174,19 @@ __device__ uint32_t count_f32_task(const float *__restrict__ px, const float *__
                                    float *__restrict__ win) {
     const int lane = lane_id();
     float xr[K], yr[K], zr[K], rr[K];
+    int row[K], nsteps[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         int i = ra + kWave * k + lane;
+        row[k] = i;
         if (i < band.n) {
             int64_t g = base + i;
             xr[k] = px[g]; yr[k] = py[g]; zr[k] = pz[g]; rr[k] = pr[g];
+            nsteps[k] = band.steps(i);
         } else {
             xr[k] = INFINITY;  // distance infinite: never hits
             yr[k] = zr[k] = rr[k] = 0.0f;
+            nsteps[k] = 0;
         }
     }
     const int rlast = min(ra + kWave * K, band.n) - 1;
@@ -219,16 +227,12 @@ __device__ uint32_t count_f32_task(const float *__restrict__ px, const float *__
         } else {
             for (int t = 0; t < gn; ++t) {
                 const int u = g0 + t;
-                const int first = max(band.first_row(u), ra);
                 const float jx = win[t], jy = win[kWave + t], jz = win[2 * kWave + t],
                             jr = win[3 * kWave + t];
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int b = ra + kWave * k;
-                    const uint64_t m = lane_range(first - b, u - 1 - b);
-                    if (m == 0) continue;
-                    cnt += count_bits_masked(hit_f32(xr[k], yr[k], zr[k], rr[k], jx, jy, jz, jr), m);
-                }
+                for (int k = 0; k < K; ++k)
+                    cnt += count_bits(hit_f32(xr[k], yr[k], zr[k], rr[k], jx, jy, jz, jr) &&
+                                      owns(u, row[k], nsteps[k]));
             }
         }
         wave_sync();
@@ -257,9 +261,10 @@ struct EnergyResult {
 template <int K, bool PerObject, bool WithCount, bool Masked>
 __device__ __forceinline__ void energy_group(const float (&xr)[K], const float (&yr)[K],
                                              const float (&zr)[K], const float (&rr)[K],
+                                             const int (&row)[K], const int (&nsteps)[K],
                                              float (&part)[K], double (&acc)[K], uint32_t &cnt,
-                                             float *__restrict__ win, const Band band, int ra,
-                                             int g0, int gn, float eps2) {
+                                             float *__restrict__ win, int g0, int gn,
+                                             float eps2) {
     const int lane = lane_id();
     for (int t0 = 0; t0 < gn; t0 += kFoldEvery) {
 #pragma unroll 2
@@ -267,23 +272,14 @@ __device__ __forceinline__ void energy_group(const float (&xr)[K], const float (
             const float jx = win[t], jy = win[kWave + t], jz = win[2 * kWave + t];
             float jr = 0.0f;
             if (WithCount) jr = win[3 * kWave + t];
-            int first = 0, u = 0;
-            if (Masked) {
-                u = g0 + t;
-                first = max(band.first_row(u), ra);
-            }
+            const int u = g0 + t;
             float js = 0.0f;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float dx = xr[k] - jx, dy = yr[k] - jy, dz = zr[k] - jz;
                 float e;
                 bool valid = true;
-                if (Masked) {
-                    // row ra + 64k + lane takes part iff first <= row <= u - 1
-                    const int lo = first - (ra + kWave * k);
-                    const int len = u - 1 - first;
-                    valid = (unsigned)(lane - lo) <= (unsigned)len && len >= 0;
-                }
+                if (Masked) valid = owns(u, row[k], nsteps[k]);
                 if (WithCount) {
                     const float d2 = sq_dist_f32(dx, dy, dz);
                     const float R = __fadd_rn(rr[k], jr);
@@ -324,16 +320,20 @@ __device__ EnergyResult energy_task(const float *__restrict__ px, const float *_
     const int lane = lane_id();
     float xr[K], yr[K], zr[K], rr[K], part[K];
     double acc[K];
+    int row[K], nsteps[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         int i = ra + kWave * k + lane;
+        row[k] = i;
         if (i < band.n) {
             int64_t g = base + i;
             xr[k] = px[g]; yr[k] = py[g]; zr[k] = pz[g];
             rr[k] = WithCount ? pr[g] : 0.0f;
+            nsteps[k] = band.steps(i);
         } else {
             xr[k] = INFINITY;  // infinite distance: e is exactly 0, never hits
             yr[k] = zr[k] = rr[k] = 0.0f;
+            nsteps[k] = 0;
         }
         part[k] = 0.0f;
         acc[k] = 0.0;
@@ -367,11 +367,11 @@ __device__ EnergyResult energy_task(const float *__restrict__ px, const float *_
         wave_sync();
         const int gn = min(kWave, u1 - g0);
         if (g0 >= core_lo && g0 + gn - 1 <= core_hi)
-            energy_group<K, PerObject, WithCount, false>(xr, yr, zr, rr, part, acc, cnt, win, band,
-                                                         ra, g0, gn, eps2);
+            energy_group<K, PerObject, WithCount, false>(xr, yr, zr, rr, row, nsteps, part, acc,
+                                                         cnt, win, g0, gn, eps2);
         else
-            energy_group<K, PerObject, WithCount, true>(xr, yr, zr, rr, part, acc, cnt, win, band,
-                                                        ra, g0, gn, eps2);
+            energy_group<K, PerObject, WithCount, true>(xr, yr, zr, rr, row, nsteps, part, acc,
+                                                        cnt, win, g0, gn, eps2);
         if (PerObject) {
             wave_sync();
             if (lane < gn)

@@ -1,0 +1,140 @@
+// Issue-rate probe of the gfx950 vector instructions the pair kernels use.
+//
+// Each probe kernel runs kChains independent dependency chains of one
+// instruction pattern per lane, kIters times, on a grid that fills every CU.
+// The host times each kernel with HIP events; lane-operations per second
+// against 256 CUs x 64 lanes x clock gives the issue cost of the pattern.
+// Used to measure the per-pair cost of the predicates (not on the hot path).
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+namespace {
+
+constexpr int kChains = 8;
+constexpr int kIters = 4096;
+
+__global__ void p_fma_f64(double *out, double a, double b) {
+    double c[kChains];
+    for (int k = 0; k < kChains; ++k) c[k] = threadIdx.x * 1e-3 + k;
+    for (int it = 0; it < kIters; ++it)
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) c[k] = __builtin_fma(c[k], a, b);
+    double s = 0;
+    for (int k = 0; k < kChains; ++k) s += c[k];
+    if (s == 12345.0) out[threadIdx.x] = s;
+}
+
+__global__ void p_fma_f32(float *out, float a, float b) {
+    float c[kChains];
+    for (int k = 0; k < kChains; ++k) c[k] = threadIdx.x * 1e-3f + k;
+    for (int it = 0; it < kIters; ++it)
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) c[k] = __builtin_fmaf(c[k], a, b);
+    float s = 0;
+    for (int k = 0; k < kChains; ++k) s += c[k];
+    if (s == 12345.0f) out[threadIdx.x] = s;
+}
+
+// reciprocal square root alone
+__global__ void p_rsq_f32(float *out, float a) {
+    float c[2 * kChains];
+    for (int k = 0; k < 2 * kChains; ++k) c[k] = threadIdx.x * 1e-3f + k + a;
+    for (int it = 0; it < kIters / 2; ++it)
+#pragma unroll
+        for (int k = 0; k < 2 * kChains; ++k) c[k] = __builtin_amdgcn_rsqf(c[k]);
+    float s = 0;
+    for (int k = 0; k < 2 * kChains; ++k) s += c[k];
+    if (s == 12345.0f) out[threadIdx.x] = s;
+}
+
+// the energy pattern: 3 fma + 1 rsq per step (4 instructions)
+__global__ void p_fma3_rsq(float *out, float a, float b) {
+    float c[kChains];
+    for (int k = 0; k < kChains; ++k) c[k] = threadIdx.x * 1e-3f + k + 1.0f;
+    for (int it = 0; it < kIters / 4; ++it)
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) {
+            float d = __builtin_fmaf(c[k], a, b);
+            d = __builtin_fmaf(d, a, b);
+            d = __builtin_fmaf(d, a, b);
+            c[k] = __builtin_amdgcn_rsqf(d);
+        }
+    float s = 0;
+    for (int k = 0; k < kChains; ++k) s += c[k];
+    if (s == 12345.0f) out[threadIdx.x] = s;
+}
+
+// the count pattern: 4 fma_f64 + 1 cmp_f64, ballot + popcount into 32 bits
+__global__ void p_count_f64(unsigned *out, double a, double b, double h) {
+    double c[kChains];
+    uint32_t cnt = 0;
+    for (int k = 0; k < kChains; ++k) c[k] = threadIdx.x * 1e-3 + k;
+    for (int it = 0; it < kIters / 5; ++it)
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) {
+            double v = __builtin_fma(c[k], a, b);
+            v = __builtin_fma(v, a, b);
+            v = __builtin_fma(v, a, b);
+            c[k] = __builtin_fma(v, a, b);
+            cnt += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(c[k] >= h));
+        }
+    if (cnt == 12345u) out[threadIdx.x] = cnt;
+}
+
+__global__ void p_mad_u64_u32(unsigned long long *out, unsigned a) {
+    unsigned long long c[kChains];
+    for (int k = 0; k < kChains; ++k) c[k] = threadIdx.x + k;
+    for (int it = 0; it < kIters; ++it)
+#pragma unroll
+        for (int k = 0; k < kChains; ++k) c[k] = (unsigned long long)(unsigned)c[k] * a + c[k];
+    unsigned long long s = 0;
+    for (int k = 0; k < kChains; ++k) s += c[k];
+    if (s == 12345ull) out[threadIdx.x] = s;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Probe names in order; pattern instruction counts per chain step.
+const char *valu_probe_names = "fma_f64,fma_f32,rsq_f32,fma3_rsq_f32,count_f64,mad_u64_u32";
+
+// Runs probe `which` once (after one warm-up) on blocks x 256 threads and
+// returns its duration in milliseconds in *ms and the number of lane
+// instructions it issued in *lane_ops; returns a hipError_t.
+int valu_probe_run(int which, int blocks, double *ms, double *lane_ops) {
+    void *buf = nullptr;
+    hipError_t e = hipMalloc(&buf, 1 << 20);
+    if (e != hipSuccess) return (int)e;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    const double lanes = (double)blocks * 256;
+    double per_lane = 0;
+    for (int rep = 0; rep < 2; ++rep) {
+        hipEventRecord(e0);
+        switch (which) {
+            case 0: p_fma_f64<<<blocks, 256>>>((double *)buf, 0.999, 1e-3); per_lane = kIters * kChains; break;
+            case 1: p_fma_f32<<<blocks, 256>>>((float *)buf, 0.999f, 1e-3f); per_lane = kIters * kChains; break;
+            case 2: p_rsq_f32<<<blocks, 256>>>((float *)buf, 1.0f); per_lane = (kIters / 2) * 2 * kChains; break;
+            case 3: p_fma3_rsq<<<blocks, 256>>>((float *)buf, 0.999f, 1e-3f); per_lane = (kIters / 4) * kChains * 4; break;
+            case 4: p_count_f64<<<blocks, 256>>>((unsigned *)buf, 0.999, 1e-3, 3.0); per_lane = (kIters / 5) * kChains * 5; break;
+            case 5: p_mad_u64_u32<<<blocks, 256>>>((unsigned long long *)buf, 12345u); per_lane = kIters * kChains; break;
+            default: hipFree(buf); return (int)hipErrorInvalidValue;
+        }
+        hipEventRecord(e1);
+        hipEventSynchronize(e1);
+    }
+    float t = 0;
+    hipEventElapsedTime(&t, e0, e1);
+    *ms = t;
+    *lane_ops = lanes * per_lane;
+    e = hipGetLastError();
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(buf);
+    return (int)e;
+}
+
+}  // extern "C"
