@@ -28,12 +28,15 @@ VALU_LANES_PER_CU = 64
 SCLK_HZ = 2.4e9
 VALU_PEAK = N_CU * VALU_LANES_PER_CU * SCLK_HZ          # lane-operations per second
 # Algorithmic VALU work per pair test of each kernel (lane-operations):
-#   exact int32 count, Gram form: 4 fused multiply-adds + 1 compare
-#   float32 energy with per-object sums: 3 sub + 3 fma + 1 rsqrt + 2 adds
+#   exact int32 count, Gram form: 4 32x32->64-bit multiply-adds + 1 compare
+#   float32 energy with per-object sums: 3 sub + 3 fma + 2 adds; the
+#     reciprocal square root issues to the separate transcendental pipe and
+#     takes no VALU slot (total-only energy runs above the VALU bound that a
+#     slot for it would impose)
 #   float32 energy with the pinned collision count: 3 sub + 1 mul + 2 fma
 #     (pinned squared distance) + add, mul, compare (radius test) + add
-#     (softening) + rsqrt + add
-C_ALG = {"count_i32": 5, "energy_f32": 9, "energy_count_f32": 12}
+#     (softening) + add
+C_ALG = {"count_i32": 5, "energy_f32": 8, "energy_count_f32": 11}
 PLAIN_DEF_OPS = 12   # operations of the plain definition per pair (either kind)
 
 
@@ -163,6 +166,8 @@ def main():
                     help="only run device-to-device copies of MIB MiB (HBM counter scale)")
     ap.add_argument("--valu-probe", action="store_true",
                     help="only measure the VALU issue rate of the kernels' instruction patterns")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the batched lines (for profiling their kernels)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
@@ -192,6 +197,10 @@ def main():
                           "GB_per_s": 2 * nbytes / (float(np.mean(ms)) * 1e-3) / 1e9}), flush=True)
         return
 
+    if a.batched_only:
+        print(json.dumps({"batched": bench_batched(P, w, torch, np, dev, a.steps)}), flush=True)
+        return
+
     # headline workload
     n = 2 ** 20
     s = w.config2(n)
@@ -216,7 +225,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32 in, f64 exact predicate, u64 count",
+        "dtype": "int32 in, int64 exact predicate, u64 count",
         "data": "synthetic (seeded uniform spheres)",
         "config": {"workload": "single set, N=2^20 int32 spheres, centres in [0,2^24)^3, "
                                "radii in [1,2^14], seed 2; exact collision count",

@@ -27,6 +27,12 @@ __device__ __forceinline__ uint32_t count_bits(bool pred) {
     return (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(pred));
 }
 
+// Lanes where both a and b hold; the two ballots are combined with a scalar and.
+__device__ __forceinline__ uint32_t count_bits_both(bool a, bool b) {
+    return (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(a) &
+                                          __builtin_amdgcn_ballot_w64(b));
+}
+
 __device__ __forceinline__ uint32_t count_bits_masked(bool pred, uint64_t mask) {
     return (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(pred) & mask);
 }
@@ -60,6 +66,64 @@ __device__ __forceinline__ float wave_total_in_lane63(float v) {
     v = dpp_plus<kDppRowBcast15, 0xa, 0xf>(v);
     v = dpp_plus<kDppRowBcast31, 0xc, 0xf>(v);
     return v;
+}
+
+// DPP controls for the reduce-scatter below.
+constexpr int kDppRowRor8 = 0x128, kDppRowHalfMirror = 0x141;
+constexpr int kDppQuadSwap1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;  // quad_perm [2,3,0,1]
+
+template <int Ctrl>
+__device__ __forceinline__ float dpp_full(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), Ctrl, 0xf, 0xf, true));
+}
+
+// Sums of 16 per-lane values over the 64 lanes, scattered: on return, the
+// four lanes 4g..4g+3 all hold the total of v[partner_of_group(g)].
+// Levels: v_permlane32_swap folds lane halves (16 values -> 8 registers),
+// v_permlane16_swap folds rows (-> 4), a row rotate by 8 and a half-row
+// mirror fold within rows (-> 2, -> 1, selecting by lane bit), and two quad
+// permutes finish each group of four lanes.
+__device__ __forceinline__ float reduce_scatter16(const float (&v)[16]) {
+    const int lane = lane_id();
+    float r1[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * p]),
+                                                   __float_as_uint(v[2 * p + 1]), false, false);
+        r1[p] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+    }
+    float r2[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(r1[2 * q]),
+                                                   __float_as_uint(r1[2 * q + 1]), false, false);
+        r2[q] = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+    }
+    const bool hi8 = (lane & 8) != 0, hi4 = (lane & 4) != 0;
+    float r3[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const float e = r2[2 * h] + dpp_full<kDppRowRor8>(r2[2 * h]);
+        const float f = r2[2 * h + 1] + dpp_full<kDppRowRor8>(r2[2 * h + 1]);
+        r3[h] = hi8 ? f : e;
+    }
+    const float g0 = r3[0] + dpp_full<kDppRowHalfMirror>(r3[0]);
+    const float g1 = r3[1] + dpp_full<kDppRowHalfMirror>(r3[1]);
+    float r = hi4 ? g1 : g0;
+    r += dpp_full<kDppQuadSwap1>(r);
+    r += dpp_full<kDppQuadSwap2>(r);
+    return r;
+}
+
+// Which of the 16 values reduce_scatter16 leaves in the calling lane's group,
+// found by reducing the values k held by lane 0 only (exact in float32).
+__device__ __forceinline__ int reduce_scatter16_slot() {
+    float probe[16];
+    const bool first = lane_id() == 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) probe[k] = first ? (float)k : 0.0f;
+    return (int)reduce_scatter16(probe);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

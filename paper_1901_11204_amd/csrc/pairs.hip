@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 #include <mutex>
 #include <new>
@@ -76,13 +77,16 @@ ClassTable make_table(int count, const int *lo, const int *K, const int *U) {
 
 // Default tile shapes by kind (index kind - 1) for single sets and batches.
 ClassTable default_table(int kind, bool batched) {
-    (void)kind;
     if (batched) {
         const int lo[4] = {4096, 1024, 256, 0}, K[4] = {8, 4, 2, 1},
                   U[4] = {2048, 1024, 512, 256};
         return make_table(4, lo, K, U);
     }
-    const int lo[3] = {65536, 8192, 0}, K[3] = {8, 4, 1}, U[3] = {8192, 1024, 256};
+    if (kind == PAIRS_KIND_ENERGY_F32) {
+        const int lo[3] = {65536, 8192, 0}, K[3] = {4, 4, 1}, U[3] = {1024, 1024, 256};
+        return make_table(3, lo, K, U);
+    }
+    const int lo[3] = {65536, 8192, 0}, K[3] = {8, 4, 1}, U[3] = {1024, 1024, 256};
     return make_table(3, lo, K, U);
 }
 
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_count_i32(const int32_t *__restrict_
                                                       const int32_t *__restrict__ z,
                                                       const int32_t *__restrict__ r, int n,
                                                       int U, uint64_t *out) {
-    __shared__ double lds[kWavesPerBlock * kCountI32Lds];
+    __shared__ int64_t lds[kWavesPerBlock * kCountI32Lds];
     const int wave = wave_id();
     const Band band = Band::of(n);
     const Tiling til = Tiling::of(band, K, U);
@@ -178,7 +182,10 @@ __global__ __launch_bounds__(kBlock) void k_count_i32(const int32_t *__restrict_
     int ra, u0, u1;
     task_range(band, til, blk, c, &ra, &u0, &u1);
     if (u0 >= u1) return;
-    uint32_t cnt = count_i32_task<K>(x, y, z, r, 0, band, ra, u0, u1, lds + wave * kCountI32Lds);
+    TaskInputs<int32_t, K> in;
+    load_task_inputs<int32_t, K, K, true>(x, y, z, r, 0, band, ra, u0, u1, in);
+    uint32_t cnt = count_i32_task<K, K>(x, y, z, r, 0, band, ra, u0, u1, lds + wave * kCountI32Lds,
+                                        in);
     if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)out, (unsigned long long)cnt);
 }
 
@@ -198,7 +205,10 @@ __global__ __launch_bounds__(kBlock) void k_count_f32(const float *__restrict__ 
     int ra, u0, u1;
     task_range(band, til, blk, c, &ra, &u0, &u1);
     if (u0 >= u1) return;
-    uint32_t cnt = count_f32_task<K>(x, y, z, r, 0, band, ra, u0, u1, lds + wave * kCountF32Lds);
+    TaskInputs<float, K> in;
+    load_task_inputs<float, K, K, true>(x, y, z, r, 0, band, ra, u0, u1, in);
+    uint32_t cnt = count_f32_task<K, K>(x, y, z, r, 0, band, ra, u0, u1, lds + wave * kCountF32Lds,
+                                        in);
     if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)out, (unsigned long long)cnt);
 }
 
@@ -217,8 +227,10 @@ __global__ __launch_bounds__(kBlock) void k_energy(const float *__restrict__ x,
     int ra, u0, u1;
     task_range(band, til, blk, c, &ra, &u0, &u1);
     if (u0 >= u1) return;
-    EnergyResult res = energy_task<K, PerObject, false>(x, y, z, nullptr, 0, band, ra, u0, u1,
-                                                        eps2, lds + wave * kEnergyLds, E);
+    TaskInputs<float, K> in;
+    load_task_inputs<float, K, K, false>(x, y, z, nullptr, 0, band, ra, u0, u1, in);
+    EnergyResult res = energy_task<K, K, PerObject, false>(x, y, z, nullptr, 0, band, ra, u0, u1,
+                                                           eps2, lds + wave * kEnergyLds, E, in);
     if (lane_id() == 0) atomicAdd(total, res.energy);
 }
 
@@ -318,6 +330,7 @@ enum Kind { kCountI32 = 1, kCountF32 = 2, kEnergyF32 = 3 };
 
 // LDS of one wave, in bytes, for every kind.
 constexpr int kLdsBytes = (kCountI32Lds * 8 > kEnergyLds * 4 ? kCountI32Lds * 8 : kEnergyLds * 4);
+static_assert(kLdsBytes % 16 == 0, "LDS windows keep 16-byte alignment");
 
 struct BatchIO {
     const void *x, *y, *z, *r;  // object arrays (r may be null for energies)
@@ -328,37 +341,69 @@ struct BatchIO {
     float eps2;
 };
 
-template <int K, int KindV>
+// Object type of a kind.
+template <int KindV>
+using ObjT = typename std::conditional<KindV == kCountI32, int32_t, float>::type;
+
+// Loads the inputs of a task of shape K (K <= KM); radii are loaded when the
+// batch has them.
+template <int K, int KM, int KindV>
+__device__ __forceinline__ void batched_inputs(const BatchIO &io, int64_t base, const Band &band,
+                                               int ra, int u0, int u1,
+                                               TaskInputs<ObjT<KindV>, KM> &in) {
+    using T = ObjT<KindV>;
+    if (io.r)
+        load_task_inputs<T, K, KM, true>((const T *)io.x, (const T *)io.y, (const T *)io.z,
+                                         (const T *)io.r, base, band, ra, u0, u1, in);
+    else
+        load_task_inputs<T, K, KM, false>((const T *)io.x, (const T *)io.y, (const T *)io.z,
+                                          nullptr, base, band, ra, u0, u1, in);
+}
+
+template <int K, int KM, int KindV>
 __device__ __forceinline__ void batched_task(const BatchIO &io, int64_t base, const Band &band,
-                                             int ra, int u0, int u1, int64_t set, void *win) {
-    if (KindV == kCountI32) {
-        uint32_t c = count_i32_task<K>((const int32_t *)io.x, (const int32_t *)io.y,
-                                       (const int32_t *)io.z, (const int32_t *)io.r, base, band,
-                                       ra, u0, u1, (double *)win);
+                                             int ra, int u0, int u1, int64_t set, void *win,
+                                             const TaskInputs<ObjT<KindV>, KM> &in) {
+    if constexpr (KindV == kCountI32) {
+        uint32_t c = count_i32_task<K, KM>((const int32_t *)io.x, (const int32_t *)io.y,
+                                           (const int32_t *)io.z, (const int32_t *)io.r, base,
+                                           band, ra, u0, u1, win,
+                                           in);
         if (lane_id() == 0 && c)
             atomicAdd((unsigned long long *)&io.counts[set], (unsigned long long)c);
-    } else if (KindV == kCountF32) {
-        uint32_t c = count_f32_task<K>((const float *)io.x, (const float *)io.y,
-                                       (const float *)io.z, (const float *)io.r, base, band, ra,
-                                       u0, u1, (float *)win);
+    } else if constexpr (KindV == kCountF32) {
+        uint32_t c = count_f32_task<K, KM>((const float *)io.x, (const float *)io.y,
+                                           (const float *)io.z, (const float *)io.r, base, band,
+                                           ra, u0, u1, (float *)win,
+                                           in);
         if (lane_id() == 0 && c)
             atomicAdd((unsigned long long *)&io.counts[set], (unsigned long long)c);
     } else {
         EnergyResult res;
         if (io.r)
-            res = energy_task<K, false, true>((const float *)io.x, (const float *)io.y,
-                                              (const float *)io.z, (const float *)io.r, base,
-                                              band, ra, u0, u1, io.eps2, (float *)win, nullptr);
+            res = energy_task<K, KM, false, true>((const float *)io.x, (const float *)io.y,
+                                                  (const float *)io.z, (const float *)io.r, base,
+                                                  band, ra, u0, u1, io.eps2, (float *)win,
+                                                  nullptr, in);
         else
-            res = energy_task<K, false, false>((const float *)io.x, (const float *)io.y,
-                                               (const float *)io.z, nullptr, base, band, ra, u0,
-                                               u1, io.eps2, (float *)win, nullptr);
+            res = energy_task<K, KM, false, false>((const float *)io.x, (const float *)io.y,
+                                                   (const float *)io.z, nullptr, base, band, ra,
+                                                   u0, u1, io.eps2, (float *)win, nullptr,
+                                                   in);
         if (lane_id() == 0) {
             atomicAdd(&io.energy[set], res.energy);
             if (io.r && res.count)
                 atomicAdd((unsigned long long *)&io.counts[set], (unsigned long long)res.count);
         }
     }
+}
+
+template <int K, int KindV>
+__device__ __forceinline__ void run_shape(const BatchIO &io, int64_t base, const Band &band,
+                                          int ra, int u0, int u1, int64_t set, void *win) {
+    TaskInputs<ObjT<KindV>, K> in;
+    batched_inputs<K, K, KindV>(io, base, band, ra, u0, u1, in);
+    batched_task<K, K, KindV>(io, base, band, ra, u0, u1, set, win, in);
 }
 
 // Runs one task with the compiled shape K (only shapes up to KMAX are compiled
@@ -368,13 +413,13 @@ template <int KindV, int KMAX>
 __device__ __forceinline__ void run_task(const BatchIO &io, int64_t base, const Band &band,
                                          int ra, int u0, int u1, int64_t set, int K, void *win) {
     if (KMAX >= 8 && K == 8)
-        batched_task<(KMAX >= 8 ? 8 : 1), KindV>(io, base, band, ra, u0, u1, set, win);
+        run_shape<(KMAX >= 8 ? 8 : 1), KindV>(io, base, band, ra, u0, u1, set, win);
     else if (KMAX >= 4 && K == 4)
-        batched_task<(KMAX >= 4 ? 4 : 1), KindV>(io, base, band, ra, u0, u1, set, win);
+        run_shape<(KMAX >= 4 ? 4 : 1), KindV>(io, base, band, ra, u0, u1, set, win);
     else if (KMAX >= 2 && K == 2)
-        batched_task<(KMAX >= 2 ? 2 : 1), KindV>(io, base, band, ra, u0, u1, set, win);
+        run_shape<(KMAX >= 2 ? 2 : 1), KindV>(io, base, band, ra, u0, u1, set, win);
     else if (K == 1)
-        batched_task<1, KindV>(io, base, band, ra, u0, u1, set, win);
+        run_shape<1, KindV>(io, base, band, ra, u0, u1, set, win);
 }
 
 // Plans: wave w runs the tasks descs[wave_start[w] .. wave_start[w+1]), a list
@@ -536,7 +581,7 @@ pairs_status_t device_state(DeviceState **st) {
         int ncu = 0;
         e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) {
-            hipFree(p);
+            (void)hipFree(p);
             return hip_fail(e);
         }
         d.n_cu = ncu;
@@ -1044,9 +1089,9 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
         e = hipMemcpy(p->d_descs, laid.data(), sizeof(TaskDesc) * (size_t)ntasks,
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        if (p->d_offsets) hipFree(p->d_offsets);
-        if (p->d_wave_start) hipFree(p->d_wave_start);
-        if (p->d_descs) hipFree(p->d_descs);
+        if (p->d_offsets) (void)hipFree(p->d_offsets);
+        if (p->d_wave_start) (void)hipFree(p->d_wave_start);
+        if (p->d_descs) (void)hipFree(p->d_descs);
         delete p;
         g_last_hip_error = e;
         return e == hipErrorOutOfMemory ? PAIRS_ERR_NO_MEMORY : PAIRS_ERR_HIP;
@@ -1110,12 +1155,12 @@ pairs_status_t pairs_plan_execute(pairs_plan_t plan, const void *const *in, void
 pairs_status_t pairs_plan_destroy(pairs_plan_t plan) {
     if (!plan) return PAIRS_OK;
     int cur = 0;
-    hipGetDevice(&cur);
-    hipSetDevice(plan->device);
-    if (plan->d_offsets) hipFree(plan->d_offsets);
-    if (plan->d_descs) hipFree(plan->d_descs);
-    if (plan->d_wave_start) hipFree(plan->d_wave_start);
-    hipSetDevice(cur);
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(plan->device);
+    if (plan->d_offsets) (void)hipFree(plan->d_offsets);
+    if (plan->d_descs) (void)hipFree(plan->d_descs);
+    if (plan->d_wave_start) (void)hipFree(plan->d_wave_start);
+    (void)hipSetDevice(cur);
     delete plan;
     return PAIRS_OK;
 }
@@ -1157,7 +1202,7 @@ pairs_status_t pairs_plan_capture_steps(pairs_plan_t plan, float *x, float *y, f
     pairs_status_t st = PAIRS_OK;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
-        hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs);
         return hip_fail(e);
     }
     for (int k = 0; k < n_steps && st == PAIRS_OK; ++k) {
@@ -1171,7 +1216,7 @@ pairs_status_t pairs_plan_capture_steps(pairs_plan_t plan, float *x, float *y, f
     }
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     if (st != PAIRS_OK) {
         if (g) hipGraphDestroy(g);
         return st;
@@ -1180,13 +1225,13 @@ pairs_status_t pairs_plan_capture_steps(pairs_plan_t plan, float *x, float *y, f
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return hip_fail(e);
     }
     pairs_graph_s *pg = new (std::nothrow) pairs_graph_s{g, ex, dev};
     if (!pg) {
-        hipGraphExecDestroy(ex);
-        hipGraphDestroy(g);
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(g);
         return PAIRS_ERR_NO_MEMORY;
     }
     *out = pg;
@@ -1201,8 +1246,8 @@ pairs_status_t pairs_graph_launch(pairs_graph_t graph, pairs_stream_t stream) {
 
 pairs_status_t pairs_graph_destroy(pairs_graph_t graph) {
     if (!graph) return PAIRS_OK;
-    hipGraphExecDestroy(graph->exec);
-    hipGraphDestroy(graph->graph);
+    (void)hipGraphExecDestroy(graph->exec);
+    (void)hipGraphDestroy(graph->graph);
     delete graph;
     return PAIRS_OK;
 }

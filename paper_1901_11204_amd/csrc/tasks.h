@@ -23,12 +23,175 @@ namespace pairs_dev {
 
 // ------------------------------------------------------------ int32 count --
 //
-// Exact predicate in double precision (Gram form).  With h = (|p|^2 - r^2)/2,
-//   |p_i - p_j|^2 <= (r_i + r_j)^2  <=>  p_i.p_j + r_i r_j - h_i >= h_j.
-// Inside the exact domain (|coordinate| <= 2^24, 0 <= r <= 2^24) every
-// product is an integer of magnitude at most 2^48 and every partial sum a
-// multiple of 1/2 below 2^51 in magnitude, so every fused multiply-add is
-// exact and the comparison decides the integer predicate.
+// Exact predicate in 64-bit integers (Gram form).  With q = |p|^2 - r^2,
+//   |p_i - p_j|^2 <= (r_i + r_j)^2  <=>  q_i + q_j <= 2 (p_i.p_j + r_i r_j),
+// which is evaluated as v = -q_i + sum over the four coordinates of
+// (2 c_i) c_j with 32x32->64-bit multiply-adds, and the test v >= q_j.
+// For |coordinate|, r <= 2^29 every 2 c_i fits in 32 bits, every product is
+// at most 2^59 in magnitude and every partial sum stays below 2^62, so nothing
+// overflows and the test is exact; the library's domain (2^24) is inside.
+
+struct RowI32 {
+    int32_t ax, ay, az, ar;  // 2x, 2y, 2z, 2r
+    int64_t nq;              // -q
+};
+
+struct PartnerI32 {
+    int32_t x, y, z, r;
+};
+
+__device__ __forceinline__ int64_t gram_q(int32_t x, int32_t y, int32_t z, int32_t r) {
+    int64_t q = (int64_t)x * x;
+    q += (int64_t)y * y;
+    q += (int64_t)z * z;
+    q -= (int64_t)r * r;
+    return q;
+}
+
+__device__ __forceinline__ bool gram_hit(const RowI32 &a, const PartnerI32 &b, int64_t qb) {
+    int64_t v = a.nq + (int64_t)a.ax * b.x;
+    v += (int64_t)a.ay * b.y;
+    v += (int64_t)a.az * b.z;
+    v += (int64_t)a.ar * b.r;
+    return v >= qb;
+}
+
+// LDS window of one wave, in 8-byte words: large enough for both forms (the
+// integer form uses 64 partner records of 16 bytes and 64 q values, the
+// double form five arrays of 64 doubles).
+constexpr int kCountI32Lds = 5 * kWave;
+
+// Row i evaluates the virtual partner u iff i < u <= i + steps(i).
+__device__ __forceinline__ bool owns(int u, int i, int steps) {
+    return (unsigned)(u - 1 - i) < (unsigned)steps;
+}
+
+__device__ __forceinline__ int64_t partner_index(int64_t base, const Band &band, int u) {
+    return base + (u >= band.n ? u - band.n : u);
+}
+
+// The raw inputs a task starts from: the K row objects of the lane and the
+// lane's partner of the first group.  Loading them is separated from running
+// the task so that a persistent wave can fetch the next task's inputs while
+// the current task computes.  KM >= K is the array size (the largest shape a
+// kernel serves); only the first K slices are used.
+template <typename T, int KM>
+struct TaskInputs {
+    T x[KM], y[KM], z[KM], r[KM];
+    T px, py, pz, pr;
+};
+
+template <typename T, int K, int KM, bool WithR>
+__device__ __forceinline__ void load_task_inputs(const T *__restrict__ X, const T *__restrict__ Y,
+                                                 const T *__restrict__ Z, const T *__restrict__ R,
+                                                 int64_t base, const Band &band, int ra, int u0,
+                                                 int u1, TaskInputs<T, KM> &in) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = ra + kWave * k + lane;
+        in.x[k] = in.y[k] = in.z[k] = in.r[k] = T(0);
+        if (i < band.n) {
+            const int64_t g = base + i;
+            in.x[k] = X[g];
+            in.y[k] = Y[g];
+            in.z[k] = Z[g];
+            if (WithR) in.r[k] = R[g];
+        }
+    }
+    in.px = in.py = in.pz = in.pr = T(0);
+    const int u = u0 + lane;
+    if (u < u1) {
+        const int64_t g = partner_index(base, band, u);
+        in.px = X[g];
+        in.py = Y[g];
+        in.pz = Z[g];
+        if (WithR) in.pr = R[g];
+    }
+}
+
+template <int K, int KM>
+__device__ __forceinline__ uint32_t count_i32_task_i64(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
+                                   const int32_t *__restrict__ pz, const int32_t *__restrict__ pr,
+                                   int64_t base, const Band band, int ra, int u0, int u1,
+                                   void *__restrict__ lds, const TaskInputs<int32_t, KM> &in) {
+    PartnerI32 *wp = (PartnerI32 *)lds;
+    int64_t *wq = (int64_t *)lds + 2 * kWave;
+    const int lane = lane_id();
+    RowI32 rows[K];
+    int row[K], nsteps[K];  // row index and its step count (0 for padding rows)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int i = ra + kWave * k + lane;
+        row[k] = i;
+        if (i < band.n) {
+            const int32_t x = in.x[k], y = in.y[k], z = in.z[k], r = in.r[k];
+            rows[k].ax = 2 * x;
+            rows[k].ay = 2 * y;
+            rows[k].az = 2 * z;
+            rows[k].ar = 2 * r;
+            rows[k].nq = -gram_q(x, y, z, r);
+            nsteps[k] = band.steps(i);
+        } else {
+            rows[k].ax = rows[k].ay = rows[k].az = rows[k].ar = 0;
+            rows[k].nq = -((int64_t)1 << 62);  // never hits
+            nsteps[k] = 0;
+        }
+    }
+    const int rlast = min(ra + kWave * K, band.n) - 1;
+    const int core_lo = rlast + 1;            // every row has u - 1 >= row
+    const int core_hi = ra + band.steps(ra);  // every row has u <= row + steps(row)
+
+    uint32_t cnt = 0;
+    int32_t qx = in.px, qy = in.py, qz = in.pz, qr = in.pr;  // this group's partner values
+    for (int g0 = u0; g0 < u1; g0 += kWave) {
+        {
+            PartnerI32 p;
+            p.x = qx; p.y = qy; p.z = qz; p.r = qr;
+            wp[lane] = p;
+            // padding partner: q above any reachable v, never hits
+            wq[lane] = (g0 + lane >= u1) ? INT64_MAX : gram_q(qx, qy, qz, qr);
+        }
+        {
+            int u = g0 + kWave + lane;
+            if (u < u1) {
+                int64_t g = partner_index(base, band, u);
+                qx = px[g]; qy = py[g]; qz = pz[g]; qr = pr[g];
+            }
+        }
+        wave_sync();
+        const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
+        if (g0 >= core_lo && g0 + gn - 1 <= core_hi) {
+#pragma unroll 2
+            for (int t = 0; t < kWave; ++t) {
+                const PartnerI32 b = wp[t];
+                const int64_t qb = wq[t];
+#pragma unroll
+                for (int k = 0; k < K; ++k) cnt += count_bits(gram_hit(rows[k], b, qb));
+            }
+        } else {
+            for (int t = 0; t < gn; ++t) {
+                const int u = g0 + t;
+                const PartnerI32 b = wp[t];
+                const int64_t qb = wq[t];
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    cnt += count_bits_both(gram_hit(rows[k], b, qb), owns(u, row[k], nsteps[k]));
+            }
+        }
+        wave_sync();
+    }
+    return cnt;
+}
+
+// The same predicate in double precision, for tall row blocks.  With
+// h = q/2 = (|p|^2 - r^2)/2 it reads p_i.p_j + r_i r_j - h_i >= h_j; inside
+// |coordinate|, r <= 2^24 every product is an integer of magnitude at most 2^48
+// and every partial sum a multiple of 1/2 below 2^51, so each fused
+// multiply-add and the comparison are exact.  Its partner records are 40
+// bytes instead of 24, but gfx950 issues its FP64 fused multiply-adds and
+// compares slightly faster than the 64-bit integer ones, so it wins where
+// one partner feeds many rows (K >= 4) and LDS traffic is no limit.
 
 __device__ __forceinline__ void gram_features(int32_t xi, int32_t yi, int32_t zi, int32_t ri,
                                               double &X, double &Y, double &Z, double &R,
@@ -44,23 +207,13 @@ __device__ __forceinline__ void gram_features(int32_t xi, int32_t yi, int32_t zi
     H = 0.5 * a;
 }
 
-// LDS window of one wave: 5 arrays of 64 doubles.
-constexpr int kCountI32Lds = 5 * kWave;
 
-// Row i evaluates the virtual partner u iff i < u <= i + steps(i).
-__device__ __forceinline__ bool owns(int u, int i, int steps) {
-    return (unsigned)(u - 1 - i) < (unsigned)steps;
-}
-
-__device__ __forceinline__ int64_t partner_index(int64_t base, const Band &band, int u) {
-    return base + (u >= band.n ? u - band.n : u);
-}
-
-template <int K>
-__device__ uint32_t count_i32_task(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
+template <int K, int KM>
+__device__ __forceinline__ uint32_t count_i32_task_f64(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
                                    const int32_t *__restrict__ pz, const int32_t *__restrict__ pr,
                                    int64_t base, const Band band, int ra, int u0, int u1,
-                                   double *__restrict__ win) {
+                                   void *__restrict__ lds, const TaskInputs<int32_t, KM> &in) {
+    double *win = (double *)lds;
     const int lane = lane_id();
     double xr[K], yr[K], zr[K], rr[K], nh[K];
     int row[K], nsteps[K];  // row index and its step count (0 for padding rows)
@@ -69,9 +222,8 @@ __device__ uint32_t count_i32_task(const int32_t *__restrict__ px, const int32_t
         int i = ra + kWave * k + lane;
         row[k] = i;
         if (i < band.n) {
-            int64_t g = base + i;
             double h;
-            gram_features(px[g], py[g], pz[g], pr[g], xr[k], yr[k], zr[k], rr[k], h);
+            gram_features(in.x[k], in.y[k], in.z[k], in.r[k], xr[k], yr[k], zr[k], rr[k], h);
             nh[k] = -h;
             nsteps[k] = band.steps(i);
         } else {
@@ -85,14 +237,7 @@ __device__ uint32_t count_i32_task(const int32_t *__restrict__ px, const int32_t
     const int core_hi = ra + band.steps(ra);  // every row has u <= row + steps(row)
 
     uint32_t cnt = 0;
-    int32_t qx = 0, qy = 0, qz = 0, qr = 0;  // next group's raw partner values
-    {
-        int u = u0 + lane;
-        if (u < u1) {
-            int64_t g = partner_index(base, band, u);
-            qx = px[g]; qy = py[g]; qz = pz[g]; qr = pr[g];
-        }
-    }
+    int32_t qx = in.px, qy = in.py, qz = in.pz, qr = in.pr;  // this group's raw partner values
     for (int g0 = u0; g0 < u1; g0 += kWave) {
         {
             double X, Y, Z, R, H;
@@ -112,7 +257,7 @@ __device__ uint32_t count_i32_task(const int32_t *__restrict__ px, const int32_t
             }
         }
         wave_sync();
-        const int gn = min(kWave, u1 - g0);
+        const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
         if (g0 >= core_lo && g0 + gn - 1 <= core_hi) {
 #pragma unroll 2
             for (int t = 0; t < kWave; ++t) {
@@ -138,13 +283,30 @@ __device__ uint32_t count_i32_task(const int32_t *__restrict__ px, const int32_t
                     v = __builtin_fma(yr[k], jy, v);
                     v = __builtin_fma(zr[k], jz, v);
                     v = __builtin_fma(rr[k], jr, v);
-                    cnt += count_bits(v >= jh && owns(u, row[k], nsteps[k]));
+                    cnt += count_bits_both(v >= jh, owns(u, row[k], nsteps[k]));
                 }
             }
         }
         wave_sync();
     }
     return cnt;
+}
+
+
+// The exact int32 count task: 64-bit integer form for short row blocks
+// (K <= 2, where the broadcast of each partner limits), double form for tall
+// ones.  Both decide the same integer predicate inside the exact domain.
+template <int K, int KM>
+__device__ __forceinline__ uint32_t count_i32_task(const int32_t *__restrict__ px,
+                                                   const int32_t *__restrict__ py,
+                                                   const int32_t *__restrict__ pz,
+                                                   const int32_t *__restrict__ pr, int64_t base,
+                                                   const Band band, int ra, int u0, int u1,
+                                                   void *__restrict__ lds,
+                                                   const TaskInputs<int32_t, KM> &in) {
+    if (K >= 4)
+        return count_i32_task_f64<K, KM>(px, py, pz, pr, base, band, ra, u0, u1, lds, in);
+    return count_i32_task_i64<K, KM>(px, py, pz, pr, base, band, ra, u0, u1, lds, in);
 }
 
 // --------------------------------------------------------- float32 count --
@@ -167,11 +329,11 @@ __device__ __forceinline__ bool hit_f32(float xi, float yi, float zi, float ri, 
 
 constexpr int kCountF32Lds = 4 * kWave;
 
-template <int K>
-__device__ uint32_t count_f32_task(const float *__restrict__ px, const float *__restrict__ py,
+template <int K, int KM>
+__device__ __forceinline__ uint32_t count_f32_task(const float *__restrict__ px, const float *__restrict__ py,
                                    const float *__restrict__ pz, const float *__restrict__ pr,
                                    int64_t base, const Band band, int ra, int u0, int u1,
-                                   float *__restrict__ win) {
+                                   float *__restrict__ win, const TaskInputs<float, KM> &in) {
     const int lane = lane_id();
     float xr[K], yr[K], zr[K], rr[K];
     int row[K], nsteps[K];
@@ -180,8 +342,7 @@ __device__ uint32_t count_f32_task(const float *__restrict__ px, const float *__
         int i = ra + kWave * k + lane;
         row[k] = i;
         if (i < band.n) {
-            int64_t g = base + i;
-            xr[k] = px[g]; yr[k] = py[g]; zr[k] = pz[g]; rr[k] = pr[g];
+            xr[k] = in.x[k]; yr[k] = in.y[k]; zr[k] = in.z[k]; rr[k] = in.r[k];
             nsteps[k] = band.steps(i);
         } else {
             xr[k] = INFINITY;  // distance infinite: never hits
@@ -192,14 +353,7 @@ __device__ uint32_t count_f32_task(const float *__restrict__ px, const float *__
     const int rlast = min(ra + kWave * K, band.n) - 1;
     const int core_lo = rlast + 1, core_hi = ra + band.steps(ra);
     uint32_t cnt = 0;
-    float qx = 0, qy = 0, qz = 0, qr = 0;
-    {
-        int u = u0 + lane;
-        if (u < u1) {
-            int64_t g = partner_index(base, band, u);
-            qx = px[g]; qy = py[g]; qz = pz[g]; qr = pr[g];
-        }
-    }
+    float qx = in.px, qy = in.py, qz = in.pz, qr = in.pr;
     for (int g0 = u0; g0 < u1; g0 += kWave) {
         const bool pad = g0 + lane >= u1;
         win[0 * kWave + lane] = pad ? -INFINITY : qx;
@@ -214,7 +368,7 @@ __device__ uint32_t count_f32_task(const float *__restrict__ px, const float *__
             }
         }
         wave_sync();
-        const int gn = min(kWave, u1 - g0);
+        const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
         if (g0 >= core_lo && g0 + gn - 1 <= core_hi) {
 #pragma unroll 2
             for (int t = 0; t < kWave; ++t) {
@@ -231,8 +385,8 @@ __device__ uint32_t count_f32_task(const float *__restrict__ px, const float *__
                             jr = win[3 * kWave + t];
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    cnt += count_bits(hit_f32(xr[k], yr[k], zr[k], rr[k], jx, jy, jz, jr) &&
-                                      owns(u, row[k], nsteps[k]));
+                    cnt += count_bits_both(hit_f32(xr[k], yr[k], zr[k], rr[k], jx, jy, jz, jr),
+                                           owns(u, row[k], nsteps[k]));
             }
         }
         wave_sync();
@@ -245,7 +399,8 @@ __device__ uint32_t count_f32_task(const float *__restrict__ px, const float *__
 // e = 1/sqrt(d2 + eps2) in float32 with the hardware reciprocal square root.
 // Row sums are float32 partials of at most kFoldEvery terms folded into
 // double accumulators.  With PerObject the partner side of each pair is
-// summed across the wave (DPP) and added once per partner and task.  With
+// summed across the wave, 16 partners at a time (reduce_scatter16), and added
+// once per partner and task.  With
 // WithCount the pinned binary32 collision predicate is evaluated on the same
 // differences and counted, and e uses d2 + eps2 with that squared distance.
 
@@ -264,11 +419,13 @@ __device__ __forceinline__ void energy_group(const float (&xr)[K], const float (
                                              const int (&row)[K], const int (&nsteps)[K],
                                              float (&part)[K], double (&acc)[K], uint32_t &cnt,
                                              float *__restrict__ win, int g0, int gn,
-                                             float eps2) {
+                                             float eps2, int slot) {
     const int lane = lane_id();
     for (int t0 = 0; t0 < gn; t0 += kFoldEvery) {
-#pragma unroll 2
-        for (int t = t0; t < t0 + kFoldEvery; ++t) {
+        float js_all[kFoldEvery];
+#pragma unroll
+        for (int tt = 0; tt < kFoldEvery; ++tt) {
+            const int t = t0 + tt;
             const float jx = win[t], jy = win[kWave + t], jz = win[2 * kWave + t];
             float jr = 0.0f;
             if (WithCount) jr = win[3 * kWave + t];
@@ -285,7 +442,7 @@ __device__ __forceinline__ void energy_group(const float (&xr)[K], const float (
                     const float R = __fadd_rn(rr[k], jr);
                     const bool hit = d2 <= __fmul_rn(R, R);
                     if (Masked)
-                        cnt += count_bits(hit && valid);
+                        cnt += count_bits_both(hit, valid);
                     else
                         cnt += count_bits(hit);
                     e = __builtin_amdgcn_rsqf(d2 + eps2);
@@ -299,10 +456,12 @@ __device__ __forceinline__ void energy_group(const float (&xr)[K], const float (
                 part[k] += e;
                 if (PerObject) js += e;
             }
-            if (PerObject) {
-                const float s = wave_total_in_lane63(js);
-                if (lane == kWave - 1) win[4 * kWave + t] = s;
-            }
+            if (PerObject) js_all[tt] = js;
+        }
+        if (PerObject) {
+            // all 4 lanes of a group store the same value to the same slot
+            const float s = reduce_scatter16(js_all);
+            win[4 * kWave + t0 + slot] = s;
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -312,11 +471,12 @@ __device__ __forceinline__ void energy_group(const float (&xr)[K], const float (
     }
 }
 
-template <int K, bool PerObject, bool WithCount>
-__device__ EnergyResult energy_task(const float *__restrict__ px, const float *__restrict__ py,
+template <int K, int KM, bool PerObject, bool WithCount>
+__device__ __forceinline__ EnergyResult energy_task(const float *__restrict__ px, const float *__restrict__ py,
                                     const float *__restrict__ pz, const float *__restrict__ pr,
                                     int64_t base, const Band band, int ra, int u0, int u1,
-                                    float eps2, float *__restrict__ win, double *__restrict__ E) {
+                                    float eps2, float *__restrict__ win, double *__restrict__ E,
+                                    const TaskInputs<float, KM> &in) {
     const int lane = lane_id();
     float xr[K], yr[K], zr[K], rr[K], part[K];
     double acc[K];
@@ -326,9 +486,8 @@ __device__ EnergyResult energy_task(const float *__restrict__ px, const float *_
         int i = ra + kWave * k + lane;
         row[k] = i;
         if (i < band.n) {
-            int64_t g = base + i;
-            xr[k] = px[g]; yr[k] = py[g]; zr[k] = pz[g];
-            rr[k] = WithCount ? pr[g] : 0.0f;
+            xr[k] = in.x[k]; yr[k] = in.y[k]; zr[k] = in.z[k];
+            rr[k] = WithCount ? in.r[k] : 0.0f;
             nsteps[k] = band.steps(i);
         } else {
             xr[k] = INFINITY;  // infinite distance: e is exactly 0, never hits
@@ -340,16 +499,9 @@ __device__ EnergyResult energy_task(const float *__restrict__ px, const float *_
     }
     const int rlast = min(ra + kWave * K, band.n) - 1;
     const int core_lo = rlast + 1, core_hi = ra + band.steps(ra);
+    const int slot = PerObject ? reduce_scatter16_slot() : 0;
     uint32_t cnt = 0;
-    float qx = 0, qy = 0, qz = 0, qr = 0;
-    {
-        int u = u0 + lane;
-        if (u < u1) {
-            int64_t g = partner_index(base, band, u);
-            qx = px[g]; qy = py[g]; qz = pz[g];
-            if (WithCount) qr = pr[g];
-        }
-    }
+    float qx = in.px, qy = in.py, qz = in.pz, qr = WithCount ? in.pr : 0.0f;
     for (int g0 = u0; g0 < u1; g0 += kWave) {
         const bool pad = g0 + lane >= u1;
         win[0 * kWave + lane] = pad ? -INFINITY : qx;
@@ -365,13 +517,13 @@ __device__ EnergyResult energy_task(const float *__restrict__ px, const float *_
             }
         }
         wave_sync();
-        const int gn = min(kWave, u1 - g0);
+        const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
         if (g0 >= core_lo && g0 + gn - 1 <= core_hi)
             energy_group<K, PerObject, WithCount, false>(xr, yr, zr, rr, row, nsteps, part, acc,
-                                                         cnt, win, g0, gn, eps2);
+                                                         cnt, win, g0, gn, eps2, slot);
         else
             energy_group<K, PerObject, WithCount, true>(xr, yr, zr, rr, row, nsteps, part, acc,
-                                                        cnt, win, g0, gn, eps2);
+                                                        cnt, win, g0, gn, eps2, slot);
         if (PerObject) {
             wave_sync();
             if (lane < gn)

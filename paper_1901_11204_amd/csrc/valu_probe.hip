@@ -108,12 +108,12 @@ int valu_probe_run(int which, int blocks, double *ms, double *lane_ops) {
     hipError_t e = hipMalloc(&buf, 1 << 20);
     if (e != hipSuccess) return (int)e;
     hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
     const double lanes = (double)blocks * 256;
     double per_lane = 0;
     for (int rep = 0; rep < 2; ++rep) {
-        hipEventRecord(e0);
+        (void)hipEventRecord(e0);
         switch (which) {
             case 0: p_fma_f64<<<blocks, 256>>>((double *)buf, 0.999, 1e-3); per_lane = kIters * kChains; break;
             case 1: p_fma_f32<<<blocks, 256>>>((float *)buf, 0.999f, 1e-3f); per_lane = kIters * kChains; break;
@@ -121,19 +121,19 @@ int valu_probe_run(int which, int blocks, double *ms, double *lane_ops) {
             case 3: p_fma3_rsq<<<blocks, 256>>>((float *)buf, 0.999f, 1e-3f); per_lane = (kIters / 4) * kChains * 4; break;
             case 4: p_count_f64<<<blocks, 256>>>((unsigned *)buf, 0.999, 1e-3, 3.0); per_lane = (kIters / 5) * kChains * 5; break;
             case 5: p_mad_u64_u32<<<blocks, 256>>>((unsigned long long *)buf, 12345u); per_lane = kIters * kChains; break;
-            default: hipFree(buf); return (int)hipErrorInvalidValue;
+            default: (void)hipFree(buf); return (int)hipErrorInvalidValue;
         }
-        hipEventRecord(e1);
-        hipEventSynchronize(e1);
+        (void)hipEventRecord(e1);
+        (void)hipEventSynchronize(e1);
     }
     float t = 0;
-    hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventElapsedTime(&t, e0, e1);
     *ms = t;
     *lane_ops = lanes * per_lane;
     e = hipGetLastError();
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(buf);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
     return (int)e;
 }
 

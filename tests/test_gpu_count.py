@@ -44,8 +44,35 @@ def test_count_i32_config1():
     assert P.count_i32(*dev(*s.arrays())) == oracle.count_i32(*s.arrays())
 
 
-def test_count_i32_domain_edges():
-    L = 2 ** 24
+@pytest.fixture
+def forced_shape():
+    """Force one single-set tile shape for a kind; restores the defaults after."""
+    kinds = []
+
+    def force(kind, rows_per_lane, chunk):
+        kinds.append(kind)
+        P.pairs_set_shapes(kind, False, [(0, rows_per_lane, chunk)])
+
+    yield force
+    for k in kinds:
+        P.pairs_set_shapes(k, False, None)
+
+
+@pytest.mark.parametrize("K,U", [(1, 64), (1, 256), (2, 128), (4, 64), (4, 1024), (8, 512)])
+def test_count_i32_every_shape(forced_shape, K, U):
+    # both predicate forms (64-bit integer for K <= 2, double for K >= 4),
+    # across tile edges
+    forced_shape(P.KIND_COUNT_I32, K, U)
+    for n in (2, 3, 64 * K - 1, 64 * K, 64 * K + 1, 3 * 64 * K + 7, 2500):
+        s = dense_i32(n, 7 * n + K)
+        announce("count_i32 forced shape", K, U, n)
+        assert P.count_i32(*dev(*s.arrays())) == oracle.count_i32(*s.arrays()), (K, U, n)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+@pytest.mark.parametrize("L", [2 ** 22, 2 ** 24])
+def test_count_i32_domain_edges(forced_shape, K, L):
+    forced_shape(P.KIND_COUNT_I32, K, 256)
     rng = np.random.default_rng(5)
     n = 3001
     x, y, z = (rng.integers(-L, L, n, endpoint=True).astype(np.int32) for _ in range(3))
@@ -113,6 +140,16 @@ def test_count_i32_config2_full_size(n, key):
 
 
 F32_SIZES = [0, 1, 2, 3, 64, 65, 127, 129, 511, 513, 1000, 4096, 8193, 20011]
+
+
+@pytest.mark.parametrize("K,U", [(1, 64), (2, 128), (4, 256), (8, 512)])
+def test_count_f32_every_shape(forced_shape, K, U):
+    forced_shape(P.KIND_COUNT_F32, K, U)
+    rng = np.random.default_rng(K)
+    for n in (2, 64 * K - 1, 64 * K + 1, 2 * 64 * K + 5, 3001):
+        x, y, z = (rng.random(n, dtype=np.float32) for _ in range(3))
+        r = np.full(n, np.float32(0.07))
+        assert P.count_f32(*dev(x, y, z, r)) == oracle.count_f32(x, y, z, r), (K, U, n)
 
 
 @pytest.mark.parametrize("n", F32_SIZES)

@@ -37,6 +37,21 @@ def test_energy_matches_oracle(n):
     assert abs(tot2 - want_tot) <= TOL_TOTAL * want_tot
 
 
+@pytest.mark.parametrize("K,U", [(1, 64), (2, 128), (4, 256), (8, 1024)])
+def test_energy_every_shape(K, U):
+    P.pairs_set_shapes(P.KIND_ENERGY_F32, False, [(0, K, U)])
+    try:
+        for n in (2, 64 * K - 1, 64 * K + 1, 2 * 64 * K + 5, 3001):
+            p = w.particles_f32(n, 100 + n)
+            E, tot = P.energy_f32(*dev(*p.arrays()), eps2=float(EPS2))
+            want_tot = oracle.energy_total(*p.arrays(), EPS2)
+            assert abs(tot - want_tot) <= TOL_TOTAL * want_tot, (K, U, n)
+            want_E = oracle.energy_rows(*p.arrays(), EPS2)
+            assert np.max(np.abs(E.cpu().numpy() - want_E) / want_E) <= TOL_PARTICLE, (K, U, n)
+    finally:
+        P.pairs_set_shapes(P.KIND_ENERGY_F32, False, None)
+
+
 @pytest.mark.parametrize("n", [0, 1])
 def test_energy_no_pairs(n):
     p = w.particles_f32(n, 1)
