@@ -40,6 +40,34 @@ C_ALG = {"count_i32": 5, "energy_f32": 8, "energy_count_f32": 11}
 PLAIN_DEF_OPS = 12   # operations of the plain definition per pair (either kind)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "count_i32_n2p20_hbm.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1901_11204_amd", "csrc", f)
+                  for f in ("band.h", "device.h", "tasks.h", "pairs.hip")]
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a device copy), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = {}
+        with open(TRAFFIC_PROFILE) as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                if k.strip() in ("traffic_bytes_per_launch", "kernel_sources_sha256"):
+                    fields[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for p in KERNEL_SOURCES:
+            with open(p, "rb") as f:
+                h.update(f.read())
+        if fields.get("kernel_sources_sha256") != h.hexdigest():
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -225,7 +253,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32 in, int64 exact predicate, u64 count",
+        "dtype": "int32 in; exact Gram predicate in fp64 (int64 for 1-2 rows per lane); u64 count",
         "data": "synthetic (seeded uniform spheres)",
         "config": {"workload": "single set, N=2^20 int32 spheres, centres in [0,2^24)^3, "
                                "radii in [1,2^14], seed 2; exact collision count",
@@ -234,7 +262,8 @@ def main():
         "timing": {"ms_min": float(np.min(ms)), "ms_median": float(np.median(ms)),
                    "ms_max": float(np.max(ms)), "wall_s": wall},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                     "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
+                     "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK,
+                     "traffic": recorded_traffic(),
                      "per_pair_ops": C_ALG["count_i32"],
                      "plain_definition_frac": pairs / (ms_step * 1e-3) * PLAIN_DEF_OPS / VALU_PEAK},
     }
