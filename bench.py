@@ -107,8 +107,14 @@ def valu_probe(torch):
         if rc != 0:
             raise RuntimeError(f"valu probe {name}: hipError {rc}")
         rate = ops.value / (ms.value * 1e-3)
-        out[name] = {"ms": ms.value, "T_lane_ops_per_s": rate / 1e12,
-                     "frac_of_peak": rate / VALU_PEAK}
+        if name.startswith("lds_"):
+            # lane reads -> wave-wide reads per clock per CU, and bytes
+            per_clk = rate / 64 / N_CU / SCLK_HZ
+            out[name] = {"ms": ms.value, "wave_reads_per_clk_per_cu": per_clk,
+                         "bytes_per_clk_per_cu": per_clk * 64 * (16 if "b128" in name else 8)}
+        else:
+            out[name] = {"ms": ms.value, "T_lane_ops_per_s": rate / 1e12,
+                         "frac_of_peak": rate / VALU_PEAK}
     return out
 
 

@@ -238,22 +238,38 @@ pairs_status_t pairs_graph_destroy(pairs_graph_t graph);
 
 /* ------------------------------------------------------------ tile shapes -- */
 /*
- * Tile shapes of the kernels, chosen per size class.  One wave handles
- * 64 * rows_per_lane consecutive rows of a set against a chunk of at most
- * `chunk` virtual partners.  Entry c of a table applies to sets with
- * n > min_n[c] that no earlier entry takes; the last entry takes the rest.
- * Entries are listed from the largest sets down (min_n strictly decreasing),
- * rows_per_lane is 1, 2, 4 or 8, chunk a multiple of 64 in [64, 2^24].
+ * Tile shapes of the kernels, chosen per size class.  Entry c of a table
+ * applies to sets with n > min_n[c] that no earlier entry takes; the last
+ * entry takes the rest.  Entries are listed from the largest sets down
+ * (min_n strictly decreasing).  Each entry names one of two wave-task forms
+ * of the balanced assignment (Section 4):
+ *
+ * PAIRS_FORM_BROADCAST: a wave holds 64 * rows_per_lane consecutive rows of a
+ *   set, K = rows_per_lane per lane in lane-major order, and sweeps a chunk of
+ *   at most `chunk` virtual partners u = row + s, each broadcast to every
+ *   lane.  rows_per_lane is 1, 2, 4 or 8; chunk a multiple of 64 in
+ *   [64, 2^24].
+ * PAIRS_FORM_STEPPING: the paper's own per-row form.  Each lane holds K =
+ *   rows_per_lane (1 or 2) consecutive rows and steps through their partners
+ *   (row + s) mod n, `chunk` steps per task.  chunk is a multiple of 16 in
+ *   [16, 288] for K = 1 and in [16, 272] for K = 2.  Batched tables only.  A
+ *   plan packs whole sets of equal size that fit one wave (ceil(n/K) <= 64)
+ *   into shared waves; unplanned calls give each set its own waves.
+ *
  * Tables are per kind (PAIRS_KIND_*) and per mode (batched = 0: single-set
  * calls, 1: batched calls and plans).  A plan keeps the table of its
  * creation.  set(NULL) restores the defaults.  Results never depend on the
  * shapes; only the speed does.
  */
+#define PAIRS_FORM_BROADCAST 0
+#define PAIRS_FORM_STEPPING 1
+
 typedef struct {
     int32_t count;            /* entries used, 1..4 */
     int32_t min_n[4];
     int32_t rows_per_lane[4];
     int32_t chunk[4];
+    int32_t form[4];          /* PAIRS_FORM_* */
 } pairs_shape_table_t;
 
 pairs_status_t pairs_get_shapes(int kind, int batched, pairs_shape_table_t *out);
@@ -269,6 +285,17 @@ pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t
  * *n_tasks receives the task count; out may be NULL to query it only.
  */
 pairs_status_t pairs_debug_task_ranges(int n, int rows_per_lane, int chunk, int32_t *out,
+                                       int64_t capacity, int64_t *n_tasks);
+
+/*
+ * Host-only: the stepping-form tasks of a single set of n objects (Section 4:
+ * row i visits (i + s) mod n for s = 1 .. steps(i)) for rows_per_lane K in
+ * {1, 2} and chunk steps per task (chunk >= 1).  Task k is written as
+ * out[4k] = first row r0, out[4k+1] = s0, out[4k+2] = T, out[4k+3] = x: the
+ * rows [r0, r0 + 64K) that exist run the steps [s0, s0 + T), and when x is 1
+ * the rows below n/2 also run step s0 + T (the extra step of an even n).
+ */
+pairs_status_t pairs_debug_step_ranges(int n, int rows_per_lane, int chunk, int32_t *out,
                                        int64_t capacity, int64_t *n_tasks);
 
 /* ---------------------------------------------------------------- errors -- */

@@ -20,6 +20,7 @@ __all__ = [
     "pairs_count_i32", "pairs_count_f32", "pairs_energy_f32",
     "pairs_batched_workspace_size", "pairs_count_i32_batched", "pairs_count_f32_batched",
     "pairs_energy_f32_batched", "pairs_jitter_f32", "pairs_debug_task_ranges",
+    "pairs_debug_step_ranges", "FORM_BROADCAST", "FORM_STEPPING",
     "Plan", "Graph", "ShapeTable", "pairs_get_shapes", "pairs_set_shapes",
     "count_i32", "count_f32", "energy_f32",
 ]
@@ -63,10 +64,15 @@ _u64 = ctypes.c_uint64
 _int = ctypes.c_int
 
 
+FORM_BROADCAST = 0
+FORM_STEPPING = 1
+
+
 class ShapeTable(ctypes.Structure):
-    """pairs_shape_table_t: up to 4 (min_n, rows_per_lane, chunk) entries."""
+    """pairs_shape_table_t: up to 4 (min_n, rows_per_lane, chunk, form) entries."""
     _fields_ = [("count", ctypes.c_int32), ("min_n", ctypes.c_int32 * 4),
-                ("rows_per_lane", ctypes.c_int32 * 4), ("chunk", ctypes.c_int32 * 4)]
+                ("rows_per_lane", ctypes.c_int32 * 4), ("chunk", ctypes.c_int32 * 4),
+                ("form", ctypes.c_int32 * 4)]
 
 
 def _declare(L):
@@ -92,6 +98,7 @@ def _declare(L):
         "pairs_graph_launch": [_vp, _vp],
         "pairs_graph_destroy": [_vp],
         "pairs_debug_task_ranges": [_int, _int, _int, _vp, _i64, ctypes.POINTER(_i64)],
+        "pairs_debug_step_ranges": [_int, _int, _int, _vp, _i64, ctypes.POINTER(_i64)],
         "pairs_get_shapes": [_int, _int, ctypes.POINTER(ShapeTable)],
         "pairs_set_shapes": [_int, _int, ctypes.POINTER(ShapeTable)],
     }
@@ -291,23 +298,40 @@ def pairs_debug_task_ranges(n: int, rows_per_lane: int, chunk: int):
     return out
 
 
+def pairs_debug_step_ranges(n: int, rows_per_lane: int, chunk: int):
+    """Host-only: the (first row, s0, T, x) of every stepping-form task of a
+    set of n objects."""
+    import numpy as np
+    cnt = _i64(0)
+    _check(lib().pairs_debug_step_ranges(n, rows_per_lane, chunk, None, 0, ctypes.byref(cnt)),
+           "pairs_debug_step_ranges")
+    out = np.zeros((int(cnt.value), 4), dtype=np.int32)
+    _check(lib().pairs_debug_step_ranges(n, rows_per_lane, chunk, out.ctypes.data_as(_vp),
+                                         int(cnt.value), ctypes.byref(cnt)),
+           "pairs_debug_step_ranges")
+    return out
+
+
 def pairs_get_shapes(kind: int, batched: bool):
-    """The tile-shape table as a list of (min_n, rows_per_lane, chunk)."""
+    """The tile-shape table as a list of (min_n, rows_per_lane, chunk, form)."""
     t = ShapeTable()
     _check(lib().pairs_get_shapes(kind, int(bool(batched)), ctypes.byref(t)), "pairs_get_shapes")
-    return [(t.min_n[c], t.rows_per_lane[c], t.chunk[c]) for c in range(t.count)]
+    return [(t.min_n[c], t.rows_per_lane[c], t.chunk[c], t.form[c]) for c in range(t.count)]
 
 
 def pairs_set_shapes(kind: int, batched: bool, entries) -> None:
-    """Set the tile-shape table from (min_n, rows_per_lane, chunk) entries,
-    largest sets first; None restores the defaults."""
+    """Set the tile-shape table from (min_n, rows_per_lane, chunk[, form])
+    entries, largest sets first (form defaults to FORM_BROADCAST); None
+    restores the defaults."""
     if entries is None:
         _check(lib().pairs_set_shapes(kind, int(bool(batched)), None), "pairs_set_shapes")
         return
     t = ShapeTable()
     t.count = len(entries)
-    for c, (lo, k, u) in enumerate(entries):
-        t.min_n[c], t.rows_per_lane[c], t.chunk[c] = int(lo), int(k), int(u)
+    for c, e in enumerate(entries):
+        lo, k, u = e[:3]
+        form = e[3] if len(e) > 3 else FORM_BROADCAST
+        t.min_n[c], t.rows_per_lane[c], t.chunk[c], t.form[c] = int(lo), int(k), int(u), int(form)
     _check(lib().pairs_set_shapes(kind, int(bool(batched)), ctypes.byref(t)), "pairs_set_shapes")
 
 

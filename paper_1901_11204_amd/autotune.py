@@ -22,11 +22,21 @@ import os
 import sys
 import time
 
-from . import (KIND_COUNT_F32, KIND_COUNT_I32, KIND_ENERGY_F32, Plan, pairs_get_shapes,
-               pairs_set_shapes)
+from . import (FORM_BROADCAST, FORM_STEPPING, KIND_COUNT_F32, KIND_COUNT_I32, KIND_ENERGY_F32,
+               Plan, pairs_get_shapes, pairs_set_shapes)
 
 ROWS = (1, 2, 4, 8)
 CHUNKS = (128, 256, 512, 1024, 2048, 4096, 8192)
+# (rows per lane, step chunks) of the row-stepping form (batched tables only)
+STEP_SHAPES = ((1, (64, 128, 192, 288)), (2, (48, 96, 144, 208, 272)))
+
+
+def candidates(batched: bool):
+    """Every (K, U, form) the tuner tries for one size class."""
+    out = [(k, u, FORM_BROADCAST) for k in ROWS for u in CHUNKS]
+    if batched:
+        out += [(k, u, FORM_STEPPING) for k, us in STEP_SHAPES for u in us]
+    return out
 KIND_NAMES = {KIND_COUNT_I32: "count_i32", KIND_COUNT_F32: "count_f32",
               KIND_ENERGY_F32: "energy_f32"}
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_shapes.json")
@@ -62,24 +72,28 @@ def time_batched(kind, table, offsets, inputs, outputs, eps2=1e-4, reps=3) -> fl
         plan.close()
 
 
+def _entry(e):
+    e = tuple(int(v) for v in e)
+    return e if len(e) == 4 else e + (FORM_BROADCAST,)
+
+
 def tune_batched(kind, offsets, inputs, outputs, eps2=1e-4, start=None, rounds=1, log=print):
-    """Coordinate descent over the (K, U) of each size class of a batch,
+    """Coordinate descent over the (K, U, form) of each size class of a batch,
     largest class first; the class boundaries of `start` stay fixed."""
-    table = [tuple(e) for e in (start or pairs_get_shapes(kind, True))]
+    table = [_entry(e) for e in (start or pairs_get_shapes(kind, True))]
     best = time_batched(kind, table, offsets, inputs, outputs, eps2)
     log(f"start {table}: {best:.3f} ms")
     for _ in range(rounds):
         for c in range(len(table)):
-            for k in ROWS:
-                for u in CHUNKS:
-                    if (k, u) == table[c][1:]:
-                        continue
-                    cand = list(table)
-                    cand[c] = (table[c][0], k, u)
-                    ms = time_batched(kind, cand, offsets, inputs, outputs, eps2)
-                    if ms < best:
-                        best, table = ms, cand
-                        log(f"  class {c} -> K={k} U={u}: {ms:.3f} ms")
+            for k, u, form in candidates(True):
+                if (k, u, form) == table[c][1:]:
+                    continue
+                cand = list(table)
+                cand[c] = (table[c][0], k, u, form)
+                ms = time_batched(kind, cand, offsets, inputs, outputs, eps2)
+                if ms < best:
+                    best, table = ms, cand
+                    log(f"  class {c} -> K={k} U={u} form={form}: {ms:.3f} ms")
     pairs_set_shapes(kind, True, table)
     return table, best
 
@@ -122,7 +136,7 @@ def load_cache(path=None, apply=True):
             if d_arch != a:
                 continue
             kind = {v: k for k, v in KIND_NAMES.items()}[kind_name]
-            pairs_set_shapes(kind, mode == "batched", [tuple(e) for e in entry["table"]])
+            pairs_set_shapes(kind, mode == "batched", [_entry(e) for e in entry["table"]])
     return data
 
 

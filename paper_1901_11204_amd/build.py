@@ -28,6 +28,9 @@ def build_cmd(out: str, extra=(), sources=None):
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             # hardware float atomics; IEEE semantics without contraction
             "-munsafe-fp-atomics", "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero",
+            # the SLP vectorizer packs per-pair predicate bits into vectors in
+            # the unrolled sweeps, which costs VALU instructions on gfx950
+            "-fno-slp-vectorize",
             "-I", INCLUDE, "-I", CSRC, *extra, "-o", out, *(sources or SOURCES)]
 
 

@@ -84,3 +84,47 @@ PAIRS_HD void task_range(const Band &b, const Tiling &t, int block, int c, int *
     *u0 = lo;
     *u1 = hi < uend ? hi : uend;
 }
+
+// Row-stepping decomposition (the paper's own form: row i visits partners
+// (i + s) mod n for s = 1, 2, ...).  A stepping task holds K consecutive rows
+// per lane, rows [r0, r0 + 64K), and runs the steps [s0, s0 + T) for all its
+// rows, plus, when x is set, the extra step s0 + T (= n/2) for the rows below
+// n/2 of an even n.  Chunk c of a row block covers the steps
+// [1 + c*U, 1 + (c+1)*U) clipped to the set's last step.
+struct StepTiling {
+    int rows;     // 64*K
+    int chunk;    // U
+    int nblocks;  // row blocks
+    int nchunks;  // step chunks per row block
+
+    PAIRS_HD static StepTiling of(const Band &b, int K, int U) {
+        StepTiling t;
+        t.rows = 64 * K;
+        t.chunk = U;
+        if (b.n < 2) {
+            t.nblocks = 0;
+            t.nchunks = 0;
+            return t;
+        }
+        t.nblocks = (b.n + t.rows - 1) / t.rows;
+        const int smax = b.h + (b.half > 0 ? 1 : 0);  // largest step of any row
+        t.nchunks = (smax + U - 1) / U;
+        return t;
+    }
+    PAIRS_HD int64_t tasks() const { return (int64_t)nblocks * nchunks; }
+};
+
+// Steps of chunk c: [*s0, *s0 + *T) for every row of the block, plus the
+// extra step *s0 + *T for the rows below n/2 when *x is 1.
+PAIRS_HD void step_range(const Band &b, const StepTiling &t, int block, int c, int *r0, int *s0,
+                         int *T, int *x) {
+    *r0 = block * t.rows;
+    const int lo = 1 + c * t.chunk;
+    const int hi = lo + t.chunk;                     // exclusive
+    const int common_end = b.h + 1;                  // steps 1..h belong to every row
+    const bool has_extra = b.half > 0 && hi > common_end && lo <= common_end;
+    const int end = hi < common_end ? hi : common_end;
+    *s0 = lo;
+    *T = end > lo ? end - lo : 0;
+    *x = has_extra ? 1 : 0;
+}

@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <type_traits>
 #include <utility>
 #include <mutex>
@@ -28,6 +29,7 @@
 #include "band.h"
 #include "device.h"
 #include "pairs.h"
+#include "steps.h"
 #include "tasks.h"
 
 using namespace pairs_dev;
@@ -53,6 +55,7 @@ struct ClassTable {
     int lo[kMaxClasses];
     int K[kMaxClasses];
     int U[kMaxClasses];
+    int form[kMaxClasses];  // PAIRS_FORM_*
 
     __host__ __device__ int class_of(int n) const {
         for (int c = 0; c < count - 1; ++c)
@@ -60,17 +63,20 @@ struct ClassTable {
         return count - 1;
     }
     __host__ __device__ int64_t tasks(int n, int c) const {
+        if (form[c] == PAIRS_FORM_STEPPING)
+            return StepTiling::of(Band::of(n), K[c], U[c]).tasks();
         return Tiling::of(Band::of(n), K[c], U[c]).tasks();
     }
 };
 
-ClassTable make_table(int count, const int *lo, const int *K, const int *U) {
+ClassTable make_table(int count, const int *lo, const int *K, const int *U, const int *form) {
     ClassTable t;
     t.count = count;
     for (int c = 0; c < kMaxClasses; ++c) {
         t.lo[c] = c < count ? lo[c] : 0;
         t.K[c] = c < count ? K[c] : 1;
         t.U[c] = c < count ? U[c] : 64;
+        t.form[c] = c < count && form ? form[c] : PAIRS_FORM_BROADCAST;
     }
     return t;
 }
@@ -78,17 +84,28 @@ ClassTable make_table(int count, const int *lo, const int *K, const int *U) {
 // Default tile shapes by kind (index kind - 1) for single sets and batches.
 ClassTable default_table(int kind, bool batched) {
     if (batched) {
-        const int lo[4] = {4096, 1024, 256, 0}, K[4] = {8, 4, 2, 1},
-                  U[4] = {2048, 1024, 512, 256};
-        return make_table(4, lo, K, U);
+        const int lo[4] = {4096, 1024, 256, 0}, K[4] = {2, 2, 2, 2},
+                  U[4] = {272, 272, 272, 272},
+                  form[4] = {PAIRS_FORM_STEPPING, PAIRS_FORM_STEPPING, PAIRS_FORM_STEPPING,
+                             PAIRS_FORM_STEPPING};
+        return make_table(4, lo, K, U, form);
     }
     if (kind == PAIRS_KIND_ENERGY_F32) {
         const int lo[3] = {65536, 8192, 0}, K[3] = {4, 4, 1}, U[3] = {1024, 1024, 256};
-        return make_table(3, lo, K, U);
+        return make_table(3, lo, K, U, nullptr);
     }
     const int lo[3] = {65536, 8192, 0}, K[3] = {8, 4, 1}, U[3] = {1024, 1024, 256};
-    return make_table(3, lo, K, U);
+    return make_table(3, lo, K, U, nullptr);
 }
+
+// Largest step chunk of a stepping task with K rows per lane: a row block's
+// window (64 K + chunk + K records) must fit the wave's window capacity.
+__host__ __device__ constexpr int step_max_chunk(int K) { return K == 1 ? 288 : 272; }
+// (a chunk of U steps has T + x <= U: the extra step only joins a short chunk)
+static_assert(1 * step_window_entries(1, 64, 287, 1) <= kStepCap, "K=1 window fits");
+static_assert(2 * step_window_entries(2, 64, 271, 1) <= kStepCap, "K=2 window fits");
+static_assert(step_window_entries(1, 64, 287, 1) <= 64 * step_iters<1>(), "K=1 staging slots");
+static_assert(step_window_entries(2, 64, 271, 1) <= 64 * step_iters<2>(), "K=2 staging slots");
 
 std::mutex g_shape_mutex;
 ClassTable g_shapes[3][2];
@@ -100,12 +117,19 @@ ClassTable shapes(int kind, bool batched) {
                                            : default_table(kind, batched);
 }
 
-bool valid_table(const ClassTable &t) {
+bool valid_table(const ClassTable &t, bool batched) {
     if (t.count < 1 || t.count > kMaxClasses) return false;
     for (int c = 0; c < t.count; ++c) {
-        if (t.K[c] != 1 && t.K[c] != 2 && t.K[c] != 4 && t.K[c] != 8) return false;
-        if (t.U[c] < 64 || t.U[c] % 64 != 0 || t.U[c] > (1 << 24)) return false;
         if (t.lo[c] < 0 || (c > 0 && t.lo[c] >= t.lo[c - 1])) return false;
+        if (t.form[c] == PAIRS_FORM_STEPPING) {
+            if (!batched || (t.K[c] != 1 && t.K[c] != 2)) return false;
+            if (t.U[c] < 16 || t.U[c] % 16 != 0 || t.U[c] > step_max_chunk(t.K[c])) return false;
+        } else if (t.form[c] == PAIRS_FORM_BROADCAST) {
+            if (t.K[c] != 1 && t.K[c] != 2 && t.K[c] != 4 && t.K[c] != 8) return false;
+            if (t.U[c] < 64 || t.U[c] % 64 != 0 || t.U[c] > (1 << 24)) return false;
+        } else {
+            return false;
+        }
     }
     return true;
 }
@@ -236,16 +260,24 @@ __global__ __launch_bounds__(kBlock) void k_energy(const float *__restrict__ x,
 
 // ---------------------------------------------------------- batched kernels --
 
-// One wave task of a plan, resolved on the host: set s (objects
-// [base, base + n)), rows [ra, ra + 64K), virtual partners [u0, u1).
+// One wave task of a plan, resolved on the host.
+//   broadcast form: set `set` (objects [base, base + n)), rows [a, a + 64K),
+//     virtual partners [b, c);
+//   stepping form, one row block: set `set` at base, rows [a, a + 64K), steps
+//     [b, b + c) plus the extra step b + c when x is 1;
+//   stepping form, a pack (set < 0): m whole sets of size n whose bases and
+//     ids are the plan's pack entries [base, base + m); steps [b, b + c) and x.
 struct TaskDesc {
     int64_t base;
     int32_t set;
     int32_t n;
-    int32_t ra;
-    int32_t u0;
-    int32_t u1;
-    int32_t K;
+    int32_t a;
+    int32_t b;
+    int32_t c;
+    uint8_t K;
+    uint8_t form;
+    uint8_t m;
+    uint8_t x;
 };
 static_assert(sizeof(TaskDesc) == 32, "one 32-byte scalar load per task");
 
@@ -328,9 +360,18 @@ __global__ __launch_bounds__(kSchedThreads) void k_batch_schedule(
 
 enum Kind { kCountI32 = 1, kCountF32 = 2, kEnergyF32 = 3 };
 
-// LDS of one wave, in bytes, for every kind.
-constexpr int kLdsBytes = (kCountI32Lds * 8 > kEnergyLds * 4 ? kCountI32Lds * 8 : kEnergyLds * 4);
-static_assert(kLdsBytes % 16 == 0, "LDS windows keep 16-byte alignment");
+// LDS of one wave of the batched kernels, in bytes, for each kind: the larger
+// of the broadcast window and the stepping window.
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+template <int KindV>
+constexpr int batched_lds_bytes() {
+    return KindV == kCountI32 ? cmax(kCountI32Lds * 8, kStepCap * 24)
+           : KindV == kCountF32 ? cmax(kCountF32Lds * 4, kStepCap * 16)
+                                : cmax(kEnergyLds * 4, kStepCap * 16);
+}
+static_assert(batched_lds_bytes<kCountI32>() % 16 == 0 && batched_lds_bytes<kCountF32>() % 16 == 0 &&
+                  batched_lds_bytes<kEnergyF32>() % 16 == 0,
+              "LDS windows keep 16-byte alignment");
 
 struct BatchIO {
     const void *x, *y, *z, *r;  // object arrays (r may be null for energies)
@@ -339,6 +380,8 @@ struct BatchIO {
     uint64_t *counts;  // [n_sets] or null
     double *energy;    // [n_sets] (energies)
     float eps2;
+    const int64_t *pack_base;  // plans: first object of each packed set
+    const int32_t *pack_set;   // plans: id of each packed set
 };
 
 // Object type of a kind.
@@ -406,6 +449,117 @@ __device__ __forceinline__ void run_shape(const BatchIO &io, int64_t base, const
     batched_task<K, K, KindV>(io, base, band, ra, u0, u1, set, win, in);
 }
 
+// Per-lane view of a stepping task's sets: the first object of the lane's
+// own segment, and (packs) the set whose totals lane j < m reports.
+struct StepSets {
+    int64_t base;
+    int64_t out_set;
+};
+
+__device__ __forceinline__ StepSets step_sets(const BatchIO &io, const TaskDesc &d) {
+    StepSets s;
+    if (d.set >= 0) {
+        s.base = d.base;
+        s.out_set = d.set;
+        return s;
+    }
+    const int lane = lane_id();
+    const int w = (d.n + d.K - 1) / d.K;
+    const int j = lane / w < d.m ? lane / w : 0;
+    s.base = io.pack_base[d.base + j];
+    s.out_set = lane < d.m ? (int64_t)io.pack_set[d.base + lane] : 0;
+    return s;
+}
+
+__device__ __forceinline__ StepGeom desc_geom(const TaskDesc &d) {
+    return step_geom(d.n, d.K, d.a, d.b, d.c, d.x, d.m, d.set < 0);
+}
+
+// Issues the loads of a stepping task's raw inputs.
+template <int KindV>
+__device__ __forceinline__ StepRaw<ObjT<KindV>> step_load_task(const BatchIO &io,
+                                                               const TaskDesc &d,
+                                                               const StepSets &ss) {
+    using T = ObjT<KindV>;
+    const StepGeom g = desc_geom(d);
+    const StepLane p = step_lane(g);
+    const T *X = (const T *)io.x, *Y = (const T *)io.y, *Z = (const T *)io.z,
+            *R = (const T *)io.r;
+    if (d.K == 2)
+        return R ? step_load<T, 2, true>(X, Y, Z, R, ss.base, g, p)
+                 : step_load<T, 2, false>(X, Y, Z, R, ss.base, g, p);
+    return R ? step_load<T, 1, true>(X, Y, Z, R, ss.base, g, p)
+             : step_load<T, 1, false>(X, Y, Z, R, ss.base, g, p);
+}
+
+// Stages and sweeps one stepping task whose raw inputs are loaded, and adds
+// its totals to the outputs.  A single segment (a row block of one set)
+// reports one total per wave; a pack sums per set over its segments.  hook()
+// runs between staging and the sweep.
+template <int K, int KindV, bool Pack, typename Hook>
+__device__ __forceinline__ void step_run(const BatchIO &io, const StepGeom &g, const StepSets &ss,
+                                         const StepRaw<ObjT<KindV>> &raw, void *win, Hook &&hook) {
+    const int lane = lane_id();
+    if constexpr (KindV == kCountI32 || KindV == kCountF32) {
+        StepCountResult r;
+        if constexpr (KindV == kCountI32)
+            r = step_count_i32<K, Pack>(raw, g, win, hook);
+        else
+            r = step_count_f32<K, Pack>(raw, g, win, hook);
+        if (Pack) {
+            const uint32_t c = segment_sum(r.lane, g, win);
+            if (lane < g.m && c)
+                atomicAdd((unsigned long long *)&io.counts[ss.out_set], (unsigned long long)c);
+        } else if (lane == 0 && r.wave) {
+            atomicAdd((unsigned long long *)&io.counts[ss.out_set], (unsigned long long)r.wave);
+        }
+    } else {
+        StepEnergyResult r;
+        if (io.r)
+            r = step_energy<K, Pack, true>(raw, g, io.eps2, win, hook);
+        else
+            r = step_energy<K, Pack, false>(raw, g, io.eps2, win, hook);
+        if (Pack) {
+            const double e = segment_sum(r.lane_energy, g, win);
+            const uint32_t c = io.r ? segment_sum(r.lane, g, win) : 0u;
+            if (lane < g.m) {
+                atomicAdd(&io.energy[ss.out_set], e);
+                if (c)
+                    atomicAdd((unsigned long long *)&io.counts[ss.out_set],
+                              (unsigned long long)c);
+            }
+        } else {
+            const double e = wave_sum(r.lane_energy);
+            if (lane == 0) {
+                atomicAdd(&io.energy[ss.out_set], e);
+                if (io.r && r.wave)
+                    atomicAdd((unsigned long long *)&io.counts[ss.out_set],
+                              (unsigned long long)r.wave);
+            }
+        }
+    }
+}
+
+template <int KindV, typename Hook>
+__device__ __forceinline__ void step_run_task(const BatchIO &io, const TaskDesc &d,
+                                              const StepSets &ss,
+                                              const StepRaw<ObjT<KindV>> &raw, void *win,
+                                              Hook &&hook) {
+    const StepGeom g = desc_geom(d);
+    const bool pack = d.set < 0;
+    if (d.K == 2) {
+        if (pack)
+            step_run<2, KindV, true>(io, g, ss, raw, win, hook);
+        else
+            step_run<2, KindV, false>(io, g, ss, raw, win, hook);
+    } else {
+        if (pack)
+            step_run<1, KindV, true>(io, g, ss, raw, win, hook);
+        else
+            step_run<1, KindV, false>(io, g, ss, raw, win, hook);
+    }
+}
+
 // Runs one task with the compiled shape K (only shapes up to KMAX are compiled
 // into a kernel, which keeps its register count, and so its occupancy, to
 // what the largest shape it serves needs).
@@ -425,11 +579,20 @@ __device__ __forceinline__ void run_task(const BatchIO &io, int64_t base, const 
 // Plans: wave w runs the tasks descs[wave_start[w] .. wave_start[w+1]), a list
 // balanced across the waves on the host; the next descriptor is fetched while
 // the current task runs.
+// Waves per SIMD the batched kernels are compiled for: four where the
+// largest compiled shape allows it without register spills (the stepping
+// sweeps hide their per-task load latency behind the other waves).
 template <int KindV, int KMAX>
-__global__ __launch_bounds__(kBlock) void k_batched_plan(BatchIO io,
+constexpr int batched_min_waves() {
+    return (KMAX <= 2 || (KindV == kEnergyF32 && KMAX <= 4)) ? 4 : 1;
+}
+
+template <int KindV, int KMAX>
+__global__ __launch_bounds__(kBlock, (batched_min_waves<KindV, KMAX>())) void k_batched_plan(BatchIO io,
                                                          const TaskDesc *__restrict__ descs,
                                                          const int32_t *__restrict__ wave_start,
                                                          int64_t n_waves) {
+    constexpr int kLdsBytes = batched_lds_bytes<KindV>();
     __shared__ __align__(16) unsigned char lds[kWavesPerBlock * kLdsBytes];
     const int wave = wave_id();
     void *win = lds + wave * kLdsBytes;
@@ -442,16 +605,23 @@ __global__ __launch_bounds__(kBlock) void k_batched_plan(BatchIO io,
     for (; i < e; ++i) {
         const TaskDesc d = next;
         if (i + 1 < e) next = descs[i + 1];
-        const Band band = Band::of(d.n);
-        run_task<KindV, KMAX>(io, d.base, band, d.ra, d.u0, d.u1, d.set, d.K, win);
+        if (d.form == PAIRS_FORM_STEPPING) {
+            const StepSets ss = step_sets(io, d);
+            const StepRaw<ObjT<KindV>> raw = step_load_task<KindV>(io, d, ss);
+            step_run_task<KindV>(io, d, ss, raw, win, []() PAIRS_INLINE {});
+        } else {
+            const Band band = Band::of(d.n);
+            run_task<KindV, KMAX>(io, d.base, band, d.a, d.b, d.c, d.set, d.K, win);
+        }
     }
 }
 
 // Unplanned calls: tasks decoded from the device-built prefix sums, taken by
 // the waves with a grid stride.
 template <int KindV, int KMAX>
-__global__ __launch_bounds__(kBlock) void k_batched_scan(BatchIO io, ScanSource src,
+__global__ __launch_bounds__(kBlock, (batched_min_waves<KindV, KMAX>())) void k_batched_scan(BatchIO io, ScanSource src,
                                                          ClassTable ct) {
+    constexpr int kLdsBytes = batched_lds_bytes<KindV>();
     __shared__ __align__(16) unsigned char lds[kWavesPerBlock * kLdsBytes];
     const int wave = wave_id();
     void *win = lds + wave * kLdsBytes;
@@ -467,6 +637,28 @@ __global__ __launch_bounds__(kBlock) void k_batched_scan(BatchIO io, ScanSource 
         if (n < 2) continue;
         const int c = ct.class_of(n);
         const Band band = Band::of(n);
+        if (ct.form[c] == PAIRS_FORM_STEPPING) {
+            const StepTiling til = StepTiling::of(band, ct.K[c], ct.U[c]);
+            if (local < 0 || (int64_t)local >= til.tasks()) continue;
+            int r0, s0, T, x;
+            step_range(band, til, local / til.nchunks, local % til.nchunks, &r0, &s0, &T, &x);
+            if (T + x == 0) continue;
+            TaskDesc d{};
+            d.base = base;
+            d.set = (int32_t)set;
+            d.n = n;
+            d.a = r0;
+            d.b = s0;
+            d.c = T;
+            d.K = (uint8_t)ct.K[c];
+            d.form = PAIRS_FORM_STEPPING;
+            d.m = 1;
+            d.x = (uint8_t)x;
+            const StepSets ss{base, set};
+            const StepRaw<ObjT<KindV>> raw = step_load_task<KindV>(io, d, ss);
+            step_run_task<KindV>(io, d, ss, raw, win, []() PAIRS_INLINE {});
+            continue;
+        }
         const Tiling til = Tiling::of(band, ct.K[c], ct.U[c]);
         if (local < 0 || (int64_t)local >= til.tasks()) continue;
         int ra, u0, u1;
@@ -805,6 +997,9 @@ struct pairs_plan_s {
     int64_t *d_offsets;
     TaskDesc *d_descs;      // wave-major task descriptors
     int32_t *d_wave_start;  // [n_waves + 1]
+    int64_t n_packed;       // sets placed in packs
+    int64_t *d_pack_base;   // [n_packed] first object of each packed set
+    int32_t *d_pack_set;    // [n_packed] its set id
 };
 
 struct pairs_graph_s {
@@ -982,29 +1177,82 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
     int64_t n_waves = 0;
     with_plan_kernel(kk, kmax, [&](auto kern) { n_waves = resident_blocks(st, kern) * kWavesPerBlock; });
 
-    // every task with its cost in VALU issue slots (per 64-partner group: 5
-    // instructions per row slice in a row block's core, 7 at the band edges)
+    // every task with its cost in VALU issue slots.  Broadcast tasks: per
+    // 64-partner group 5 instructions per row slice in a row block's core, 7
+    // at the band edges.  Stepping tasks: about 6 per row and step, plus the
+    // staging of the window.
     std::vector<TaskDesc> tasks;
     std::vector<int64_t> cost;
+    std::vector<int64_t> pack_base;
+    std::vector<int32_t> pack_set;
+    // small sets of stepping classes, grouped by (n, K) for packing
+    std::map<std::pair<int, int>, std::vector<int64_t>> packable;
+    auto add = [&](const TaskDesc &d, int64_t w) -> bool {
+        try {
+            tasks.push_back(d);
+            cost.push_back(w);
+        } catch (const std::bad_alloc &) {
+            return false;
+        }
+        return true;
+    };
+    auto step_cost = [](int K, int T, int x, int S, int w) -> int64_t {
+        return 400 + (int64_t)(T + x + K) * K * 6 + (int64_t)K * ((S + w - 1) / w) * 40;
+    };
     for (int64_t s = 0; s < n_sets; ++s) {
         const int n = (int)(h_offsets[s + 1] - h_offsets[s]);
         if (n < 2) continue;
         const int c = ct.class_of(n);
         const Band band = Band::of(n);
+        if (ct.form[c] == PAIRS_FORM_STEPPING) {
+            const int K = ct.K[c];
+            if ((n + K - 1) / K <= kWave) {
+                const int Kp = n < 4 * K ? 1 : K;  // tiny sets: one row per lane
+                try {
+                    packable[std::make_pair(n, Kp)].push_back(s);
+                } catch (const std::bad_alloc &) {
+                    return PAIRS_ERR_NO_MEMORY;
+                }
+                continue;
+            }
+            const StepTiling til = StepTiling::of(band, K, ct.U[c]);
+            for (int b = 0; b < til.nblocks; ++b)
+                for (int ch = 0; ch < til.nchunks; ++ch) {
+                    int r0, s0, T, x;
+                    step_range(band, til, b, ch, &r0, &s0, &T, &x);
+                    if (T + x == 0) continue;
+                    TaskDesc d{};
+                    d.base = h_offsets[s];
+                    d.set = (int32_t)s;
+                    d.n = n;
+                    d.a = r0;
+                    d.b = s0;
+                    d.c = T;
+                    d.K = (uint8_t)K;
+                    d.form = PAIRS_FORM_STEPPING;
+                    d.m = 1;
+                    d.x = (uint8_t)x;
+                    if (!add(d, step_cost(K, T, x, step_window_entries(K, kWave, T, x), kWave)))
+                        return PAIRS_ERR_NO_MEMORY;
+                }
+            continue;
+        }
         const Tiling til = Tiling::of(band, ct.K[c], ct.U[c]);
         for (int b = 0; b < til.nblocks; ++b)
             for (int ch = 0; ch < til.nchunks; ++ch) {
                 int ra, u0, u1;
                 task_range(band, til, b, ch, &ra, &u0, &u1);
                 if (u0 >= u1) continue;
-                TaskDesc d;
+                TaskDesc d{};
                 d.base = h_offsets[s];
                 d.set = (int32_t)s;
                 d.n = n;
-                d.ra = ra;
-                d.u0 = u0;
-                d.u1 = u1;
-                d.K = ct.K[c];
+                d.a = ra;
+                d.b = u0;
+                d.c = u1;
+                d.K = (uint8_t)ct.K[c];
+                d.form = PAIRS_FORM_BROADCAST;
+                d.m = 1;
                 const int rlast = std::min(ra + 64 * d.K, n) - 1;
                 const int core_lo = rlast + 1, core_hi = ra + band.steps(ra);
                 int64_t w = 600;
@@ -1013,13 +1261,41 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
                     const bool full = g0 >= core_lo && g0 + gn - 1 <= core_hi;
                     w += 40 + (full ? 64 * 5 : gn * 7) * (int64_t)d.K;
                 }
-                try {
-                    tasks.push_back(d);
-                    cost.push_back(w);
-                } catch (const std::bad_alloc &) {
-                    return PAIRS_ERR_NO_MEMORY;
-                }
+                if (!add(d, w)) return PAIRS_ERR_NO_MEMORY;
             }
+    }
+    // packs: whole sets of one size, as many per wave as lanes and window allow
+    for (const auto &kv : packable) {
+        const int n = kv.first.first, K = kv.first.second;
+        const Band band = Band::of(n);
+        const int w = (n + K - 1) / K;
+        const int T = band.h, x = band.half > 0 ? 1 : 0;
+        const int S = step_window_entries(K, w, T, x);
+        const int mmax = std::max(1, std::min(kWave / w, kStepCap / (K * S)));
+        const std::vector<int64_t> &sets = kv.second;
+        for (size_t i0 = 0; i0 < sets.size(); i0 += (size_t)mmax) {
+            const int m = (int)std::min<size_t>((size_t)mmax, sets.size() - i0);
+            TaskDesc d{};
+            d.base = (int64_t)pack_base.size();
+            d.set = -1;
+            d.n = n;
+            d.a = 0;
+            d.b = 1;
+            d.c = T;
+            d.K = (uint8_t)K;
+            d.form = PAIRS_FORM_STEPPING;
+            d.m = (uint8_t)m;
+            d.x = (uint8_t)x;
+            try {
+                for (int j = 0; j < m; ++j) {
+                    pack_base.push_back(h_offsets[sets[i0 + (size_t)j]]);
+                    pack_set.push_back((int32_t)sets[i0 + (size_t)j]);
+                }
+            } catch (const std::bad_alloc &) {
+                return PAIRS_ERR_NO_MEMORY;
+            }
+            if (!add(d, step_cost(K, T, x, S, w) + 40 * (int64_t)m)) return PAIRS_ERR_NO_MEMORY;
+        }
     }
     const int64_t ntasks = (int64_t)tasks.size();
     if (ntasks >= INT32_MAX) return PAIRS_ERR_INVALID_ARG;
@@ -1074,7 +1350,20 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
     p->d_offsets = nullptr;
     p->d_descs = nullptr;
     p->d_wave_start = nullptr;
+    p->n_packed = (int64_t)pack_base.size();
+    p->d_pack_base = nullptr;
+    p->d_pack_set = nullptr;
     hipError_t e = hipMalloc(&p->d_offsets, sizeof(int64_t) * (size_t)(n_sets + 1));
+    if (e == hipSuccess && p->n_packed > 0)
+        e = hipMalloc(&p->d_pack_base, sizeof(int64_t) * (size_t)p->n_packed);
+    if (e == hipSuccess && p->n_packed > 0)
+        e = hipMalloc(&p->d_pack_set, sizeof(int32_t) * (size_t)p->n_packed);
+    if (e == hipSuccess && p->n_packed > 0)
+        e = hipMemcpy(p->d_pack_base, pack_base.data(), sizeof(int64_t) * (size_t)p->n_packed,
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && p->n_packed > 0)
+        e = hipMemcpy(p->d_pack_set, pack_set.data(), sizeof(int32_t) * (size_t)p->n_packed,
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMalloc(&p->d_wave_start, sizeof(int32_t) * (size_t)(n_waves + 1));
     if (e == hipSuccess && ntasks > 0)
@@ -1092,6 +1381,8 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
         if (p->d_offsets) (void)hipFree(p->d_offsets);
         if (p->d_wave_start) (void)hipFree(p->d_wave_start);
         if (p->d_descs) (void)hipFree(p->d_descs);
+        if (p->d_pack_base) (void)hipFree(p->d_pack_base);
+        if (p->d_pack_set) (void)hipFree(p->d_pack_set);
         delete p;
         g_last_hip_error = e;
         return e == hipErrorOutOfMemory ? PAIRS_ERR_NO_MEMORY : PAIRS_ERR_HIP;
@@ -1123,6 +1414,8 @@ pairs_status_t pairs_plan_execute(pairs_plan_t plan, const void *const *in, void
     io.r = in[3];
     io.off = plan->d_offsets;
     io.n_total = plan->n_total;
+    io.pack_base = plan->d_pack_base;
+    io.pack_set = plan->d_pack_set;
     if (plan->n_total > 0 && (!io.x || !io.y || !io.z)) return PAIRS_ERR_INVALID_ARG;
     if (plan->kind == PAIRS_KIND_ENERGY_F32) {
         if (!(eps2 > 0.0f) || !isfinite(eps2)) return PAIRS_ERR_INVALID_ARG;
@@ -1160,6 +1453,8 @@ pairs_status_t pairs_plan_destroy(pairs_plan_t plan) {
     if (plan->d_offsets) (void)hipFree(plan->d_offsets);
     if (plan->d_descs) (void)hipFree(plan->d_descs);
     if (plan->d_wave_start) (void)hipFree(plan->d_wave_start);
+    if (plan->d_pack_base) (void)hipFree(plan->d_pack_base);
+    if (plan->d_pack_set) (void)hipFree(plan->d_pack_set);
     (void)hipSetDevice(cur);
     delete plan;
     return PAIRS_OK;
@@ -1261,6 +1556,7 @@ pairs_status_t pairs_get_shapes(int kind, int batched, pairs_shape_table_t *out)
         out->min_n[c] = t.lo[c];
         out->rows_per_lane[c] = t.K[c];
         out->chunk[c] = t.U[c];
+        out->form[c] = t.form[c];
     }
     return PAIRS_OK;
 }
@@ -1273,8 +1569,9 @@ pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t
         return PAIRS_OK;
     }
     if (table->count < 1 || table->count > kMaxClasses) return PAIRS_ERR_INVALID_ARG;
-    ClassTable t = make_table(table->count, table->min_n, table->rows_per_lane, table->chunk);
-    if (!valid_table(t)) return PAIRS_ERR_INVALID_ARG;
+    ClassTable t = make_table(table->count, table->min_n, table->rows_per_lane, table->chunk,
+                              table->form);
+    if (!valid_table(t, batched != 0)) return PAIRS_ERR_INVALID_ARG;
     g_shapes[kind - 1][batched != 0] = t;
     g_shapes_set[kind - 1][batched != 0] = true;
     return PAIRS_OK;
@@ -1319,3 +1616,25 @@ const char *pairs_status_string(pairs_status_t s) {
 int pairs_last_hip_error(void) { return (int)g_last_hip_error; }
 
 }  // extern "C"
+
+pairs_status_t pairs_debug_step_ranges(int n, int rows_per_lane, int chunk, int32_t *out,
+                                       int64_t capacity, int64_t *n_tasks) {
+    if (n < 0 || !n_tasks || (rows_per_lane != 1 && rows_per_lane != 2) || chunk <= 0)
+        return PAIRS_ERR_INVALID_ARG;
+    const Band band = Band::of(n);
+    const StepTiling til = StepTiling::of(band, rows_per_lane, chunk);
+    *n_tasks = til.tasks();
+    if (!out) return PAIRS_OK;
+    if (capacity < til.tasks()) return PAIRS_ERR_WORKSPACE;
+    int64_t k = 0;
+    for (int b = 0; b < til.nblocks; ++b)
+        for (int c = 0; c < til.nchunks; ++c, ++k) {
+            int r0, s0, T, x;
+            step_range(band, til, b, c, &r0, &s0, &T, &x);
+            out[4 * k] = r0;
+            out[4 * k + 1] = s0;
+            out[4 * k + 2] = T;
+            out[4 * k + 3] = x;
+        }
+    return PAIRS_OK;
+}

@@ -5,6 +5,11 @@
 // The host times each kernel with HIP events; lane-operations per second
 // against 256 CUs x 64 lanes x clock gives the issue cost of the pattern.
 // Used to measure the per-pair cost of the predicates (not on the hot path).
+//
+// The LDS probes time wave-wide reads of 8 or 16 bytes per lane, every lane
+// at one address (a broadcast) or at consecutive addresses (a gather), with
+// one three-input add per 8 bytes to consume the data; their "lane
+// operations" are lane reads.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -93,12 +98,47 @@ __global__ void p_mad_u64_u32(unsigned long long *out, unsigned a) {
     if (s == 12345ull) out[threadIdx.x] = s;
 }
 
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+constexpr int kLdsWords = 8192;  // 32 KB per block
+constexpr int kLdsIters = 2048;  // 8 reads each
+
+// Mode: 0 broadcast b128, 1 gather b128, 2 broadcast b64, 3 gather b64.
+// Largest byte offset read: 63 * 16 + 7 * 2048 + 7 * 256 + 16 < 32 KB.
+template <int Mode>
+__global__ __launch_bounds__(256) void p_lds_read(uint32_t *out) {
+    __shared__ __align__(16) uint32_t buf[kLdsWords];
+    for (int i = threadIdx.x; i < kLdsWords; i += 256) buf[i] = i * 2654435761u;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int lane_off = Mode == 1 ? lane * 16 : Mode == 3 ? lane * 8 : 0;
+    const char *b = (const char *)buf;
+    uint32_t acc = 0;
+    for (int it = 0; it < kLdsIters; ++it) {
+        const char *p = b + lane_off + (it & 7) * 2048;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (Mode <= 1) {
+                const u4 v = *(const u4 *)(p + k * 256);
+                acc = acc + v.x + v.y;  // v_add3_u32
+                acc = acc + v.z + v.w;
+            } else {
+                const u2 v = *(const u2 *)(p + k * 256);
+                acc = acc + v.x + v.y;
+            }
+        }
+    }
+    if (acc == 0x12345678u) out[threadIdx.x] = acc;
+}
+
 }  // namespace
 
 extern "C" {
 
 // Probe names in order; pattern instruction counts per chain step.
-const char *valu_probe_names = "fma_f64,fma_f32,rsq_f32,fma3_rsq_f32,count_f64,mad_u64_u32";
+const char *valu_probe_names =
+    "fma_f64,fma_f32,rsq_f32,fma3_rsq_f32,count_f64,mad_u64_u32,"
+    "lds_bcast_b128,lds_gather_b128,lds_bcast_b64,lds_gather_b64";
 
 // Runs probe `which` once (after one warm-up) on blocks x 256 threads and
 // returns its duration in milliseconds in *ms and the number of lane
@@ -121,6 +161,10 @@ int valu_probe_run(int which, int blocks, double *ms, double *lane_ops) {
             case 3: p_fma3_rsq<<<blocks, 256>>>((float *)buf, 0.999f, 1e-3f); per_lane = (kIters / 4) * kChains * 4; break;
             case 4: p_count_f64<<<blocks, 256>>>((unsigned *)buf, 0.999, 1e-3, 3.0); per_lane = (kIters / 5) * kChains * 5; break;
             case 5: p_mad_u64_u32<<<blocks, 256>>>((unsigned long long *)buf, 12345u); per_lane = kIters * kChains; break;
+            case 6: p_lds_read<0><<<blocks, 256>>>((uint32_t *)buf); per_lane = kLdsIters * 8; break;
+            case 7: p_lds_read<1><<<blocks, 256>>>((uint32_t *)buf); per_lane = kLdsIters * 8; break;
+            case 8: p_lds_read<2><<<blocks, 256>>>((uint32_t *)buf); per_lane = kLdsIters * 8; break;
+            case 9: p_lds_read<3><<<blocks, 256>>>((uint32_t *)buf); per_lane = kLdsIters * 8; break;
             default: (void)hipFree(buf); return (int)hipErrorInvalidValue;
         }
         (void)hipEventRecord(e1);

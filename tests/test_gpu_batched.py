@@ -282,3 +282,134 @@ def test_config5_full_graph_sampled():
                 oracle_steps(b, sets, {0, 1, 49, 99}, 6, 1e-3), b.n_sets)
     g.close()
     plan.close()
+
+
+# ------------------------------------------------------- every task form --
+#
+# Forced batched shape tables: the broadcast sweep, the row-stepping form
+# (row blocks and, in plans, packs of equal-size small sets) and a mix, on a
+# batch with many repeated small sizes (multi-set packs), ragged sizes and
+# dense collisions.
+
+B, S = P.FORM_BROADCAST, P.FORM_STEPPING
+FORM_TABLES = {
+    "bcast-1x256": [(0, 1, 256, B)],
+    "bcast-8x512": [(0, 8, 512, B)],
+    "step-1x16": [(0, 1, 16, S)],
+    "step-1x192": [(0, 1, 192, S)],
+    "step-1x288": [(0, 1, 288, S)],
+    "step-2x16": [(0, 2, 16, S)],
+    "step-2x48": [(0, 2, 48, S)],
+    "step-2x144": [(0, 2, 144, S)],
+    "step-2x272": [(0, 2, 272, S)],
+    "mixed": [(1000, 4, 1024, B), (100, 2, 144, S), (0, 1, 64, S)],
+}
+
+
+def form_batch(seed):
+    rng = np.random.default_rng(seed)
+    small = np.repeat(np.arange(0, 140), 3)                  # every small size, 3 times
+    ragged = rng.integers(140, 1200, 25)
+    sizes = np.concatenate([small, ragged, [2048, 1, 0, 2]]).astype(np.int64)
+    rng.shuffle(sizes)
+    return sizes, w.offsets_from_sizes(sizes)
+
+
+@pytest.fixture
+def forced_batched():
+    kinds = []
+
+    def set_(kind, table):
+        kinds.append(kind)
+        P.pairs_set_shapes(kind, True, table)
+    yield set_
+    for k in kinds:
+        P.pairs_set_shapes(k, True, None)
+
+
+@pytest.mark.parametrize("name", list(FORM_TABLES))
+@pytest.mark.parametrize("planned", [False, True])
+def test_batched_count_i32_every_form(forced_batched, name, planned):
+    forced_batched(P.KIND_COUNT_I32, FORM_TABLES[name])
+    sizes, off = form_batch(31)
+    s = w.spheres_i32(int(off[-1]), 32, 48, 4, radius_lo=0)
+    announce("batched count_i32 form", name, planned)
+    got = run_count_i32(*s.arrays(), off, planned)
+    want = oracle.count_i32_batched(*s.arrays(), off)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("name", ["bcast-1x256", "step-1x192", "step-2x48", "step-2x272",
+                                  "mixed"])
+@pytest.mark.parametrize("planned", [False, True])
+def test_batched_energy_count_every_form(forced_batched, name, planned):
+    T = torch()
+    forced_batched(P.KIND_ENERGY_F32, FORM_TABLES[name])
+    sizes, off = form_batch(33)
+    n = int(off[-1])
+    p = w.particles_f32(n, 34)
+    x, y, z = p.arrays()
+    x, y, z = x * 0.3, y * 0.3, z * 0.3                      # dense: many contacts
+    r = np.full(n, 0.02, np.float32)
+    tx = dev(x, y, z, r)
+    energy = T.empty(len(sizes), dtype=T.float64, device="cuda")
+    counts = T.empty(len(sizes), dtype=T.int64, device="cuda")
+    announce("batched energy+count form", name, planned)
+    if planned:
+        plan = P.Plan(P.KIND_ENERGY_F32, off)
+        plan.execute(tx, (energy, counts), eps2=float(EPS2))
+        T.cuda.synchronize()
+        plan.close()
+    else:
+        (toff,) = dev(off)
+        P.pairs_energy_f32_batched(*tx, toff, float(EPS2), energy, counts)
+    want_e, want_c = oracle.energy_count_f32_batched(x, y, z, r, off, EPS2)
+    np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint64), want_c)
+    got_e = energy.cpu().numpy()
+    nz = want_e > 0
+    assert np.all(got_e[~nz] == 0.0)
+    rel = np.abs(got_e[nz] - want_e[nz]) / want_e[nz]
+    assert rel.max() <= TOL_SET, rel.max()
+
+
+@pytest.mark.parametrize("name", ["step-1x16", "step-1x288", "step-2x272", "mixed"])
+def test_batched_count_f32_every_form(forced_batched, name):
+    T = torch()
+    forced_batched(P.KIND_COUNT_F32, FORM_TABLES[name])
+    sizes, off = form_batch(35)
+    n = int(off[-1])
+    p = w.particles_f32(n, 36)
+    x, y, z = (a * np.float32(0.25) for a in p.arrays())
+    r = np.full(n, 0.02, np.float32)
+    counts = T.empty(len(sizes), dtype=T.int64, device="cuda")
+    for planned in (False, True):
+        if planned:
+            plan = P.Plan(P.KIND_COUNT_F32, off)
+            plan.execute(dev(x, y, z, r), (counts,))
+            T.cuda.synchronize()
+            plan.close()
+        else:
+            (toff,) = dev(off)
+            P.pairs_count_f32_batched(*dev(x, y, z, r), toff, counts)
+        _, want = oracle.energy_count_f32_batched(x, y, z, r, off, EPS2)
+        np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint64), want)
+
+
+def test_energy_per_set_without_count_every_form(forced_batched):
+    T = torch()
+    for name in ("step-1x288", "step-2x272"):
+        forced_batched(P.KIND_ENERGY_F32, FORM_TABLES[name])
+        sizes, off = form_batch(37)
+        n = int(off[-1])
+        x, y, z = w.particles_f32(n, 38).arrays()
+        energy = T.empty(len(sizes), dtype=T.float64, device="cuda")
+        plan = P.Plan(P.KIND_ENERGY_F32, off)
+        tx = dev(x, y, z)
+        plan.execute((tx[0], tx[1], tx[2], None), (energy, None), eps2=float(EPS2))
+        T.cuda.synchronize()
+        plan.close()
+        want_e, _ = oracle.energy_count_f32_batched(x, y, z, np.zeros(n, np.float32), off, EPS2)
+        got = energy.cpu().numpy()
+        nz = want_e > 0
+        assert np.all(got[~nz] == 0.0)
+        assert (np.abs(got[nz] - want_e[nz]) / want_e[nz]).max() <= TOL_SET

@@ -62,3 +62,150 @@ def test_bad_shapes_rejected():
         P.pairs_debug_task_ranges(100, 1, 100)
     with pytest.raises(P.PairsError):
         P.pairs_debug_task_ranges(-1, 1, 64)
+
+
+# ----------------------------------------------------------- stepping form --
+#
+# pairs_debug_step_ranges lists the stepping-form tasks (the paper's per-row
+# form): rows [r0, r0 + 64K) run the steps [s0, s0 + T) and, when x is 1, the
+# rows below n/2 run the extra step s0 + T.
+
+def expand_steps(n, K, U):
+    tasks = P.pairs_debug_step_ranges(n, K, U)
+    seen = np.zeros((n, n), np.int32)
+    for r0, s0, T, x in tasks:
+        for i in range(r0, min(r0 + 64 * K, n)):
+            ss = list(range(s0, s0 + T))
+            if x and n % 2 == 0 and i < n // 2:
+                ss.append(s0 + T)
+            for s in ss:
+                j = (i + s) % n
+                a, b = (i, j) if i < j else (j, i)
+                seen[a, b] += 1
+    return tasks, seen
+
+
+@pytest.mark.parametrize("K,U", [(1, 16), (1, 192), (1, 288), (2, 16), (2, 48), (2, 144), (2, 272)])
+def test_step_tasks_cover_every_pair_once(K, U):
+    sizes = sorted(set([0, 1, 2, 3, 4, 5, 6, 7, 8, 31, 32, 33, 63, 64, 65, 127, 128, 129, 200,
+                        257, 289, 290, 511, 512, 513, 64 * K + 1, 1000, 1025]))
+    for n in sizes:
+        tasks, seen = expand_steps(n, K, U)
+        iu = np.triu_indices(n, 1)
+        assert np.all(seen[iu] == 1), (n, K, U)
+        assert seen.sum() == n * (n - 1) // 2
+        for r0, s0, T, x in tasks:
+            assert r0 % (64 * K) == 0 and r0 < n
+            assert s0 >= 1 and 0 <= T and T + x <= U and x in (0, 1)
+            assert s0 + T + x - 1 <= n // 2
+
+
+def test_step_shapes_rejected():
+    with pytest.raises(P.PairsError):
+        P.pairs_debug_step_ranges(100, 4, 64)
+    with pytest.raises(P.PairsError):
+        P.pairs_debug_step_ranges(100, 1, 0)
+    bad = [(0, 4, 64, P.FORM_STEPPING)]          # stepping takes 1 or 2 rows per lane
+    with pytest.raises(P.PairsError):
+        P.pairs_set_shapes(P.KIND_COUNT_I32, True, bad)
+    with pytest.raises(P.PairsError):         # chunk above the window capacity
+        P.pairs_set_shapes(P.KIND_COUNT_I32, True, [(0, 2, 288, P.FORM_STEPPING)])
+    with pytest.raises(P.PairsError):         # single-set tables are broadcast only
+        P.pairs_set_shapes(P.KIND_COUNT_I32, False, [(0, 1, 64, P.FORM_STEPPING)])
+    P.pairs_set_shapes(P.KIND_COUNT_I32, True, [(0, 1, 192, P.FORM_STEPPING)])
+    assert P.pairs_get_shapes(P.KIND_COUNT_I32, True) == [(0, 1, 192, P.FORM_STEPPING)]
+    P.pairs_set_shapes(P.KIND_COUNT_I32, True, None)
+
+
+# The window indexing of a stepping task, emulated lane by lane exactly as the
+# kernel computes it (segments of w lanes, K-interleaved window of S entries
+# per residue, sweep positions split into the unmasked core and the masked
+# extra step).  Checks that every window entry a lane reads was staged by the
+# task, lies inside the wave's window, and holds the partner the paper's rule
+# assigns; together with the coverage test above, every pair is tested once.
+
+STEP_CAP = 416
+
+
+def window_entries(K, w, T, x):
+    return w + (T + x + K - 1 + K - 1) // K
+
+
+def sweep_positions(K, T, x):
+    """(tau, k, masked) in the order the kernel tests them."""
+    out = []
+    if K == 1:
+        out += [(t, 0, False) for t in range(T)]
+        if x:
+            out.append((T, 0, True))
+        return out
+    if T > 0:
+        out.append((0, 0, False))
+    for t in range(1, T):
+        out += [(t, 0, False), (t, 1, False)]
+    if T > 0:
+        out.append((T, 1, False))
+    if x:
+        out += [(T, 0, True), (T + 1, 1, True)]
+    return out
+
+
+def emulate(n, K, r0, s0, T, x, m, w):
+    S = window_entries(K, w, T, x)
+    assert m * K * S <= STEP_CAP and m * w <= 64
+    assert S <= w * (6 if K == 1 else 4)                      # staging slots per lane
+    staged = {}
+    for lane in range(64):
+        j, l = divmod(lane, w)
+        if j >= m:
+            continue
+        for c in range(K):
+            for i in range((S + w - 1) // w):
+                q = l + w * i
+                if q < S:
+                    o = r0 + s0 + K * q + c
+                    o = o - n if o >= n else o
+                    staged[(j * K + c) * S + q] = (j, o if o < n else None)
+    pairs = []
+    for lane in range(64):
+        j, l = divmod(lane, w)
+        live = j < m
+        if not live:
+            j, l = 0, 0
+        e0 = (j * K) * S + l
+        for tau, k, masked in sweep_positions(K, T, x):
+            e = e0 + (tau % K) * S + tau // K
+            assert 0 <= e < m * K * S <= STEP_CAP
+            seg, o = staged[e]
+            assert seg == j
+            row = r0 + K * l + k
+            if not live or row >= n:
+                continue
+            if masked and not (n % 2 == 0 and row < n // 2):
+                continue
+            s = s0 + tau - k
+            assert o == (row + s) % n, (n, K, row, s, o)
+            pairs.append((j, row, o))
+    return pairs
+
+
+@pytest.mark.parametrize("K", [1, 2])
+def test_step_window_emulation_blocks(K):
+    for n in [2, 3, 5, 64, 65, 70, 129, 130, 256, 301, 1000]:
+        for U in [16, 48, 272 if K == 2 else 288]:
+            for r0, s0, T, x in P.pairs_debug_step_ranges(n, K, U):
+                emulate(n, K, int(r0), int(s0), int(T), int(x), 1, 64)
+
+
+@pytest.mark.parametrize("K", [1, 2])
+def test_step_window_emulation_packs(K):
+    for n in range(2, 64 * K + 1):
+        Kp = 1 if n < 4 * K else K
+        w = -(-n // Kp)
+        h, x = (n - 1) // 2, 1 if n % 2 == 0 else 0
+        S = window_entries(Kp, w, h, x)
+        m = max(1, min(64 // w, STEP_CAP // (Kp * S)))
+        pairs = emulate(n, Kp, 0, 1, h, x, m, w)
+        for j in range(m):
+            got = sorted(tuple(sorted((r, o))) for (jj, r, o) in pairs if jj == j)
+            assert got == [(a, b) for a in range(n) for b in range(a + 1, n)], (n, Kp, j)
