@@ -482,14 +482,22 @@ __device__ __forceinline__ StepRaw<ObjT<KindV>> step_load_task(const BatchIO &io
                                                                const StepSets &ss) {
     using T = ObjT<KindV>;
     const StepGeom g = desc_geom(d);
-    const StepLane p = step_lane(g);
+    const bool pack = d.set < 0;
+    const StepLane p = pack ? step_lane<true>(g) : step_lane<false>(g);
     const T *X = (const T *)io.x, *Y = (const T *)io.y, *Z = (const T *)io.z,
             *R = (const T *)io.r;
-    if (d.K == 2)
-        return R ? step_load<T, 2, true>(X, Y, Z, R, ss.base, g, p)
-                 : step_load<T, 2, false>(X, Y, Z, R, ss.base, g, p);
-    return R ? step_load<T, 1, true>(X, Y, Z, R, ss.base, g, p)
-             : step_load<T, 1, false>(X, Y, Z, R, ss.base, g, p);
+    if (d.K == 2) {
+        if (pack)
+            return R ? step_load<T, 2, true, true>(X, Y, Z, R, ss.base, g, p)
+                     : step_load<T, 2, false, true>(X, Y, Z, R, ss.base, g, p);
+        return R ? step_load<T, 2, true, false>(X, Y, Z, R, ss.base, g, p)
+                 : step_load<T, 2, false, false>(X, Y, Z, R, ss.base, g, p);
+    }
+    if (pack)
+        return R ? step_load<T, 1, true, true>(X, Y, Z, R, ss.base, g, p)
+                 : step_load<T, 1, false, true>(X, Y, Z, R, ss.base, g, p);
+    return R ? step_load<T, 1, true, false>(X, Y, Z, R, ss.base, g, p)
+             : step_load<T, 1, false, false>(X, Y, Z, R, ss.base, g, p);
 }
 
 // Stages and sweeps one stepping task whose raw inputs are loaded, and adds

@@ -88,9 +88,16 @@ struct StepLane {
     bool live;
 };
 
+template <bool Pack>
 __device__ __forceinline__ StepLane step_lane(const StepGeom &g) {
     const int lane = lane_id();
     StepLane p;
+    if (!Pack) {  // one segment of all 64 lanes
+        p.j = 0;
+        p.l = lane;
+        p.live = true;
+        return p;
+    }
     p.j = lane / g.w;
     p.l = lane - p.j * g.w;
     p.live = p.j < g.m;
@@ -168,8 +175,10 @@ __device__ __forceinline__ void static_for(F &&f) {
 }
 
 // Returns the loaded values by value (not through a reference), so that the
-// two shapes' loads of one task merge as register values.
-template <typename T, int K, bool WithR>
+// two shapes' loads of one task merge as register values.  A pack covers whole
+// sets, so its window holds only objects of its own rows: only the rows are
+// loaded, and staging places each row in the window (step_stage).
+template <typename T, int K, bool WithR, bool Pack>
 __device__ __forceinline__ StepRaw<T> step_load(const T *__restrict__ X, const T *__restrict__ Y,
                                                 const T *__restrict__ Z, const T *__restrict__ R,
                                                 int64_t base, const StepGeom &g,
@@ -183,6 +192,7 @@ __device__ __forceinline__ StepRaw<T> step_load(const T *__restrict__ X, const T
             raw_row<k>(raw) = Vec4<T>::make(X[o], Y[o], Z[o], WithR ? R[o] : T(0));
         }
     });
+    if (Pack) return raw;
     static_for<K * step_iters<K>()>([&](auto sc) PAIRS_INLINE {
         constexpr int slot = decltype(sc)::value;
         constexpr int c = slot / step_iters<K>(), i = slot % step_iters<K>();
@@ -196,11 +206,29 @@ __device__ __forceinline__ StepRaw<T> step_load(const T *__restrict__ X, const T
     return raw;
 }
 
-// Stage: every staged entry is written (a converted record or a sentinel),
-// then the wave synchronises.  rec(e, valid, vals) writes entry e.
-template <typename T, int K, typename Rec>
+// Stage, then synchronise the wave.  rec(e, valid, vals) writes entry e.
+// Row blocks write every staged entry (a converted record or a sentinel).  A
+// pack (whole sets, r0 = 0, s0 = 1) writes each of its rows o to the window
+// positions v = o - 1 and v = o - 1 + n that exist: every position below
+// 2n - 1 holds object (v + 1) mod n, and no row of a pack reads past it.
+template <typename T, int K, bool Pack, typename Rec>
 __device__ __forceinline__ void step_stage(const StepGeom &g, const StepLane &p,
                                            const StepRaw<T> &raw, Rec &&rec) {
+    if (Pack) {
+        static_for<K>([&](auto kc) PAIRS_INLINE {
+            constexpr int k = decltype(kc)::value;
+            const int o = K * p.l + k;
+            if (p.live && o < g.n) {
+                const auto &v = raw_row<k>(raw);
+                const int v1 = o - 1, v2 = o - 1 + g.n, lim = K * g.S;
+                const int seg = p.j * K * g.S;
+                if (v1 >= 0 && v1 < lim) rec(seg + (v1 % K) * g.S + v1 / K, true, v);
+                if (v2 < lim) rec(seg + (v2 % K) * g.S + v2 / K, true, v);
+            }
+        });
+        wave_sync();
+        return;
+    }
     static_for<K * step_iters<K>()>([&](auto sc) PAIRS_INLINE {
         constexpr int slot = decltype(sc)::value;
         constexpr int c = slot / step_iters<K>(), i = slot % step_iters<K>();
@@ -310,7 +338,7 @@ __device__ __forceinline__ StepCountResult step_count_i32(const StepRaw<int32_t>
                                                           Hook &&hook) {
     int4 *wa = (int4 *)lds;
     int64_t *wq = (int64_t *)((char *)lds + kStepCap * sizeof(int4));
-    const StepLane p = step_lane(g);
+    const StepLane p = step_lane<Pack>(g);
     RowI32 rows[K];
     bool extra[K];
 #pragma unroll
@@ -330,7 +358,7 @@ __device__ __forceinline__ StepCountResult step_count_i32(const StepRaw<int32_t>
             rows[k].nq = -((int64_t)1 << 62);  // never hits
         }
     }
-    step_stage<int32_t, K>(g, p, raw, [&](int e, bool valid, const int4 &v) PAIRS_INLINE {
+    step_stage<int32_t, K, Pack>(g, p, raw, [&](int e, bool valid, const int4 &v) PAIRS_INLINE {
         wa[e] = valid ? v : make_int4(0, 0, 0, 0);
         wq[e] = valid ? gram_q(v.x, v.y, v.z, v.w) : INT64_MAX;  // sentinel: never reached
     });
@@ -361,7 +389,7 @@ __device__ __forceinline__ StepCountResult step_count_f32(const StepRaw<float> &
                                                           const StepGeom &g, void *__restrict__ lds,
                                                           Hook &&hook) {
     float4 *wa = (float4 *)lds;
-    const StepLane p = step_lane(g);
+    const StepLane p = step_lane<Pack>(g);
     float xr[K], yr[K], zr[K], rr[K];
     bool extra[K];
 #pragma unroll
@@ -376,7 +404,7 @@ __device__ __forceinline__ StepCountResult step_count_f32(const StepRaw<float> &
             yr[k] = zr[k] = rr[k] = 0.0f;
         }
     }
-    step_stage<float, K>(g, p, raw, [&](int e, bool valid, const float4 &v) PAIRS_INLINE {
+    step_stage<float, K, Pack>(g, p, raw, [&](int e, bool valid, const float4 &v) PAIRS_INLINE {
         wa[e] = valid ? v : make_float4(-INFINITY, 0.0f, 0.0f, 0.0f);
     });
     hook();
@@ -413,7 +441,7 @@ __device__ __forceinline__ StepEnergyResult step_energy(const StepRaw<float> &ra
                                                         const StepGeom &g, float eps2,
                                                         void *__restrict__ lds, Hook &&hook) {
     float4 *wa = (float4 *)lds;
-    const StepLane p = step_lane(g);
+    const StepLane p = step_lane<Pack>(g);
     float xr[K], yr[K], zr[K], rr[K], part[K];
     double acc[K];
     bool extra[K], live_row[K];
@@ -433,7 +461,7 @@ __device__ __forceinline__ StepEnergyResult step_energy(const StepRaw<float> &ra
         part[k] = 0.0f;
         acc[k] = 0.0;
     }
-    step_stage<float, K>(g, p, raw, [&](int e, bool valid, const float4 &v) PAIRS_INLINE {
+    step_stage<float, K, Pack>(g, p, raw, [&](int e, bool valid, const float4 &v) PAIRS_INLINE {
         wa[e] = valid ? make_float4(v.x, v.y, v.z, WithCount ? v.w : 0.0f)
                       : make_float4(-INFINITY, 0.0f, 0.0f, 0.0f);
     });

@@ -150,7 +150,7 @@ def sweep_positions(K, T, x):
     return out
 
 
-def emulate(n, K, r0, s0, T, x, m, w):
+def emulate(n, K, r0, s0, T, x, m, w, pack=False):
     S = window_entries(K, w, T, x)
     assert m * K * S <= STEP_CAP and m * w <= 64
     assert S <= w * (6 if K == 1 else 4)                      # staging slots per lane
@@ -158,6 +158,16 @@ def emulate(n, K, r0, s0, T, x, m, w):
     for lane in range(64):
         j, l = divmod(lane, w)
         if j >= m:
+            continue
+        if pack:
+            # whole sets: each row o is written to window positions o - 1, o - 1 + n
+            assert r0 == 0 and s0 == 1
+            for k in range(K):
+                o = K * l + k
+                if o < n:
+                    for v in (o - 1, o - 1 + n):
+                        if 0 <= v < K * S:
+                            staged[(j * K + v % K) * S + v // K] = (j, o)
             continue
         for c in range(K):
             for i in range((S + w - 1) // w):
@@ -176,10 +186,12 @@ def emulate(n, K, r0, s0, T, x, m, w):
         for tau, k, masked in sweep_positions(K, T, x):
             e = e0 + (tau % K) * S + tau // K
             assert 0 <= e < m * K * S <= STEP_CAP
-            seg, o = staged[e]
-            assert seg == j
             row = r0 + K * l + k
-            if not live or row >= n:
+            if not live:
+                continue                     # idle lanes report nothing
+            seg, o = staged[e]               # live lanes, padding rows included, read staged entries
+            assert seg == j
+            if row >= n:
                 continue
             if masked and not (n % 2 == 0 and row < n // 2):
                 continue
@@ -205,7 +217,7 @@ def test_step_window_emulation_packs(K):
         h, x = (n - 1) // 2, 1 if n % 2 == 0 else 0
         S = window_entries(Kp, w, h, x)
         m = max(1, min(64 // w, STEP_CAP // (Kp * S)))
-        pairs = emulate(n, Kp, 0, 1, h, x, m, w)
+        pairs = emulate(n, Kp, 0, 1, h, x, m, w, pack=True)
         for j in range(m):
             got = sorted(tuple(sorted((r, o))) for (jj, r, o) in pairs if jj == j)
             assert got == [(a, b) for a in range(n) for b in range(a + 1, n)], (n, Kp, j)
