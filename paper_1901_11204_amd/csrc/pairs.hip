@@ -587,6 +587,9 @@ __device__ __forceinline__ void run_task(const BatchIO &io, int64_t base, const 
 // Plans: wave w runs the tasks descs[wave_start[w] .. wave_start[w+1]), a list
 // balanced across the waves on the host; the next descriptor is fetched while
 // the current task runs.
+// Wave lists of a plan per resident wave.
+constexpr int kPlanWaveFactor = 8;
+
 // Waves per SIMD the batched kernels are compiled for: four where the
 // largest compiled shape allows it without register spills (the stepping
 // sweeps hide their per-task load latency behind the other waves).
@@ -1183,7 +1186,12 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
     const int kk = kind == PAIRS_KIND_COUNT_I32 ? kCountI32
                    : kind == PAIRS_KIND_COUNT_F32 ? kCountF32 : kEnergyF32;
     int64_t n_waves = 0;
-    with_plan_kernel(kk, kmax, [&](auto kern) { n_waves = resident_blocks(st, kern) * kWavesPerBlock; });
+    // Task lists for eight times the resident waves: the lists are balanced by
+    // a cost estimate, and as resident waves finish, the hardware starts the
+    // waiting ones, which evens out what the estimate misses.
+    with_plan_kernel(kk, kmax, [&](auto kern) {
+        n_waves = resident_blocks(st, kern) * kWavesPerBlock * kPlanWaveFactor;
+    });
 
     // every task with its cost in VALU issue slots.  Broadcast tasks: per
     // 64-partner group 5 instructions per row slice in a row block's core, 7

@@ -252,14 +252,19 @@ __device__ __forceinline__ void step_stage(const StepGeom &g, const StepLane &p,
 // registers); fold() runs at least once every kStepUnroll + 2 tests of a row.
 constexpr int kStepUnroll = 8;
 
-template <int K, typename Test, typename Fold>
-__device__ __forceinline__ void step_sweep(const StepGeom &g, int e0, Test &&test, Fold &&fold) {
+//
+// group(ea, eb) tests every row slice against both entries ea and eb, all
+// unmasked; the main loops use it so that a kind can interleave the
+// independent dependency chains of several tests.
+template <int K, typename Test, typename Group, typename Fold>
+__device__ __forceinline__ void step_sweep(const StepGeom &g, int e0, Test &&test, Group &&group,
+                                           Fold &&fold) {
     const int T = g.T;
     if (K == 1) {
         int tau = 0;
         for (; tau + kStepUnroll <= T; tau += kStepUnroll) {
 #pragma unroll
-            for (int d = 0; d < kStepUnroll; ++d) test(e0 + tau + d, 0, false);
+            for (int d = 0; d < kStepUnroll; d += 2) group(e0 + tau + d, e0 + tau + d + 1);
             fold();
         }
         for (; tau < T; ++tau) test(e0 + tau, 0, false);
@@ -275,12 +280,7 @@ __device__ __forceinline__ void step_sweep(const StepGeom &g, int e0, Test &&tes
         int u = 0;
         for (; u + kStepUnroll / 2 <= pairs; u += kStepUnroll / 2) {
 #pragma unroll
-            for (int d = 0; d < kStepUnroll / 2; ++d) {
-                test(b1 + u + d, 0, false);
-                test(b1 + u + d, 1, false);
-                test(b0 + u + d, 0, false);
-                test(b0 + u + d, 1, false);
-            }
+            for (int d = 0; d < kStepUnroll / 2; ++d) group(b1 + u + d, b0 + u + d);
             fold();
         }
         for (; u < pairs; ++u) {
@@ -365,15 +365,51 @@ __device__ __forceinline__ StepCountResult step_count_i32(const StepRaw<int32_t>
     hook();
     const int e0 = (p.j * K) * g.S + p.l;
     StepCountResult res{0u, 0u};
+    auto tally = [&](bool hit) PAIRS_INLINE {
+        if (Pack)
+            res.lane += hit ? 1u : 0u;
+        else
+            res.wave += count_bits(hit);
+    };
     step_sweep<K>(
         g, e0,
         [&](int e, int k, bool masked) PAIRS_INLINE {
             bool hit = step_hit_i32(rows[k], wa[e], wq[e]);
             if (masked) hit = hit && extra[k];
-            if (Pack) {
-                res.lane += hit ? 1u : 0u;
-            } else {
-                res.wave += count_bits(hit);
+            tally(hit);
+        },
+        [&](int ea, int eb) PAIRS_INLINE {
+            // 2K independent multiply-add chains, advanced in lockstep: a
+            // dependent 64-bit multiply-add waits on its predecessor, so a
+            // wave needs several chains in flight to issue every cycle
+            const int4 a = wa[ea], b = wa[eb];
+            const int64_t qa = wq[ea], qb = wq[eb];
+            int64_t va[K], vb[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                asm("" : "+v"(rows[k].ax), "+v"(rows[k].ay), "+v"(rows[k].az), "+v"(rows[k].ar));
+                va[k] = rows[k].nq + (int64_t)rows[k].ax * a.x;
+                vb[k] = rows[k].nq + (int64_t)rows[k].ax * b.x;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                va[k] += (int64_t)rows[k].ay * a.y;
+                vb[k] += (int64_t)rows[k].ay * b.y;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                va[k] += (int64_t)rows[k].az * a.z;
+                vb[k] += (int64_t)rows[k].az * b.z;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                va[k] += (int64_t)rows[k].ar * a.w;
+                vb[k] += (int64_t)rows[k].ar * b.w;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                tally(va[k] >= qa);
+                tally(vb[k] >= qb);
             }
         },
         []() PAIRS_INLINE {});
@@ -410,16 +446,23 @@ __device__ __forceinline__ StepCountResult step_count_f32(const StepRaw<float> &
     hook();
     const int e0 = (p.j * K) * g.S + p.l;
     StepCountResult res{0u, 0u};
+    auto test = [&](int e, int k, bool masked) PAIRS_INLINE {
+        const float4 b = wa[e];
+        bool hit = hit_f32(xr[k], yr[k], zr[k], rr[k], b.x, b.y, b.z, b.w);
+        if (masked) hit = hit && extra[k];
+        if (Pack) {
+            res.lane += hit ? 1u : 0u;
+        } else {
+            res.wave += count_bits(hit);
+        }
+    };
     step_sweep<K>(
-        g, e0,
-        [&](int e, int k, bool masked) PAIRS_INLINE {
-            const float4 b = wa[e];
-            bool hit = hit_f32(xr[k], yr[k], zr[k], rr[k], b.x, b.y, b.z, b.w);
-            if (masked) hit = hit && extra[k];
-            if (Pack) {
-                res.lane += hit ? 1u : 0u;
-            } else {
-                res.wave += count_bits(hit);
+        g, e0, test,
+        [&](int ea, int eb) PAIRS_INLINE {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                test(ea, k, false);
+                test(eb, k, false);
             }
         },
         []() PAIRS_INLINE {});
@@ -468,31 +511,38 @@ __device__ __forceinline__ StepEnergyResult step_energy(const StepRaw<float> &ra
     hook();
     const int e0 = (p.j * K) * g.S + p.l;
     StepEnergyResult res{0.0, 0u, 0u};
-    step_sweep<K>(
-        g, e0,
-        [&](int ent, int k, bool masked) PAIRS_INLINE {
-            const float4 b = wa[ent];
-            const float dx = xr[k] - b.x, dy = yr[k] - b.y, dz = zr[k] - b.z;
-            float e;
-            if (WithCount) {
-                const float d2 = sq_dist_f32(dx, dy, dz);
-                const float Rs = __fadd_rn(rr[k], b.w);
-                bool hit = d2 <= __fmul_rn(Rs, Rs);
-                if (masked) hit = hit && extra[k];
-                if (Pack) {
-                    res.lane += hit ? 1u : 0u;
-                } else {
-                    res.wave += count_bits(hit);
-                }
-                e = __builtin_amdgcn_rsqf(d2 + eps2);
+    auto test = [&](int ent, int k, bool masked) PAIRS_INLINE {
+        const float4 b = wa[ent];
+        const float dx = xr[k] - b.x, dy = yr[k] - b.y, dz = zr[k] - b.z;
+        float e;
+        if (WithCount) {
+            const float d2 = sq_dist_f32(dx, dy, dz);
+            const float Rs = __fadd_rn(rr[k], b.w);
+            bool hit = d2 <= __fmul_rn(Rs, Rs);
+            if (masked) hit = hit && extra[k];
+            if (Pack) {
+                res.lane += hit ? 1u : 0u;
             } else {
-                float d2 = __builtin_fmaf(dx, dx, eps2);
-                d2 = __builtin_fmaf(dy, dy, d2);
-                d2 = __builtin_fmaf(dz, dz, d2);
-                e = __builtin_amdgcn_rsqf(d2);
+                res.wave += count_bits(hit);
             }
-            if (masked) e = extra[k] ? e : 0.0f;
-            part[k] += e;
+            e = __builtin_amdgcn_rsqf(d2 + eps2);
+        } else {
+            float d2 = __builtin_fmaf(dx, dx, eps2);
+            d2 = __builtin_fmaf(dy, dy, d2);
+            d2 = __builtin_fmaf(dz, dz, d2);
+            e = __builtin_amdgcn_rsqf(d2);
+        }
+        if (masked) e = extra[k] ? e : 0.0f;
+        part[k] += e;
+    };
+    step_sweep<K>(
+        g, e0, test,
+        [&](int ea, int eb) PAIRS_INLINE {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                test(ea, k, false);
+                test(eb, k, false);
+            }
         },
         [&]() PAIRS_INLINE {
 #pragma unroll
