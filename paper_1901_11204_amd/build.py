@@ -14,6 +14,8 @@ LIB = os.path.join(PKG, "libpairs.so")
 SOURCES = [os.path.join(CSRC, "pairs.hip")]
 PROBE_LIB = os.path.join(PKG, "libvaluprobe.so")
 PROBE_SOURCES = [os.path.join(CSRC, "valu_probe.hip")]
+AB_LIB = os.path.join(PKG, "libpairs_ab.so")
+AB_SOURCES = [os.path.join(CSRC, "ab_straightforward.hip")]
 ARCH = "gfx950"
 
 
@@ -46,9 +48,11 @@ def _compile(lib, sources, verbose):
 
 
 def build(verbose: bool = False) -> str:
-    """Compile libpairs.so and the VALU issue-rate probe library."""
+    """Compile libpairs.so, the VALU issue-rate probe library and the
+    benchmark's assignment-comparison library."""
     _compile(LIB, SOURCES, verbose)
     _compile(PROBE_LIB, PROBE_SOURCES, verbose)
+    _compile(AB_LIB, AB_SOURCES, verbose)
     return LIB
 
 

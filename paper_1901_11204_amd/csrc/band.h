@@ -43,6 +43,21 @@ struct Band {
     PAIRS_HD int64_t pairs() const { return (int64_t)n * (n - 1) / 2; }
 };
 
+// The straightforward assignment that the paper measures its method against
+// (Section 5): row i evaluates every j in (i, n), so row i does n-1-i steps
+// and the "virtual partner" u is j itself.  Only the comparison kernels of the
+// benchmark use it.
+struct TriBand {
+    int n;
+
+    PAIRS_HD static TriBand of(int n) {
+        TriBand b;
+        b.n = n;
+        return b;
+    }
+    PAIRS_HD int steps(int i) const { return n - 1 - i; }
+};
+
 // Work decomposition of one set into wave tasks.  A task is a block of 64*K
 // consecutive rows [ra, ra + 64K) and a chunk of at most U consecutive virtual
 // partners; chunk c of row block b covers u in [ra+1 + c*U, ra+1 + (c+1)*U)

@@ -70,6 +70,10 @@ __device__ __forceinline__ int64_t partner_index(int64_t base, const Band &band,
     return base + (u >= band.n ? u - band.n : u);
 }
 
+__device__ __forceinline__ int64_t partner_index(int64_t base, const TriBand &, int u) {
+    return base + u;
+}
+
 // The raw inputs a task starts from: the K row objects of the lane and the
 // lane's partner of the first group.  Loading them is separated from running
 // the task so that a persistent wave can fetch the next task's inputs while
@@ -81,10 +85,10 @@ struct TaskInputs {
     T px, py, pz, pr;
 };
 
-template <typename T, int K, int KM, bool WithR>
+template <typename T, int K, int KM, bool WithR, typename BandT = Band>
 __device__ __forceinline__ void load_task_inputs(const T *__restrict__ X, const T *__restrict__ Y,
                                                  const T *__restrict__ Z, const T *__restrict__ R,
-                                                 int64_t base, const Band &band, int ra, int u0,
+                                                 int64_t base, const BandT &band, int ra, int u0,
                                                  int u1, TaskInputs<T, KM> &in) {
     const int lane = lane_id();
 #pragma unroll
@@ -110,10 +114,10 @@ __device__ __forceinline__ void load_task_inputs(const T *__restrict__ X, const 
     }
 }
 
-template <int K, int KM>
+template <int K, int KM, typename BandT = Band>
 __device__ __forceinline__ uint32_t count_i32_task_i64(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
                                    const int32_t *__restrict__ pz, const int32_t *__restrict__ pr,
-                                   int64_t base, const Band band, int ra, int u0, int u1,
+                                   int64_t base, const BandT band, int ra, int u0, int u1,
                                    void *__restrict__ lds, const TaskInputs<int32_t, KM> &in) {
     PartnerI32 *wp = (PartnerI32 *)lds;
     int64_t *wq = (int64_t *)lds + 2 * kWave;
@@ -208,10 +212,10 @@ __device__ __forceinline__ void gram_features(int32_t xi, int32_t yi, int32_t zi
 }
 
 
-template <int K, int KM>
+template <int K, int KM, typename BandT = Band>
 __device__ __forceinline__ uint32_t count_i32_task_f64(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
                                    const int32_t *__restrict__ pz, const int32_t *__restrict__ pr,
-                                   int64_t base, const Band band, int ra, int u0, int u1,
+                                   int64_t base, const BandT band, int ra, int u0, int u1,
                                    void *__restrict__ lds, const TaskInputs<int32_t, KM> &in) {
     double *win = (double *)lds;
     const int lane = lane_id();
@@ -296,17 +300,19 @@ __device__ __forceinline__ uint32_t count_i32_task_f64(const int32_t *__restrict
 // The exact int32 count task: 64-bit integer form for short row blocks
 // (K <= 2, where the broadcast of each partner limits), double form for tall
 // ones.  Both decide the same integer predicate inside the exact domain.
-template <int K, int KM>
+// The balanced assignment (Band) on the library's path; the comparison
+// kernels of the benchmark also run the straightforward one (TriBand).
+template <int K, int KM, typename BandT = Band>
 __device__ __forceinline__ uint32_t count_i32_task(const int32_t *__restrict__ px,
                                                    const int32_t *__restrict__ py,
                                                    const int32_t *__restrict__ pz,
                                                    const int32_t *__restrict__ pr, int64_t base,
-                                                   const Band band, int ra, int u0, int u1,
+                                                   const BandT band, int ra, int u0, int u1,
                                                    void *__restrict__ lds,
                                                    const TaskInputs<int32_t, KM> &in) {
     if (K >= 4)
-        return count_i32_task_f64<K, KM>(px, py, pz, pr, base, band, ra, u0, u1, lds, in);
-    return count_i32_task_i64<K, KM>(px, py, pz, pr, base, band, ra, u0, u1, lds, in);
+        return count_i32_task_f64<K, KM, BandT>(px, py, pz, pr, base, band, ra, u0, u1, lds, in);
+    return count_i32_task_i64<K, KM, BandT>(px, py, pz, pr, base, band, ra, u0, u1, lds, in);
 }
 
 // --------------------------------------------------------- float32 count --

@@ -106,3 +106,23 @@ def test_plan_argument_errors_on_the_host():
     assert L.pairs_plan_destroy(None) == OK
     assert L.pairs_jitter_f32(x_ := fake(0), fake(1), fake(2), 10, 1, 0, -1.0, 0,
                               None) == INVALID
+
+
+def test_comparison_library_exports_and_checks_arguments():
+    """include/pairs_ab.h: the benchmark's assignment comparison."""
+    from paper_1901_11204_amd import build as B
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "pairs_ab.h")).read(),
+                  flags=re.S)
+    names = sorted(set(re.findall(r"\b(pairs_[a-z0-9_]+)\s*\(", text)))
+    assert names == ["pairs_ab_count_i32"]
+    L = ctypes.CDLL(B.AB_LIB)
+    f = L.pairs_ab_count_i32
+    f.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_int,
+                                                           ctypes.c_void_p, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    x, y, z, r, out = (fake(k) for k in range(5))
+    assert f(2, x, y, z, r, 10, 1, out, None) == -1      # no such variant
+    assert f(0, x, y, z, r, 10, 4, out, None) == -1      # rows per lane 1 or 8
+    assert f(0, None, y, z, r, 10, 1, out, None) == -1   # missing input
+    assert f(1, x, y, z, r, 10, 1, None, None) == -1     # missing output
+    assert f(1, x, y, z, r, -1, 1, out, None) == -1
