@@ -587,8 +587,10 @@ __device__ __forceinline__ void run_task(const BatchIO &io, int64_t base, const 
 // Plans: wave w runs the tasks descs[wave_start[w] .. wave_start[w+1]), a list
 // balanced across the waves on the host; the next descriptor is fetched while
 // the current task runs.
-// Wave lists of a plan per resident wave.
+// Wave lists of a plan per resident wave, and blocks of an unplanned call per
+// resident block.
 constexpr int kPlanWaveFactor = 8;
+constexpr int kScanBlockFactor = 16;
 
 // Waves per SIMD the batched kernels are compiled for: four where the
 // largest compiled shape allows it without register spills (the stepping
@@ -950,8 +952,10 @@ pairs_status_t launch_scan(int kind, const BatchIO &io, const ScanSource &src,
                            const ClassTable &ct, hipStream_t s) {
     DeviceState *st;
     PAIRS_TRY(device_state(&st));
+    // sixteen times the resident blocks: each block takes fewer grid-stride
+    // tasks, and blocks that start as others finish even out the tail
     with_scan_kernel(kind, max_rows(ct), [&](auto kern) {
-        const int64_t blocks = resident_blocks(st, kern);
+        const int64_t blocks = resident_blocks(st, kern) * kScanBlockFactor;
         kern<<<(unsigned)blocks, kBlock, 0, s>>>(io, src, ct);
     });
     PAIRS_HIP_CHECK(hipGetLastError());
