@@ -515,9 +515,13 @@ __device__ __forceinline__ void step_run(const BatchIO &io, const StepGeom &g, c
         else
             r = step_count_f32<K, Pack>(raw, g, win, hook);
         if (Pack) {
-            const uint32_t c = segment_sum(r.lane, g, win);
-            if (lane < g.m && c)
-                atomicAdd((unsigned long long *)&io.counts[ss.out_set], (unsigned long long)c);
+            // collisions are usually rare: most packs have nothing to report
+            if (__builtin_amdgcn_ballot_w64(r.lane != 0)) {
+                const uint32_t c = segment_sum(r.lane, g, win);
+                if (lane < g.m && c)
+                    atomicAdd((unsigned long long *)&io.counts[ss.out_set],
+                              (unsigned long long)c);
+            }
         } else if (lane == 0 && r.wave) {
             atomicAdd((unsigned long long *)&io.counts[ss.out_set], (unsigned long long)r.wave);
         }
@@ -529,7 +533,9 @@ __device__ __forceinline__ void step_run(const BatchIO &io, const StepGeom &g, c
             r = step_energy<K, Pack, false>(raw, g, io.eps2, win, hook);
         if (Pack) {
             const double e = segment_sum(r.lane_energy, g, win);
-            const uint32_t c = io.r ? segment_sum(r.lane, g, win) : 0u;
+            const uint32_t c = io.r && __builtin_amdgcn_ballot_w64(r.lane != 0)
+                                   ? segment_sum(r.lane, g, win)
+                                   : 0u;
             if (lane < g.m) {
                 atomicAdd(&io.energy[ss.out_set], e);
                 if (c)

@@ -561,7 +561,8 @@ __device__ __forceinline__ StepEnergyResult step_energy(const StepRaw<float> &ra
 }
 
 // Sums of per-lane values over each segment of w lanes, through the window
-// (after the sweep): on return lane j < m holds the sum of segment j.
+// (after the sweep): on return lane j < m holds the sum of segment j.  Four
+// independent partial sums keep the LDS reads of a segment in flight together.
 template <typename T>
 __device__ __forceinline__ T segment_sum(T v, const StepGeom &g, void *__restrict__ lds) {
     T *s = (T *)lds;
@@ -569,8 +570,19 @@ __device__ __forceinline__ T segment_sum(T v, const StepGeom &g, void *__restric
     s[lane] = v;
     wave_sync();
     T tot = T(0);
-    if (lane < g.m)
-        for (int i = 0; i < g.w; ++i) tot += s[lane * g.w + i];
+    if (lane < g.m) {
+        const T *seg = s + lane * g.w;
+        T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+        int i = 0;
+        for (; i + 4 <= g.w; i += 4) {
+            a0 += seg[i];
+            a1 += seg[i + 1];
+            a2 += seg[i + 2];
+            a3 += seg[i + 3];
+        }
+        for (; i < g.w; ++i) a0 += seg[i];
+        tot = (a0 + a1) + (a2 + a3);
+    }
     wave_sync();
     return tot;
 }
