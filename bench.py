@@ -157,6 +157,27 @@ PAPER_CONTEXT = {
 }
 
 
+def graph_per_call(torch, P, t, out, calls):
+    """Per-call time of the small-set count when `calls` calls are captured in
+    one HIP graph (the calls allocate nothing and synchronise nothing)."""
+    import numpy as np
+    want = int(out.item())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        P.pairs_count_i32(*t, out)  # warm-up on the capturing stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(calls):
+            P.pairs_count_i32(*t, out)
+    ms, _ = timed_steps(lambda: g.replay(), 3, 1)
+    if int(out.item()) != want:
+        raise RuntimeError("graph replay changed the count")
+    return {"us_per_call": float(np.mean(ms)) * 1e3 / calls, "calls": calls}
+
+
 def assignment_comparison(torch, x, y, z, r, n, want, steps):
     """The paper's Section 5 comparison on this GPU: the balanced circular
     assignment against the straightforward triangular one, both with one wave
@@ -324,6 +345,11 @@ def main():
         "paper_context": PAPER_CONTEXT,
         "timing": {"ms_min": float(np.min(ms)), "ms_median": float(np.median(ms)),
                    "ms_max": float(np.max(ms)), "wall_s": wall},
+        "c_pair": {"per_pair_ops": C_ALG["count_i32"],
+                   "inner_loop": "per partner and row slice: 4 v_fma_f64 + 1 v_cmp_ge_f64 "
+                                 "(exact Gram form, 8 rows per lane); ballot into "
+                                 "s_bcnt1/s_add on the scalar unit",
+                   "measured_valu_lane_instr_per_pair": "5.16 (rocprofv3 SQ_INSTS_VALU)"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
                      "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK,
                      "traffic": recorded_traffic(),
@@ -351,6 +377,7 @@ def main():
         ms1, _ = timed_steps(lambda: P.pairs_count_i32(*t1, out), 50, 5)
         m1 = float(np.median(ms1))
         sec["count_i32_4096"] = {"ms": m1, "G_pairs_per_s": p1 / m1 / 1e6, "count": int(out.item())}
+        sec["count_i32_4096"]["graph_of_1000_calls"] = graph_per_call(torch, P, t1, out, 1000)
         p3 = w.config3()
         t3 = [torch.from_numpy(v).to(dev) for v in p3.arrays()]
         n3 = p3.n

@@ -175,3 +175,35 @@ def test_count_f32_validate_rejects_nonfinite():
     z = np.zeros(n, np.float32)
     with pytest.raises(P.PairsError):
         P.count_f32(*dev(x, z, z, z), validate=True)
+
+
+def test_count_i32_calls_captured_in_a_graph():
+    """Single-set calls allocate and synchronise nothing, so a HIP graph can
+    hold them: each replay, with eager calls on other data in between, gives
+    the oracle's count."""
+    import torch
+    s = w.config1()
+    want = oracle.count_i32(*s.arrays())
+    t = dev(*s.arrays())
+    other = dev(*w.spheres_i32(777, 5, 32, 3, radius_lo=0).arrays())
+    want_other = oracle.count_i32(*w.spheres_i32(777, 5, 32, 3, radius_lo=0).arrays())
+    out = torch.empty(1, dtype=torch.int64, device="cuda")
+    out2 = torch.empty(1, dtype=torch.int64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        P.pairs_count_i32(*t, out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(10):
+            P.pairs_count_i32(*t, out)
+    for rep in range(3):
+        out.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(out.item()) == want, rep
+        P.pairs_count_i32(*other, out2)
+        torch.cuda.synchronize()
+        assert int(out2.item()) == want_other
