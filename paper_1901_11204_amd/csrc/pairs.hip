@@ -90,12 +90,16 @@ ClassTable default_table(int kind, bool batched) {
                              PAIRS_FORM_STEPPING};
         return make_table(4, lo, K, U, form);
     }
+    // single sets: measured on MI355X by autotune.tune_single at n = 4096,
+    // 16384, 65536 and 262144 (the largest class is the N = 2^20 optimum)
     if (kind == PAIRS_KIND_ENERGY_F32) {
-        const int lo[3] = {65536, 8192, 0}, K[3] = {4, 4, 1}, U[3] = {1024, 1024, 256};
-        return make_table(3, lo, K, U, nullptr);
+        const int lo[4] = {65536, 16384, 4096, 0}, K[4] = {8, 8, 4, 4},
+                  U[4] = {256, 128, 128, 64};
+        return make_table(4, lo, K, U, nullptr);
     }
-    const int lo[3] = {65536, 8192, 0}, K[3] = {8, 4, 1}, U[3] = {1024, 1024, 256};
-    return make_table(3, lo, K, U, nullptr);
+    const int lo[4] = {524288, 65536, 8192, 0}, K[4] = {8, 4, 4, 1},
+              U[4] = {1024, 512, 128, 64};
+    return make_table(4, lo, K, U, nullptr);
 }
 
 // Largest step chunk of a stepping task with K rows per lane: a row block's

@@ -12,8 +12,9 @@ from gpu_util import announce, dev
 
 pytestmark = pytest.mark.gpu
 
-# sizes around every tile edge of the three single-set shapes (64, 256 and 512
-# rows per wave), ragged tails, both parities, and the shape switches
+# sizes around every tile edge of the single-set shapes (64 to 512 rows per
+# wave), ragged tails, both parities, and the size-class switches of the
+# default tables (4096, 8192, 16384, 65536)
 SIZES = [0, 1, 2, 3, 4, 5, 6, 7, 63, 64, 65, 66, 127, 128, 129, 255, 256, 257, 511, 512, 513,
          1000, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193, 8194,
          12345, 16383, 16384, 16385, 30001, 65535, 65536, 65537, 65538]
