@@ -14,6 +14,7 @@ reported under "secondary"; the CPU oracle timed on a bounded sample of the
 same workload is reported under "cpu_baseline".
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -66,6 +67,16 @@ def recorded_traffic():
         return int(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden", "config_values.json")
+
+
+def golden():
+    """Expected values of the full-size workloads, written by the CPU oracle
+    (tests/golden/make_golden.py)."""
+    with open(GOLDEN) as f:
+        return json.load(f)
 
 
 def log(*a):
@@ -229,7 +240,9 @@ def bench_batched(P, w, torch, np, dev, steps):
         "workload": "200000 sets, sizes lognormal(4,1.2) clipped to [2,8192], seed 5",
         "pair_tests": pairs, "ms": m, "G_pairs_per_s": pairs / m / 1e6,
         "valu_frac": pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK,
-        "n_tasks": plan.info()["n_tasks"], "total_count": int(counts.sum().item())}
+        "n_tasks": plan.info()["n_tasks"], "total_count": int(counts.sum().item()),
+        "matches_oracle": hashlib.sha256(counts.cpu().numpy().astype("<u8").tobytes()).hexdigest()
+                          == golden()["config4_counts"]["sha256_le_u64"]}
     toff = torch.from_numpy(b.offsets).to(dev)
     ws = torch.empty(P.pairs_batched_workspace_size(b.n_sets, b.n_total), dtype=torch.uint8,
                      device=dev)
@@ -341,7 +354,7 @@ def main():
         "config": {"workload": "single set, N=2^20 int32 spheres, centres in [0,2^24)^3, "
                                "radii in [1,2^14], seed 2; exact collision count",
                    "n": n, "pair_tests": pairs, "parallelism": "single GPU"},
-        "result": {"count": count},
+        "result": {"count": count, "matches_oracle": count == golden()["config2_even_count"]},
         "paper_context": PAPER_CONTEXT,
         "timing": {"ms_min": float(np.min(ms)), "ms_median": float(np.median(ms)),
                    "ms_max": float(np.max(ms)), "wall_s": wall},
@@ -389,7 +402,10 @@ def main():
         m3 = float(np.mean(ms3))
         sec["energy_f32_2^18"] = {"ms": m3, "G_pairs_per_s": pp3 / m3 / 1e6,
                                   "valu_frac": pp3 / (m3 * 1e-3) * C_ALG["energy_f32"] / VALU_PEAK,
-                                  "total": float(tot.item())}
+                                  "total": float(tot.item()),
+                                  "rel_err_total_vs_fp64_oracle":
+                                      abs(float(tot.item()) - golden()["config3_energy_total"])
+                                      / golden()["config3_energy_total"]}
         ms3b, _ = timed_steps(lambda: P.pairs_energy_f32(*t3, 1e-4, None, tot), max(3, a.steps // 2), 1)
         m3b = float(np.mean(ms3b))
         sec["energy_f32_2^18_total_only"] = {"ms": m3b, "G_pairs_per_s": pp3 / m3b / 1e6}
