@@ -43,7 +43,7 @@ PLAIN_DEF_OPS = 12   # operations of the plain definition per pair (either kind)
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "count_i32_n2p20_hbm.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1901_11204_amd", "csrc", f)
-                  for f in ("band.h", "device.h", "tasks.h", "pairs.hip")]
+                  for f in ("band.h", "device.h", "tasks.h", "steps.h", "pairs.hip")]
 
 
 def recorded_traffic():
@@ -151,7 +151,44 @@ def cpu_baseline(sample_n):
     return {"value": pairs / dt / 1e9, "unit": "G pair tests/s", "cores": threads,
             "kind": "oracle", "seconds": dt, "nproc": os.cpu_count(), "cpu_model": model,
             "sample": f"plain i<j loop over the first {sample_n} spheres of the N=2^20 "
-                      f"set ({pairs} pair tests), {threads} OpenMP threads"}
+                      f"set ({pairs} pair tests), {threads} OpenMP threads",
+            "serial": cpu_serial(oracle, w)}
+
+
+def cpu_serial(oracle, w):
+    """One-thread oracle rates: the whole 4096-sphere set, and row slices of
+    the 2^20 count and the 2^18 energy, extrapolated to the whole set by the
+    pair count (every pair costs the same)."""
+    import numpy as np
+    out = {}
+    a1 = w.config1().arrays()
+    t = time.perf_counter()
+    oracle.count_i32(*a1, threads=1)
+    dt = time.perf_counter() - t
+    p1 = 4096 * 4095 // 2
+    out["count_i32_4096"] = {"seconds": dt, "G_pairs_per_s": p1 / dt / 1e9}
+    s2 = w.config2(2 ** 20).arrays()
+    rows, cols = 2 ** 12, 2 ** 17
+    a = [v[:rows].copy() for v in s2]
+    b = [v[rows:rows + cols].copy() for v in s2]
+    t = time.perf_counter()
+    oracle.cross_count_i32(a, b, threads=1)
+    dt = time.perf_counter() - t
+    rate = rows * cols / dt
+    p2 = 2 ** 20 * (2 ** 20 - 1) // 2
+    out["count_i32_2^20"] = {"sample": f"{rows} rows x {cols} partners", "seconds": dt,
+                             "G_pairs_per_s": rate / 1e9, "extrapolated_full_s": p2 / rate}
+    x3, y3, z3 = w.config3().arrays()
+    rows3 = 2 ** 8
+    t = time.perf_counter()
+    oracle.energy_rows(x3, y3, z3, np.float32(1e-4), np.arange(rows3), threads=1)
+    dt = time.perf_counter() - t
+    n3 = x3.shape[0]
+    rate3 = rows3 * (n3 - 1) / dt
+    out["energy_2^18"] = {"sample": f"E_i of {rows3} rows over all {n3 - 1} partners",
+                          "seconds": dt, "G_pairs_per_s": rate3 / 1e9,
+                          "extrapolated_full_s": n3 * (n3 - 1) // 2 / rate3}
+    return out
 
 
 # The paper's own GPU result for this path, quoted as context next to the
@@ -357,6 +394,7 @@ def main():
         "result": {"count": count, "matches_oracle": count == golden()["config2_even_count"]},
         "paper_context": PAPER_CONTEXT,
         "timing": {"ms_min": float(np.min(ms)), "ms_median": float(np.median(ms)),
+                   "ms_iqr": float(np.percentile(ms, 75) - np.percentile(ms, 25)),
                    "ms_max": float(np.max(ms)), "wall_s": wall},
         "c_pair": {"per_pair_ops": C_ALG["count_i32"],
                    "inner_loop": "per partner and row slice: 4 v_fma_f64 + 1 v_cmp_ge_f64 "
