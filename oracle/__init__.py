@@ -56,6 +56,8 @@ def lib():
                                                                ctypes.c_void_p, ctypes.c_void_p,
                                                                _INT]
     L.oracle_energy_count_f32_batched.restype = None
+    L.oracle_lattice_batched.argtypes = [_i32p] * 3 + [_i64p, _I64, _u64p, _u64p, _INT]
+    L.oracle_lattice_batched.restype = None
     L.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
     L.oracle_philox4x32_10.restype = None
     L.oracle_jitter_scale.argtypes = [ctypes.c_float]
@@ -137,6 +139,26 @@ def energy_count_f32_batched(x, y, z, r, offsets, eps2=np.float32(1e-4), threads
                                           e.ctypes.data_as(ctypes.c_void_p),
                                           c.ctypes.data_as(ctypes.c_void_p), threads)
     return e, c
+
+
+def lattice_counts_batched(x, y, z, offsets, threads: int = 0):
+    """Per bead vector (CSR), the number of bead pairs on one lattice site
+    (collisions) and on neighbouring sites (contacts), as two uint64 arrays;
+    the plain pairwise definition of the paper's Section 3 counts."""
+    x, y, z = (_c(a, np.int32) for a in (x, y, z))
+    off = _c(offsets, np.int64)
+    n_sets = off.shape[0] - 1
+    coll = np.zeros(n_sets, np.uint64)
+    cont = np.zeros(n_sets, np.uint64)
+    lib().oracle_lattice_batched(x, y, z, off, n_sets, coll, cont, threads)
+    return coll, cont
+
+
+def lattice_counts(x, y, z, threads: int = 0):
+    """(collisions, contacts) of one bead vector."""
+    n = np.asarray(x).shape[0]
+    c, t = lattice_counts_batched(x, y, z, np.array([0, n], np.int64), threads)
+    return int(c[0]), int(t[0])
 
 
 def philox4x32_10(ctr, key) -> np.ndarray:

@@ -290,3 +290,44 @@ void oracle_jitter_f32(float *x, float *y, float *z, int64_t n, uint64_t seed,
         }
     }
 }
+
+/* ---------------------------------------------------------- lattice beads -- */
+/* Beads are points of the integer lattice Z^3 (Section 3).  For one vector of
+ * beads the paper counts
+ *   - collisions: pairs of beads on the same lattice site (its countColls
+ *     accumulates, bead by bead, how many earlier beads occupy the site; the
+ *     total is the number of unordered pairs with equal coordinates), and
+ *   - contacts: pairs of beads on neighbouring sites, the six sites at unit
+ *     distance along one axis (its countContacts sums the occupancy of the six
+ *     neighbours of every bead and halves the result, so each unordered pair
+ *     counts once).
+ * This is that plain definition over the unordered pairs i < j of a vector,
+ * with the coordinate differences taken in 64 bits so that any int32 input is
+ * exact.  Vectors are CSR like the sphere batches. */
+
+void oracle_lattice_counts(const int32_t *x, const int32_t *y, const int32_t *z,
+                           int64_t n, uint64_t *collisions, uint64_t *contacts) {
+    uint64_t coll = 0, cont = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            int64_t dx = (int64_t)x[i] - x[j];
+            int64_t dy = (int64_t)y[i] - y[j];
+            int64_t dz = (int64_t)z[i] - z[j];
+            int64_t l1 = llabs(dx) + llabs(dy) + llabs(dz);
+            coll += l1 == 0;
+            cont += l1 == 1;
+        }
+    }
+    *collisions = coll;
+    *contacts = cont;
+}
+
+void oracle_lattice_batched(const int32_t *x, const int32_t *y, const int32_t *z,
+                            const int64_t *off, int64_t n_sets, uint64_t *collisions,
+                            uint64_t *contacts, int threads) {
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads_or_default(threads))
+    for (int64_t s = 0; s < n_sets; ++s) {
+        int64_t b = off[s];
+        oracle_lattice_counts(x + b, y + b, z + b, off[s + 1] - b, collisions + s, contacts + s);
+    }
+}

@@ -1,0 +1,174 @@
+"""Pins of the lattice-bead oracle (collision and contact counts, Section 3).
+
+The oracle is the plain pairwise definition (oracle_lattice_counts in
+oracle/pairs_oracle.c).  These tests check it against facts fixed outside
+it: closed forms of regular bead arrangements, a hand-worked walk (a fixture
+under tests/golden/), the paper's own occupancy-array algorithms (countColls
+and countContacts, Section 3) written here in numpy over a dense array, and
+invariants.  A swapped predicate (collision for contact), a missing axis, a
+diagonal counted as a contact, a halving error or a pair counted twice each
+fail one of them.  All run on the CPU.
+"""
+import json
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+
+
+def beads(points):
+    p = np.asarray(points, dtype=np.int32).reshape(-1, 3)
+    return [np.ascontiguousarray(p[:, k]) for k in range(3)]
+
+
+# ------------------------------------------------------------- closed forms --
+
+@pytest.mark.parametrize("n", [0, 1, 2, 5, 64, 257])
+def test_all_beads_on_one_site(n):
+    # every pair collides, none is a contact
+    assert oracle.lattice_counts(*beads([[3, -4, 9]] * n)) == (comb(n, 2), 0)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("n", [1, 2, 10, 333])
+def test_straight_line(axis, n):
+    # a straight chain: consecutive beads touch, nothing else
+    p = np.zeros((n, 3), np.int32)
+    p[:, axis] = np.arange(n) - 7
+    assert oracle.lattice_counts(*beads(p)) == (0, max(n - 1, 0))
+
+
+@pytest.mark.parametrize("n", [2, 3, 8, 101])
+def test_chain_folded_back_and_forth(n):
+    # a chain stepping +x, -x, +x, ...: ceil(n/2) beads on site A, floor(n/2) on B
+    p = np.zeros((n, 3), np.int32)
+    p[1::2, 0] = 1
+    a, b = (n + 1) // 2, n // 2
+    assert oracle.lattice_counts(*beads(p)) == (comb(a, 2) + comb(b, 2), a * b)
+
+
+@pytest.mark.parametrize("k,m", [(1, 1), (2, 1), (3, 1), (4, 2), (5, 3)])
+def test_full_cube(k, m):
+    # k^3 sites with m beads each: 3 k^2 (k-1) neighbouring site pairs
+    g = np.stack(np.meshgrid(*[np.arange(k)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    p = np.repeat(g, m, axis=0) + np.array([100, -50, 7])
+    assert oracle.lattice_counts(*beads(p)) == (k ** 3 * comb(m, 2),
+                                                3 * k * k * (k - 1) * m * m)
+
+
+def test_diagonal_and_distance_two_are_not_contacts():
+    for d in ([1, 1, 0], [1, 0, 1], [0, 1, 1], [1, 1, 1], [2, 0, 0], [0, -2, 0], [0, 0, 2]):
+        assert oracle.lattice_counts(*beads([[0, 0, 0], d])) == (0, 0)
+    for d in ([1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]):
+        assert oracle.lattice_counts(*beads([[0, 0, 0], d])) == (0, 1)
+
+
+def test_extreme_coordinates():
+    # differences beyond int32 must not wrap into a collision or contact
+    lo, hi = -2 ** 31, 2 ** 31 - 1
+    assert oracle.lattice_counts(*beads([[lo, 0, 0], [hi, 0, 0]])) == (0, 0)
+    assert oracle.lattice_counts(*beads([[hi, hi, hi], [hi, hi, hi - 1], [hi, hi, hi]])) == (1, 2)
+    assert oracle.lattice_counts(*beads([[lo, lo, lo], [lo + 1, lo, lo]])) == (0, 1)
+
+
+# ------------------------------------------------------------- hand-worked --
+
+def test_hand_worked_walks(golden_dir):
+    with open(os.path.join(golden_dir, "lattice_hand.json")) as f:
+        cases = json.load(f)["cases"]
+    assert len(cases) >= 3
+    for c in cases:
+        got = oracle.lattice_counts(*beads(c["beads"]))
+        assert got == (c["collisions"], c["contacts"]), c["name"]
+
+
+# ------------------------------------------ the paper's algorithms, dense --
+
+def count_colls_dense(p):
+    """Section 3, countColls: one pass; each bead adds the occupancy of its
+    site so far, then occupies it.  The space is a dense array over the box."""
+    lo = p.min(axis=0) - 1
+    space = np.zeros(tuple(p.max(axis=0) - lo + 2), np.int64)
+    collisions = 0
+    for b in p - lo:
+        collisions += space[tuple(b)]
+        space[tuple(b)] += 1
+    return int(collisions)
+
+
+def count_contacts_dense(p):
+    """Section 3, countContacts: place every bead, then sum the occupancy of
+    the six neighbours of every bead and halve."""
+    lo = p.min(axis=0) - 1
+    space = np.zeros(tuple(p.max(axis=0) - lo + 2), np.int64)
+    q = p - lo
+    for b in q:
+        space[tuple(b)] += 1
+    contacts = 0
+    for b in q:
+        for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            contacts += space[tuple(b + np.array(d))]
+    assert contacts % 2 == 0
+    return int(contacts // 2)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_matches_the_papers_occupancy_algorithms(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 300))
+    if seed % 2:
+        b = w.lattice_walks(1, n, seed)
+        p = np.stack(b.objs.arrays(), 1).astype(np.int64)
+    else:
+        p = np.rint(rng.normal(0, 1.5, (n, 3))).astype(np.int64)
+    got = oracle.lattice_counts(*beads(p))
+    assert got == (count_colls_dense(p), count_contacts_dense(p))
+
+
+# --------------------------------------------------------------- invariants --
+
+def test_invariant_under_translation_and_permutation():
+    b = w.lattice_walks(1, 500, 3)
+    p = np.stack(b.objs.arrays(), 1)
+    ref = oracle.lattice_counts(*beads(p))
+    rng = np.random.default_rng(1)
+    q = p[rng.permutation(len(p))] + np.array([12345, -999, 70000], np.int32)
+    assert oracle.lattice_counts(*beads(q)) == ref
+
+
+def test_walks_touch_along_the_chain():
+    # consecutive beads of a chain are always one unit apart
+    b = w.lattice_walks(20, 200, 4)
+    coll, cont = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets)
+    assert np.all(cont >= 199)
+    # a step straight back lands on the site two beads before: a collision
+    x, y, z = b.objs.arrays()
+    for s in range(20):
+        sl = slice(b.offsets[s], b.offsets[s + 1])
+        p = np.stack([x[sl], y[sl], z[sl]], 1)
+        backs = int(np.sum(np.all(p[2:] == p[:-2], axis=1)))
+        assert coll[s] >= backs
+
+
+def test_batched_equals_single_vectors():
+    b = w.lattice_walks(7, [0, 1, 2, 3, 50, 129, 400], 9)
+    coll, cont = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets)
+    x, y, z = b.objs.arrays()
+    for s in range(7):
+        sl = slice(b.offsets[s], b.offsets[s + 1])
+        assert (int(coll[s]), int(cont[s])) == oracle.lattice_counts(x[sl], y[sl], z[sl])
+
+
+def test_generator_recipe():
+    # chains from the origin by unit steps along one axis
+    b = w.lattice_walks(30, 64, 2)
+    p = np.stack(b.objs.arrays(), 1).astype(np.int64)
+    off = b.offsets
+    assert np.all(p[off[:-1]] == 0)
+    for s in range(30):
+        d = np.abs(np.diff(p[off[s]:off[s + 1]], axis=0)).sum(axis=1)
+        assert np.all(d == 1)

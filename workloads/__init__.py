@@ -8,10 +8,12 @@ Every generator uses ``numpy.random.default_rng(seed)`` and draws in the order
 written.  The object sets are returned as structure-of-arrays (one contiguous
 array per coordinate), the layout the GPU kernels read.
 
-The paper's own GPU workload is "random vectors of floating point spheres of
-diameter 1" with an unstated distribution (Section 5, experiments on the GPU).
-The recipes below stand in for it with uniform boxes, as fixed in the
-measurement plan of this library.
+The paper's own GPU workload is randomly generated vectors of spheres with
+floating-point coordinates and unit diameter, distribution unstated (Section
+5).  The sphere recipes below stand in for it with uniform boxes.  The lattice
+recipes follow the bead vectors of the paper's linear-time counting
+experiments (Section 5): chains grown from the origin by random unit steps, or
+coordinates drawn from a rounded normal distribution.
 """
 from __future__ import annotations
 
@@ -22,6 +24,7 @@ __all__ = [
     "spheres_i32", "particles_f32",
     "config1", "config2", "config3", "config4", "config5",
     "lognormal_sizes", "offsets_from_sizes",
+    "Beads", "lattice_walks", "lattice_normal",
 ]
 
 
@@ -150,3 +153,52 @@ def config5(n_sets: int = 50_000, seed: int = 6, size_hi: int = 4096,
     x, y, z = _soa(xyz)
     r = np.full(total, np.float32(radius), dtype=np.float32)
     return Batch(off, Spheres(x, y, z, r))
+
+
+class Beads:
+    """int32 lattice points, SoA."""
+
+    def __init__(self, x, y, z):
+        self.x, self.y, self.z = x, y, z
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    def arrays(self):
+        return self.x, self.y, self.z
+
+
+_STEPS = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]],
+                  dtype=np.int32)
+
+
+def lattice_walks(n_vectors: int, n_beads, seed: int) -> Batch:
+    """Bead vectors grown as chains: bead 0 of every vector at the origin, each
+    later bead one unit from the previous one along one of the six axis
+    directions, drawn uniformly.  n_beads is one length for all vectors or an
+    array of lengths (each >= 1)."""
+    rng = np.random.default_rng(seed)
+    sizes = np.broadcast_to(np.asarray(n_beads, dtype=np.int64), (n_vectors,)).copy()
+    off = offsets_from_sizes(sizes)
+    total = int(off[-1])
+    d = rng.integers(0, 6, total, dtype=np.int8)
+    first = off[:-1][sizes > 0]
+    out = []
+    for axis in range(3):
+        step = _STEPS[:, axis][d]
+        step[first] = 0  # the first bead of each vector sits at the origin
+        c = np.cumsum(step, dtype=np.int64)
+        # restart the running sum at every vector
+        base = np.repeat(c[first] - step[first], sizes[sizes > 0])
+        out.append((c - base).astype(np.int32))
+    return Batch(off, Beads(*out))
+
+
+def lattice_normal(n_vectors: int, n_beads: int, sigma: float, seed: int) -> Batch:
+    """Bead vectors with every coordinate rint(normal(0, sigma)), as int32."""
+    rng = np.random.default_rng(seed)
+    sizes = np.full(n_vectors, n_beads, dtype=np.int64)
+    off = offsets_from_sizes(sizes)
+    xyz = np.rint(rng.normal(0.0, sigma, (int(off[-1]), 3))).astype(np.int32)
+    return Batch(off, Beads(*_soa(xyz)))
