@@ -1,6 +1,7 @@
 /*
  * pairs.h -- C ABI of libpairs, brute-force all-pairs interactions within sets
- * of objects on AMD Instinct MI355X (gfx950).
+ * of objects on AMD Instinct MI355X (gfx950), and the linear-time collision
+ * and contact counts of lattice beads (paper Section 3, at the end).
  *
  * Method: Saldanha & de Souza, "High Performance Algorithms for Counting
  * Collisions and Pairwise Interactions", ICCS 2019, Section 4.  Every
@@ -274,6 +275,64 @@ typedef struct {
 
 pairs_status_t pairs_get_shapes(int kind, int batched, pairs_shape_table_t *out);
 pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t *table);
+
+/* --------------------------------------------------------- lattice beads -- */
+/*
+ * Collision and contact counts of bead vectors on the integer lattice Z^3
+ * (Section 3, algorithms countColls and countContacts).  Beads are points
+ * (x, y, z) of int32 coordinates; for each vector
+ *
+ *   collisions = #{ i < j : bead i and bead j occupy the same site }
+ *   contacts   = #{ i < j : |x_i-x_j| + |y_i-y_j| + |z_i-z_j| == 1 }
+ *
+ * i.e. the pairs on one site and the pairs on sites one unit apart along one
+ * axis.  The paper counts both with an occupancy array over the bounded
+ * lattice in O(n) time; here the occupancy lives in a hash table per vector
+ * (LDS for vectors of at most PAIRS_LATTICE_LDS_BEADS beads, device memory
+ * from the workspace for longer ones), so no bound on the lattice is needed
+ * beyond the domain below.  Counts are exact integers.
+ *
+ * Domain, per vector: at most PAIRS_LATTICE_MAX_BEADS beads, and a bounding
+ * box that, padded by one site on every side, holds fewer than 2^40 sites:
+ * (max x - min x + 3)(max y - min y + 3)(max z - min z + 3) < 2^40.  Any
+ * chain of unit steps shorter than about 30 000 beads is inside.  A vector
+ * outside the domain gets UINT64_MAX in both of its outputs; with
+ * PAIRS_FLAG_VALIDATE the call then waits for the stream and returns
+ * PAIRS_ERR_DOMAIN (box) or PAIRS_ERR_INVALID_ARG (length).
+ *
+ * Workspace: pairs_lattice_workspace_size() bytes of device memory, owned by
+ * the caller; zero bytes (d_ws may be NULL) when every vector has at most
+ * PAIRS_LATTICE_LDS_BEADS beads and the call is told so through max_n.
+ */
+#define PAIRS_LATTICE_LDS_BEADS 4096
+#define PAIRS_LATTICE_MAX_BEADS (((int64_t)1 << 24) - 1)
+
+/* Workspace bytes for a batch whose vectors have at most max_n beads each
+ * (max_n = 0: unknown).  A single vector of n beads is (1, n, n). */
+pairs_status_t pairs_lattice_workspace_size(int64_t n_sets, int64_t n_total, int64_t max_n,
+                                            size_t *bytes);
+
+/* One vector of n beads.  d_collisions, d_contacts: one uint64 each in device
+ * memory; either may be NULL (its pass is skipped: the collision count costs
+ * less alone).  Vectors longer than PAIRS_LATTICE_LDS_BEADS use the whole
+ * grid with the table in the workspace. */
+pairs_status_t pairs_lattice_count(const int32_t *x, const int32_t *y, const int32_t *z,
+                                   int64_t n, uint64_t *d_collisions, uint64_t *d_contacts,
+                                   void *d_ws, size_t ws_bytes, unsigned flags,
+                                   pairs_stream_t stream);
+
+/* A CSR batch of vectors (offsets as for the sphere batches), one workgroup
+ * per vector.  max_n: an upper bound of every vector's length, or 0 if
+ * unknown; it sizes the LDS tables.  A vector longer than a non-zero max_n
+ * is a caller error (UINT64_MAX outputs; PAIRS_ERR_INVALID_ARG under
+ * PAIRS_FLAG_VALIDATE).  d_collisions, d_contacts: uint64[n_sets] each,
+ * either may be NULL. */
+pairs_status_t pairs_lattice_count_batched(const int32_t *x, const int32_t *y, const int32_t *z,
+                                           const int64_t *d_offsets, int64_t n_sets,
+                                           int64_t n_total, int64_t max_n,
+                                           uint64_t *d_collisions, uint64_t *d_contacts,
+                                           void *d_ws, size_t ws_bytes, unsigned flags,
+                                           pairs_stream_t stream);
 
 /* ---------------------------------------------------------- introspection -- */
 /*

@@ -23,6 +23,8 @@ __all__ = [
     "pairs_debug_step_ranges", "FORM_BROADCAST", "FORM_STEPPING",
     "Plan", "Graph", "ShapeTable", "pairs_get_shapes", "pairs_set_shapes",
     "count_i32", "count_f32", "energy_f32",
+    "pairs_lattice_workspace_size", "pairs_lattice_count", "pairs_lattice_count_batched",
+    "LATTICE_LDS_BEADS", "LATTICE_MAX_BEADS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,6 +32,8 @@ _LIB_PATH = os.path.join(_HERE, "libpairs.so")
 _lib = None
 
 FLAG_VALIDATE = 1
+LATTICE_LDS_BEADS = 4096
+LATTICE_MAX_BEADS = (1 << 24) - 1
 KIND_COUNT_I32, KIND_COUNT_F32, KIND_ENERGY_F32 = 1, 2, 3
 
 _STATUS = {
@@ -100,6 +104,10 @@ def _declare(L):
         "pairs_debug_task_ranges": [_int, _int, _int, _vp, _i64, ctypes.POINTER(_i64)],
         "pairs_debug_step_ranges": [_int, _int, _int, _vp, _i64, ctypes.POINTER(_i64)],
         "pairs_get_shapes": [_int, _int, ctypes.POINTER(ShapeTable)],
+        "pairs_lattice_workspace_size": [_i64, _i64, _i64, ctypes.POINTER(_sz)],
+        "pairs_lattice_count": [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _u32, _vp],
+        "pairs_lattice_count_batched": [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _sz,
+                                        _u32, _vp],
         "pairs_set_shapes": [_int, _int, ctypes.POINTER(ShapeTable)],
     }
     for name, args in sig.items():
@@ -273,6 +281,56 @@ def pairs_energy_f32_batched(x, y, z, r, offsets, eps2, energy, counts=None, ws=
                                           n_sets, n_total, float(eps2), _ptr(energy),
                                           _ptr(counts), _ptr(ws), nbytes, flags,
                                           _stream(stream)), "pairs_energy_f32_batched")
+
+
+def pairs_lattice_workspace_size(n_sets: int, n_total: int, max_n: int) -> int:
+    """Bytes of device workspace a lattice call needs (max_n = 0: unknown)."""
+    b = _sz(0)
+    _check(lib().pairs_lattice_workspace_size(n_sets, n_total, max_n, ctypes.byref(b)),
+           "pairs_lattice_workspace_size")
+    return int(b.value)
+
+
+def _lattice_ws(ws, n_sets, n_total, max_n, device):
+    import torch
+    need = pairs_lattice_workspace_size(n_sets, n_total, max_n)
+    if ws is None and need > 0:
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+    return ws, 0 if ws is None else int(ws.numel() * ws.element_size())
+
+
+def pairs_lattice_count(x, y, z, collisions, contacts, ws=None, flags: int = 0,
+                        stream=None) -> None:
+    """Collisions and contacts of one vector of int32 lattice beads into
+    int64[1] tensors (read as uint64); either output may be None."""
+    import torch
+    n = int(x.shape[0])
+    _require((x, y, z), torch.int32, n, "pairs_lattice_count")
+    for t in (collisions, contacts):
+        if t is not None:
+            _require((t,), torch.int64, 1, "pairs_lattice_count outputs")
+    ws, nbytes = _lattice_ws(ws, 1, n, n, x.device)
+    _check(lib().pairs_lattice_count(_ptr(x), _ptr(y), _ptr(z), n, _ptr(collisions),
+                                     _ptr(contacts), _ptr(ws), nbytes, flags, _stream(stream)),
+           "pairs_lattice_count")
+
+
+def pairs_lattice_count_batched(x, y, z, offsets, max_n: int, collisions, contacts, ws=None,
+                                flags: int = 0, stream=None) -> None:
+    """Per-vector collisions and contacts of a CSR batch of lattice bead vectors
+    into int64[n_sets] tensors (read as uint64); either output may be None.
+    max_n bounds every vector's length (0: unknown)."""
+    import torch
+    n_total, n_sets = _batch_checks(x, (x, y, z), torch.int32, offsets,
+                                    "pairs_lattice_count_batched")
+    for t in (collisions, contacts):
+        if t is not None:
+            _require((t,), torch.int64, n_sets, "pairs_lattice_count_batched outputs")
+    ws, nbytes = _lattice_ws(ws, n_sets, n_total, max_n, x.device)
+    _check(lib().pairs_lattice_count_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(offsets), n_sets,
+                                             n_total, max_n, _ptr(collisions), _ptr(contacts),
+                                             _ptr(ws), nbytes, flags, _stream(stream)),
+           "pairs_lattice_count_batched")
 
 
 def pairs_jitter_f32(x, y, z, seed: int, step: int, sigma: float, first_index: int = 0,

@@ -9,6 +9,7 @@
 //                per-class prefix sums built on the device by one scheduling
 //                kernel, searched by each wave;
 //   jitter     : the per-step perturbation of the repeated-step workload;
+//   lattice    : collision and contact counts of lattice beads (lattice.h);
 //   helpers    : fills (in place of memsets, so every launch can be
 //                captured into a graph), validation.
 #include <hip/hip_runtime.h>
@@ -28,6 +29,7 @@
 
 #include "band.h"
 #include "device.h"
+#include "lattice.h"
 #include "pairs.h"
 #include "steps.h"
 #include "tasks.h"
@@ -1006,6 +1008,100 @@ pairs_status_t batched_args(const void *x, const void *y, const void *z,
     return PAIRS_OK;
 }
 
+// ---------------------------------------------------------- lattice beads --
+
+namespace lat = pairs_lattice;
+
+size_t lattice_ws_bytes(int64_t n_total, int64_t max_n) {
+    if (max_n > 0 && max_n <= lat::kMaxLdsBeads) return 0;
+    return 256 + 32 * (size_t)n_total;
+}
+
+// Beads per thread and table size of the LDS kernel for vectors of at most m beads.
+int lattice_bpt(int64_t m) {
+    int b = 1;
+    while (b < lat::kMaxBpt && (int64_t)b * lat::kBlock < m) b *= 2;
+    return b;
+}
+
+int lattice_tlog(int64_t m) {
+    int l = lat::kMinLog;
+    while (l < lat::kMaxLog && (int64_t(1) << (l - 1)) < m) ++l;
+    return l;
+}
+
+template <bool C, typename F>
+void with_lattice_kernels(int bpt, F f) {
+    switch (bpt) {
+        case 1: f(lat::k_lattice_near<1, C>, lat::k_lattice<1, C, uint64_t>); break;
+        case 2: f(lat::k_lattice_near<2, C>, lat::k_lattice<2, C, uint64_t>); break;
+        case 4: f(lat::k_lattice_near<4, C>, lat::k_lattice<4, C, uint64_t>); break;
+        case 8: f(lat::k_lattice_near<8, C>, lat::k_lattice<8, C, uint64_t>); break;
+        default: f(lat::k_lattice_near<16, C>, lat::k_lattice<16, C, uint64_t>); break;
+    }
+}
+
+// The status word the lattice kernels raise bits in: the validation word
+// under PAIRS_FLAG_VALIDATE (cleared first), else a word nobody reads.
+pairs_status_t lattice_flag(DeviceState *st, bool validate, hipStream_t s, int **flag) {
+    if (validate) {
+        k_fill_u64<<<1, 1, 0, s>>>((uint64_t *)st->d_flag, 1, 0);
+        PAIRS_HIP_CHECK(hipGetLastError());
+        *flag = st->d_flag;
+    } else {
+        *flag = st->d_flag + 16;
+    }
+    return PAIRS_OK;
+}
+
+pairs_status_t lattice_status(DeviceState *st, hipStream_t s) {
+    int bad = 0;
+    PAIRS_HIP_CHECK(hipMemcpyAsync(&bad, st->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    PAIRS_HIP_CHECK(hipStreamSynchronize(s));
+    if (bad & lat::kFlagDomain) return PAIRS_ERR_DOMAIN;
+    return bad ? PAIRS_ERR_INVALID_ARG : PAIRS_OK;
+}
+
+// LDS kernel over every vector of at most m beads; `defer` leaves longer
+// vectors to k_lattice_global.
+pairs_status_t lattice_lds(const lat::IO &io, int64_t m, bool defer, const DeviceState *st,
+                           hipStream_t s) {
+    const int bpt = lattice_bpt(m), tlog = lattice_tlog(m);
+    const size_t lds = sizeof(uint64_t) << tlog;
+    // the near pass sums into the outputs with atomics
+    PAIRS_TRY(fill_u64(io.coll, io.n_sets, 0, s));
+    PAIRS_TRY(fill_u64(io.cont, io.n_sets, 0, s));
+    auto grid = [&](auto kern) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, lat::kBlock, lds) !=
+                hipSuccess ||
+            per_cu <= 0)
+            per_cu = 1;
+        const int64_t resident = (int64_t)per_cu * (st->n_cu > 0 ? st->n_cu : 1);
+        return (unsigned)std::min<int64_t>(io.n_sets, resident * 4);
+    };
+    // keys relative to the first bead for every vector whose beads stay near
+    // it, then box-based 64-bit keys for the vectors the first pass marked
+    auto launch = [&](auto near, auto wide) {
+        near<<<grid(near), lat::kBlock, lds, s>>>(io, tlog, defer ? 1 : 0);
+        wide<<<grid(wide), lat::kBlock, lds, s>>>(io, tlog, defer ? 1 : 0);
+    };
+    if (io.cont)
+        with_lattice_kernels<true>(bpt, launch);
+    else
+        with_lattice_kernels<false>(bpt, launch);
+    PAIRS_HIP_CHECK(hipGetLastError());
+    return PAIRS_OK;
+}
+
+pairs_status_t lattice_args(const int32_t *x, const int32_t *y, const int32_t *z,
+                            uint64_t *coll, uint64_t *cont, int64_t n_total, unsigned flags) {
+    if (n_total < 0 || (flags & ~PAIRS_FLAG_VALIDATE)) return PAIRS_ERR_INVALID_ARG;
+    if (n_total > 0 && (!x || !y || !z)) return PAIRS_ERR_INVALID_ARG;
+    if (!coll && !cont) return PAIRS_ERR_INVALID_ARG;
+    return PAIRS_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------- plans --
@@ -1628,6 +1724,83 @@ pairs_status_t pairs_debug_task_ranges(int n, int rows_per_lane, int chunk, int3
             out[3 * k + 2] = u1;
         }
     return PAIRS_OK;
+}
+
+pairs_status_t pairs_lattice_workspace_size(int64_t n_sets, int64_t n_total, int64_t max_n,
+                                            size_t *bytes) {
+    if (!bytes || n_sets < 0 || n_total < 0 || max_n < 0) return PAIRS_ERR_INVALID_ARG;
+    *bytes = lattice_ws_bytes(n_total, max_n);
+    return PAIRS_OK;
+}
+
+pairs_status_t pairs_lattice_count(const int32_t *x, const int32_t *y, const int32_t *z,
+                                   int64_t n, uint64_t *d_collisions, uint64_t *d_contacts,
+                                   void *d_ws, size_t ws_bytes, unsigned flags,
+                                   pairs_stream_t stream) {
+    PAIRS_TRY(lattice_args(x, y, z, d_collisions, d_contacts, n, flags));
+    if (n > PAIRS_LATTICE_MAX_BEADS) return PAIRS_ERR_INVALID_ARG;
+    const bool global = n > lat::kMaxLdsBeads;
+    if (global && (!d_ws || ws_bytes < lattice_ws_bytes(n, n))) return PAIRS_ERR_WORKSPACE;
+    DeviceState *st;
+    PAIRS_TRY(device_state(&st));
+    hipStream_t s = (hipStream_t)stream;
+    const bool validate = flags & PAIRS_FLAG_VALIDATE;
+    lat::IO io{x, y, z, nullptr, 1, n, d_collisions, d_contacts, nullptr};
+    PAIRS_TRY(lattice_flag(st, validate, s, &io.flag));
+    if (!global) {
+        PAIRS_TRY(lattice_lds(io, std::max<int64_t>(n, 2), false, st, s));
+    } else {
+        int tlog = 1;
+        while ((int64_t(1) << tlog) < 2 * n) ++tlog;
+        lat::SingleState *g = (lat::SingleState *)d_ws;
+        uint64_t *table = (uint64_t *)((unsigned char *)d_ws + 256);
+        const unsigned blocks =
+            (unsigned)std::min<int64_t>(blocks_for(n, lat::kBlock), (int64_t)st->n_cu * 8);
+        const unsigned clear_blocks = (unsigned)std::min<int64_t>(
+            blocks_for(int64_t(1) << tlog, lat::kBlock), (int64_t)st->n_cu * 8);
+        lat::k_lattice_single_init<<<1, 64, 0, s>>>(g, d_collisions, d_contacts);
+        lat::k_lattice_single_box<<<blocks, lat::kBlock, 0, s>>>(io, g);
+        lat::k_lattice_single_clear<<<clear_blocks, lat::kBlock, 0, s>>>(io, g, table, tlog);
+        lat::k_lattice_single_pass<false><<<blocks, lat::kBlock, 0, s>>>(io, g, table, tlog);
+        if (d_contacts)
+            lat::k_lattice_single_pass<true><<<blocks, lat::kBlock, 0, s>>>(io, g, table, tlog);
+        PAIRS_HIP_CHECK(hipGetLastError());
+    }
+    return validate ? lattice_status(st, s) : PAIRS_OK;
+}
+
+pairs_status_t pairs_lattice_count_batched(const int32_t *x, const int32_t *y, const int32_t *z,
+                                           const int64_t *d_offsets, int64_t n_sets,
+                                           int64_t n_total, int64_t max_n,
+                                           uint64_t *d_collisions, uint64_t *d_contacts,
+                                           void *d_ws, size_t ws_bytes, unsigned flags,
+                                           pairs_stream_t stream) {
+    PAIRS_TRY(batched_args(x, y, z, d_offsets, n_sets, n_total, flags));
+    PAIRS_TRY(lattice_args(x, y, z, d_collisions, d_contacts, n_total, flags));
+    if (max_n < 0) return PAIRS_ERR_INVALID_ARG;
+    const bool global = max_n == 0 || max_n > lat::kMaxLdsBeads;
+    if (global && (!d_ws || ws_bytes < lattice_ws_bytes(n_total, max_n)))
+        return PAIRS_ERR_WORKSPACE;
+    DeviceState *st;
+    PAIRS_TRY(device_state(&st));
+    hipStream_t s = (hipStream_t)stream;
+    const bool validate = flags & PAIRS_FLAG_VALIDATE;
+    if (validate) PAIRS_TRY(validate_offsets(d_offsets, n_sets, n_total, s));
+    if (n_sets == 0) return PAIRS_OK;
+    lat::IO io{x, y, z, d_offsets, n_sets, n_total, d_collisions, d_contacts, nullptr};
+    PAIRS_TRY(lattice_flag(st, validate, s, &io.flag));
+    const int64_t m = global ? lat::kMaxLdsBeads : std::max<int64_t>(max_n, 2);
+    PAIRS_TRY(lattice_lds(io, m, global, st, s));
+    if (global) {
+        const unsigned blocks = (unsigned)std::min<int64_t>(n_sets, (int64_t)st->n_cu * 4);
+        uint64_t *table = (uint64_t *)((unsigned char *)d_ws + 256);
+        if (d_contacts)
+            lat::k_lattice_global<true><<<blocks, lat::kBlock, 0, s>>>(io, table);
+        else
+            lat::k_lattice_global<false><<<blocks, lat::kBlock, 0, s>>>(io, table);
+        PAIRS_HIP_CHECK(hipGetLastError());
+    }
+    return validate ? lattice_status(st, s) : PAIRS_OK;
 }
 
 const char *pairs_status_string(pairs_status_t s) {

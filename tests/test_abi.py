@@ -126,3 +126,33 @@ def test_comparison_library_exports_and_checks_arguments():
     assert f(0, None, y, z, r, 10, 1, out, None) == -1   # missing input
     assert f(1, x, y, z, r, 10, 1, None, None) == -1     # missing output
     assert f(1, x, y, z, r, -1, 1, out, None) == -1
+
+
+def test_lattice_arguments_are_rejected_on_the_host():
+    L = P.lib()
+    x, y, z, c, k, ws, off = (fake(k) for k in range(7))
+    n_sz = ctypes.c_size_t(0)
+    assert L.pairs_lattice_workspace_size(1, 100, -1, ctypes.byref(n_sz)) == INVALID
+    assert L.pairs_lattice_workspace_size(1, 100, 100, ctypes.byref(n_sz)) == OK
+    assert n_sz.value == 0
+    assert L.pairs_lattice_workspace_size(1, 5000, 5000, ctypes.byref(n_sz)) == OK
+    assert n_sz.value >= 32 * 5000
+    # single vector: bad length, no outputs, bad flags, missing workspace
+    assert L.pairs_lattice_count(x, y, z, -1, c, k, None, 0, 0, None) == INVALID
+    assert L.pairs_lattice_count(x, y, z, 10, None, None, None, 0, 0, None) == INVALID
+    assert L.pairs_lattice_count(None, y, z, 10, c, k, None, 0, 0, None) == INVALID
+    assert L.pairs_lattice_count(x, y, z, 10, c, k, None, 0, 0x10, None) == INVALID
+    assert L.pairs_lattice_count(x, y, z, 1 << 24, c, k, ws, 1 << 40, 0, None) == INVALID
+    assert L.pairs_lattice_count(x, y, z, 5000, c, k, None, 0, 0, None) == WORKSPACE
+    assert L.pairs_lattice_count(x, y, z, 5000, c, k, ws, 1000, 0, None) == WORKSPACE
+    # batches: negative bound, missing offsets, unknown bound without workspace
+    assert L.pairs_lattice_count_batched(x, y, z, off, 2, 10, -1, c, k, None, 0, 0,
+                                         None) == INVALID
+    assert L.pairs_lattice_count_batched(x, y, z, None, 2, 10, 5, c, k, None, 0, 0,
+                                         None) == INVALID
+    assert L.pairs_lattice_count_batched(x, y, z, off, 2, 10, 5, None, None, None, 0, 0,
+                                         None) == INVALID
+    assert L.pairs_lattice_count_batched(x, y, z, off, 2, 10, 0, c, k, None, 0, 0,
+                                         None) == WORKSPACE
+    assert L.pairs_lattice_count_batched(x, y, z, off, 2, 10, 5000, c, k, ws, 64, 0,
+                                         None) == WORKSPACE

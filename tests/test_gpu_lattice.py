@@ -1,0 +1,201 @@
+"""Lattice-bead collision and contact counts on the GPU (Section 3) against
+the CPU oracle's plain pairwise definition, bit for bit.
+
+Covers the LDS path at every table size (ragged vector lengths around the
+thread and table boundaries), the batched global path for vectors longer than
+the LDS tables, the single-vector grid-wide path, optional outputs, extreme
+coordinates, the domain and length errors, and the paper's own scale (1000
+chains of 1920 beads)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1901_11204_amd as P
+import workloads as w
+from gpu_util import announce, dev
+
+pytestmark = pytest.mark.gpu
+
+BAD = -1  # UINT64_MAX read back as int64
+
+
+def run_batched(b, max_n, want=(True, True), flags=0):
+    import torch
+    x, y, z = dev(*b.objs.arrays())
+    off, = dev(b.offsets)
+    coll = torch.full((b.n_sets,), 7, dtype=torch.int64, device="cuda") if want[0] else None
+    cont = torch.full((b.n_sets,), 7, dtype=torch.int64, device="cuda") if want[1] else None
+    P.pairs_lattice_count_batched(x, y, z, off, max_n, coll, cont, flags=flags)
+    torch.cuda.synchronize()
+    return (None if coll is None else coll.cpu().numpy().astype(np.uint64),
+            None if cont is None else cont.cpu().numpy().astype(np.uint64))
+
+
+def run_single(arrays, want=(True, True), flags=0):
+    import torch
+    x, y, z = dev(*arrays)
+    coll = torch.full((1,), 7, dtype=torch.int64, device="cuda") if want[0] else None
+    cont = torch.full((1,), 7, dtype=torch.int64, device="cuda") if want[1] else None
+    P.pairs_lattice_count(x, y, z, coll, cont, flags=flags)
+    torch.cuda.synchronize()
+    return (None if coll is None else int(coll.item()), None if cont is None else int(cont.item()))
+
+
+RAGGED = [0, 1, 2, 3, 4, 31, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1000,
+          1023, 1024, 1025, 1920, 2047, 2048, 2049, 3000, 4095, 4096]
+
+
+@pytest.mark.parametrize("max_n", ["exact", 0, 4096])
+def test_batched_walks_ragged(max_n):
+    b = w.lattice_walks(len(RAGGED), RAGGED, 21)
+    m = max(RAGGED) if max_n == "exact" else max_n
+    announce("lattice batched ragged", max_n)
+    coll, cont = run_batched(b, m)
+    c0, c1 = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets)
+    np.testing.assert_array_equal(coll, c0)
+    np.testing.assert_array_equal(cont, c1)
+
+
+@pytest.mark.parametrize("n,max_n", [(16, 16), (128, 128), (200, 256), (768, 768),
+                                     (1920, 1920), (1920, 4000)])
+def test_batched_table_sizes(n, max_n):
+    # every (beads per thread, table size) pair the host picks
+    b = w.lattice_walks(300, n, 1000 + n)
+    announce("lattice batched", n, max_n)
+    coll, cont = run_batched(b, max_n)
+    c0, c1 = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets)
+    np.testing.assert_array_equal(coll, c0)
+    np.testing.assert_array_equal(cont, c1)
+
+
+@pytest.mark.parametrize("sigma", [0.6, 2.0, 20.0])
+def test_batched_normal_coordinates(sigma):
+    # dense clouds: many beads per site, long probe sequences
+    b = w.lattice_normal(100, 1500, sigma, 31)
+    announce("lattice normal", sigma)
+    coll, cont = run_batched(b, 1500)
+    c0, c1 = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets)
+    np.testing.assert_array_equal(coll, c0)
+    np.testing.assert_array_equal(cont, c1)
+
+
+def test_one_output_only():
+    b = w.lattice_walks(64, 700, 5)
+    c0, c1 = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets)
+    announce("lattice collisions only")
+    coll, cont = run_batched(b, 700, want=(True, False))
+    assert cont is None
+    np.testing.assert_array_equal(coll, c0)
+    announce("lattice contacts only")
+    coll, cont = run_batched(b, 700, want=(False, True))
+    np.testing.assert_array_equal(cont, c1)
+
+
+def test_batched_long_vectors_global_path():
+    sizes = [5000, 100, 12000, 4097, 3, 0, 9000]
+    b = w.lattice_walks(len(sizes), sizes, 8)
+    c0, c1 = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets)
+    for want in [(True, True), (True, False)]:
+        announce("lattice batched global", want)
+        coll, cont = run_batched(b, 0, want=want)
+        np.testing.assert_array_equal(coll, c0)
+        if want[1]:
+            np.testing.assert_array_equal(cont, c1)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 100, 4096, 4097, 30000])
+def test_single_vector(n):
+    b = w.lattice_walks(1, n, 40 + n)
+    a = b.objs.arrays()
+    announce("lattice single", n)
+    assert run_single(a) == oracle.lattice_counts(*a)
+
+
+def test_single_vector_global_one_output():
+    b = w.lattice_normal(1, 20000, 5.0, 3)
+    a = b.objs.arrays()
+    want = oracle.lattice_counts(*a)
+    announce("lattice single global collisions only")
+    assert run_single(a, want=(True, False))[0] == want[0]
+    announce("lattice single global contacts only")
+    assert run_single(a, want=(False, True))[1] == want[1]
+
+
+def test_extreme_coordinates():
+    # chains translated next to both ends of int32; only the box matters
+    b = w.lattice_walks(4, 900, 12)
+    x, y, z = (v.astype(np.int64) for v in b.objs.arrays())
+    shift = [(2 ** 31 - 1 - 1000, 0, 0), (-2 ** 31 + 1000, 2 ** 31 - 1000, 5),
+             (0, -2 ** 31 + 1000, 2 ** 31 - 1000), (123, -456, 789)]
+    xs, ys, zs = x.copy(), y.copy(), z.copy()
+    for s, (a, c, d) in enumerate(shift):
+        sl = slice(b.offsets[s], b.offsets[s + 1])
+        xs[sl] += a
+        ys[sl] += c
+        zs[sl] += d
+    arrs = [v.astype(np.int32) for v in (xs, ys, zs)]
+    bb = w.Batch(b.offsets, w.Beads(*arrs))
+    announce("lattice extreme coordinates")
+    coll, cont = run_batched(bb, 900)
+    c0, c1 = oracle.lattice_counts_batched(*arrs, b.offsets)
+    np.testing.assert_array_equal(coll, c0)
+    np.testing.assert_array_equal(cont, c1)
+
+
+def test_domain_and_length_errors():
+    import torch
+    # vector 1 spans 2^31 on every axis: its padded box exceeds 2^40 sites
+    good = w.lattice_walks(1, 50, 1)
+    gx, gy, gz = good.objs.arrays()
+    far = np.array([-2 ** 30, 2 ** 30, 0, 7], np.int32)
+    x = np.concatenate([gx, far, gx])
+    y = np.concatenate([gy, far, gy])
+    z = np.concatenate([gz, far[::-1].copy(), gz])
+    off = np.array([0, 50, 54, 104], np.int64)
+    b = w.Batch(off, w.Beads(x, y, z))
+    announce("lattice domain error")
+    coll, cont = run_batched(b, 64)
+    want = oracle.lattice_counts(gx, gy, gz)
+    assert (int(coll[0]), int(cont[0])) == want and (int(coll[2]), int(cont[2])) == want
+    assert coll[1] == np.uint64(2 ** 64 - 1) and cont[1] == np.uint64(2 ** 64 - 1)
+    with pytest.raises(P.PairsError) as e:
+        run_batched(b, 64, flags=P.FLAG_VALIDATE)
+    assert e.value.status == -2
+    # a vector longer than the max_n the call was given
+    b2 = w.lattice_walks(3, [100, 300, 100], 2)
+    announce("lattice length error")
+    coll, cont = run_batched(b2, 100)
+    assert coll[1] == np.uint64(2 ** 64 - 1)
+    c0, _ = oracle.lattice_counts_batched(*b2.objs.arrays(), b2.offsets)
+    assert coll[0] == c0[0] and coll[2] == c0[2]
+    with pytest.raises(P.PairsError) as e:
+        run_batched(b2, 100, flags=P.FLAG_VALIDATE)
+    assert e.value.status == -1
+    # a valid batch passes validation
+    announce("lattice validate ok")
+    coll, cont = run_batched(good, 50, flags=P.FLAG_VALIDATE)
+    assert (int(coll[0]), int(cont[0])) == want
+    torch.cuda.synchronize()
+
+
+def test_paper_scale_1000_chains_of_1920():
+    # the linear-time experiments count 1000 bead vectors per execution,
+    # up to 1920 beads each (Section 5)
+    b = w.lattice_walks(1000, 1920, 77)
+    announce("lattice paper scale")
+    coll, cont = run_batched(b, 1920)
+    c0, c1 = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets)
+    np.testing.assert_array_equal(coll, c0)
+    np.testing.assert_array_equal(cont, c1)
+
+
+def test_repeated_calls_reuse_nothing():
+    # a second call on other data must not see the first call's tables
+    b1 = w.lattice_normal(50, 2000, 1.0, 1)
+    b2 = w.lattice_walks(50, 2000, 2)
+    announce("lattice repeated")
+    run_batched(b1, 2000)
+    coll, cont = run_batched(b2, 2000)
+    c0, c1 = oracle.lattice_counts_batched(*b2.objs.arrays(), b2.offsets)
+    np.testing.assert_array_equal(coll, c0)
+    np.testing.assert_array_equal(cont, c1)
