@@ -205,6 +205,50 @@ PAPER_CONTEXT = {
 }
 
 
+HBM_PEAK = 8.0e12  # bytes per second
+LATTICE_BYTES_PER_BEAD = 12  # three int32 coordinates, read once
+
+
+def bench_lattice(P, w, torch, np, dev, steps):
+    """Lattice-bead collision and contact counts (Section 3): the paper's batch of
+    1000 chains of 1920 beads, and 65536 such chains for throughput.  The
+    per-vector counts are checked against the oracle's stored values."""
+    def sha(t):
+        return hashlib.sha256(t.cpu().numpy().astype("<u8").tobytes()).hexdigest()
+
+    out = {}
+    for name, make, key, nsteps in [("paper_1000x1920", w.lattice_paper, "lattice_paper_counts", 50),
+                                    ("large_65536x1920", w.lattice_large, "lattice_large_counts",
+                                     max(3, steps))]:
+        b = make()
+        log(f"[bench] lattice {name}: {b.n_sets} chains, {b.n_total} beads")
+        x, y, z = (torch.from_numpy(v).to(dev) for v in b.objs.arrays())
+        off = torch.from_numpy(b.offsets).to(dev)
+        coll = torch.empty(b.n_sets, dtype=torch.int64, device=dev)
+        cont = torch.empty_like(coll)
+        ms, _ = timed_steps(lambda: P.pairs_lattice_count_batched(x, y, z, off, 1920, coll, cont),
+                            nsteps, 3)
+        m = float(np.median(ms))
+        ms1, _ = timed_steps(lambda: P.pairs_lattice_count_batched(x, y, z, off, 1920, coll, None),
+                             nsteps, 3)
+        P.pairs_lattice_count_batched(x, y, z, off, 1920, coll, cont)
+        g = golden()[key]
+        beads = b.n_total
+        gbs = beads * LATTICE_BYTES_PER_BEAD / (m * 1e-3)
+        out[name] = {
+            "workload": f"{b.n_sets} random chains of 1920 unit steps from the origin on Z^3",
+            "beads": beads, "ms": m, "G_beads_per_s": beads / m / 1e6,
+            "ms_collisions_only": float(np.median(ms1)),
+            "roofline": {"bound": "hbm", "achieved": gbs / 1e9, "peak": HBM_PEAK / 1e9,
+                         "unit": "GB/s", "frac": gbs / HBM_PEAK,
+                         "bytes_per_bead": LATTICE_BYTES_PER_BEAD},
+            "collisions_total": int(coll.sum().item()), "contacts_total": int(cont.sum().item()),
+            "matches_oracle": sha(coll) == g["collisions_sha256_le_u64"]
+                              and sha(cont) == g["contacts_sha256_le_u64"]}
+        del x, y, z, off, coll, cont
+    return out
+
+
 def graph_per_call(torch, P, t, out, calls):
     """Per-call time of the small-set count when `calls` calls are captured in
     one HIP graph (the calls allocate nothing and synchronise nothing)."""
@@ -452,6 +496,7 @@ def main():
                                                                    max(2, a.steps // 2))
         rec["secondary"] = sec
         rec["batched"] = bench_batched(P, w, torch, np, dev, a.steps)
+        rec["lattice"] = bench_lattice(P, w, torch, np, dev, a.steps)
 
     if not a.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle on {a.cpu_sample} spheres")

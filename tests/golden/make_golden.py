@@ -41,11 +41,18 @@ def compute(key, threads):
         return {"total": int(c.sum()),
                 "sha256_le_u64": hashlib.sha256(c.astype("<u8").tobytes()).hexdigest(),
                 "first16": [int(v) for v in c[:16]]}
+    if key in ("lattice_paper_counts", "lattice_large_counts"):
+        b = w.lattice_paper() if key == "lattice_paper_counts" else w.lattice_large()
+        coll, cont = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets, threads=threads)
+        return {"collisions_total": int(coll.sum()), "contacts_total": int(cont.sum()),
+                "collisions_sha256_le_u64": hashlib.sha256(coll.astype("<u8").tobytes()).hexdigest(),
+                "contacts_sha256_le_u64": hashlib.sha256(cont.astype("<u8").tobytes()).hexdigest(),
+                "first8": [[int(a), int(c)] for a, c in zip(coll[:8], cont[:8])]}
     raise KeyError(key)
 
 
 KEYS = ["config1_count", "config4_counts", "config3_energy_total", "config2_odd_count",
-        "config2_even_count"]
+        "config2_even_count", "lattice_paper_counts", "lattice_large_counts"]
 
 
 def main():

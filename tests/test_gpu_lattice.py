@@ -199,3 +199,46 @@ def test_repeated_calls_reuse_nothing():
     c0, c1 = oracle.lattice_counts_batched(*b2.objs.arrays(), b2.offsets)
     np.testing.assert_array_equal(coll, c0)
     np.testing.assert_array_equal(cont, c1)
+
+
+def test_large_workload_matches_stored_oracle_values(golden_dir):
+    # 65536 chains of 1920 beads; the expected per-vector counts were written
+    # by tests/golden/make_golden.py from the oracle
+    import hashlib
+    import json
+    import os
+    with open(os.path.join(golden_dir, "config_values.json")) as f:
+        g = json.load(f)["lattice_large_counts"]
+    b = w.lattice_large()
+    announce("lattice large stored values")
+    coll, cont = run_batched(b, 1920)
+    assert hashlib.sha256(coll.astype("<u8").tobytes()).hexdigest() == g["collisions_sha256_le_u64"]
+    assert hashlib.sha256(cont.astype("<u8").tobytes()).hexdigest() == g["contacts_sha256_le_u64"]
+
+
+@pytest.mark.parametrize("want", [(True, True), (True, False), (False, True)])
+def test_far_vectors_take_the_box_pass(want):
+    # beads more than ~1000 sites from their vector's first bead cannot use
+    # the near keys; such vectors are recounted with box-based 64-bit keys.
+    # Mixed with near vectors, and with either output alone (the marker then
+    # lives in the other output).
+    near = w.lattice_walks(20, 700, 4)
+    # sigma 800: beads thousands of sites from the first one, while the box
+    # stays inside the 2^40-site domain
+    far = w.lattice_normal(20, 700, 800.0, 5)
+    dense_far = w.lattice_normal(20, 700, 1.5, 6)
+    for v in dense_far.objs.arrays():
+        v += 50_000  # a dense cloud whose first bead is an outlier
+    for v, s in zip(dense_far.objs.arrays(), (-40_000, 0, 40_000)):
+        v[dense_far.offsets[:-1]] += s
+    parts = [near, far, dense_far]
+    arrs = [np.concatenate([p.objs.arrays()[a] for p in parts]) for a in range(3)]
+    sizes = np.concatenate([np.diff(p.offsets) for p in parts])
+    b = w.Batch(w.offsets_from_sizes(sizes), w.Beads(*arrs))
+    announce("lattice far vectors", want)
+    coll, cont = run_batched(b, 700, want=want)
+    c0, c1 = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets)
+    if want[0]:
+        np.testing.assert_array_equal(coll, c0)
+    if want[1]:
+        np.testing.assert_array_equal(cont, c1)

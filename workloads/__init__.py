@@ -24,7 +24,7 @@ __all__ = [
     "spheres_i32", "particles_f32",
     "config1", "config2", "config3", "config4", "config5",
     "lognormal_sizes", "offsets_from_sizes",
-    "Beads", "lattice_walks", "lattice_normal",
+    "Beads", "lattice_walks", "lattice_normal", "lattice_paper", "lattice_large",
 ]
 
 
@@ -202,3 +202,15 @@ def lattice_normal(n_vectors: int, n_beads: int, sigma: float, seed: int) -> Bat
     off = offsets_from_sizes(sizes)
     xyz = np.rint(rng.normal(0.0, sigma, (int(off[-1]), 3))).astype(np.int32)
     return Batch(off, Beads(*_soa(xyz)))
+
+
+def lattice_paper(seed: int = 7) -> Batch:
+    """1000 chains of 1920 beads: the batch size and the largest chain length of
+    the paper's linear-time counting experiments."""
+    return lattice_walks(1000, 1920, seed)
+
+
+def lattice_large(seed: int = 8) -> Batch:
+    """65536 chains of 1920 beads (126 M beads, 1.5 GB of int32 coordinates): the
+    throughput workload of the lattice counts."""
+    return lattice_walks(65536, 1920, seed)
