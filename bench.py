@@ -121,8 +121,9 @@ def valu_probe(torch):
         if name.startswith("lds_"):
             # lane reads -> wave-wide reads per clock per CU, and bytes
             per_clk = rate / 64 / N_CU / SCLK_HZ
-            out[name] = {"ms": ms.value, "wave_reads_per_clk_per_cu": per_clk,
-                         "bytes_per_clk_per_cu": per_clk * 64 * (16 if "b128" in name else 8)}
+            width = 16 if "b128" in name else 4 if "b32" in name else 8
+            out[name] = {"ms": ms.value, "wave_ops_per_clk_per_cu": per_clk,
+                         "bytes_per_clk_per_cu": per_clk * 64 * width}
         else:
             out[name] = {"ms": ms.value, "T_lane_ops_per_s": rate / 1e12,
                          "frac_of_peak": rate / VALU_PEAK}

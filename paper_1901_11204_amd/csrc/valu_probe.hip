@@ -9,7 +9,8 @@
 // The LDS probes time wave-wide reads of 8 or 16 bytes per lane, every lane
 // at one address (a broadcast) or at consecutive addresses (a gather), with
 // one three-input add per 8 bytes to consume the data; their "lane
-// operations" are lane reads.
+// operations" are lane reads.  The random-address LDS probes time the reads
+// and atomics of a hash table.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -131,6 +132,42 @@ __global__ __launch_bounds__(256) void p_lds_read(uint32_t *out) {
     if (acc == 0x12345678u) out[threadIdx.x] = acc;
 }
 
+// Random-address LDS operations, as a hash table makes them: Mode 0 a
+// 16-byte read, 1 a 32-bit atomic add returning the old value, 2 a 32-bit
+// compare-and-swap (whose compare mostly fails), 3 a 32-bit atomic add
+// without return.  Each lane draws its addresses from its own xorshift
+// sequence; eight independent operations per step.  Indices stay inside the
+// 32 KB buffer (masked).
+template <int Mode>
+__global__ __launch_bounds__(256) void p_lds_rand(uint32_t *out) {
+    __shared__ __align__(16) uint32_t buf[kLdsWords];
+    for (int i = threadIdx.x; i < kLdsWords; i += 256) buf[i] = i * 2654435761u;
+    __syncthreads();
+    uint32_t h = (threadIdx.x + 1) * 0x9E3779B1u ^ (blockIdx.x * 0x85EBCA6Bu);
+    uint32_t acc = 0;
+    for (int it = 0; it < kLdsIters; ++it) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            h ^= h << 13;
+            h ^= h >> 17;
+            h ^= h << 5;
+            if (Mode == 0) {
+                const u4 v = *(const u4 *)&buf[4 * ((h >> 8) & (kLdsWords / 4 - 1))];
+                acc = acc + v.x + v.y;
+                acc = acc + v.z + v.w;
+            } else if (Mode == 1) {
+                acc += atomicAdd(&buf[(h >> 8) & (kLdsWords - 1)], 1u);
+            } else if (Mode == 2) {
+                acc += atomicCAS(&buf[(h >> 8) & (kLdsWords - 1)], 0x12345u, h);
+            } else {
+                atomicAdd(&buf[(h >> 8) & (kLdsWords - 1)], 1u);
+            }
+        }
+    }
+    if (Mode == 3) acc = buf[threadIdx.x];
+    if (acc == 0x12345678u) out[threadIdx.x] = acc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -138,7 +175,8 @@ extern "C" {
 // Probe names in order; pattern instruction counts per chain step.
 const char *valu_probe_names =
     "fma_f64,fma_f32,rsq_f32,fma3_rsq_f32,count_f64,mad_u64_u32,"
-    "lds_bcast_b128,lds_gather_b128,lds_bcast_b64,lds_gather_b64";
+    "lds_bcast_b128,lds_gather_b128,lds_bcast_b64,lds_gather_b64,"
+    "lds_rand_b128,lds_rand_add_rtn_b32,lds_rand_cas_b32,lds_rand_add_b32";
 
 // Runs probe `which` once (after one warm-up) on blocks x 256 threads and
 // returns its duration in milliseconds in *ms and the number of lane
@@ -165,6 +203,10 @@ int valu_probe_run(int which, int blocks, double *ms, double *lane_ops) {
             case 7: p_lds_read<1><<<blocks, 256>>>((uint32_t *)buf); per_lane = kLdsIters * 8; break;
             case 8: p_lds_read<2><<<blocks, 256>>>((uint32_t *)buf); per_lane = kLdsIters * 8; break;
             case 9: p_lds_read<3><<<blocks, 256>>>((uint32_t *)buf); per_lane = kLdsIters * 8; break;
+            case 10: p_lds_rand<0><<<blocks, 256>>>((uint32_t *)buf); per_lane = kLdsIters * 8; break;
+            case 11: p_lds_rand<1><<<blocks, 256>>>((uint32_t *)buf); per_lane = kLdsIters * 8; break;
+            case 12: p_lds_rand<2><<<blocks, 256>>>((uint32_t *)buf); per_lane = kLdsIters * 8; break;
+            case 13: p_lds_rand<3><<<blocks, 256>>>((uint32_t *)buf); per_lane = kLdsIters * 8; break;
             default: (void)hipFree(buf); return (int)hipErrorInvalidValue;
         }
         (void)hipEventRecord(e1);
