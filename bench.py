@@ -374,6 +374,8 @@ def main():
                     help="only measure the VALU issue rate of the kernels' instruction patterns")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the batched lines (for profiling their kernels)")
+    ap.add_argument("--lattice-only", action="store_true",
+                    help="only the lattice-bead counts (for profiling)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
@@ -405,6 +407,9 @@ def main():
 
     if a.batched_only:
         print(json.dumps({"batched": bench_batched(P, w, torch, np, dev, a.steps)}), flush=True)
+        return
+    if a.lattice_only:
+        print(json.dumps({"lattice": bench_lattice(P, w, torch, np, dev, a.steps)}), flush=True)
         return
 
     # headline workload
