@@ -56,6 +56,9 @@ def lib():
                                                                ctypes.c_void_p, ctypes.c_void_p,
                                                                _INT]
     L.oracle_energy_count_f32_batched.restype = None
+    L.oracle_force_rows.argtypes = [_f32p] * 3 + [_I64, ctypes.c_float, ctypes.c_void_p, _I64,
+                                             _f64p, _f64p, _f64p, _f64p, _INT]
+    L.oracle_force_rows.restype = None
     L.oracle_lattice_batched.argtypes = [_i32p] * 3 + [_i64p, _I64, _u64p, _u64p, _INT]
     L.oracle_lattice_batched.restype = None
     L.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
@@ -117,6 +120,23 @@ def energy_rows(x, y, z, eps2=np.float32(1e-4), rows=None, threads: int = 0) -> 
                                  rows.ctypes.data_as(ctypes.c_void_p), rows.shape[0], out,
                                  threads)
     return out
+
+
+def force_rows(x, y, z, eps2=np.float32(1e-4), rows=None, threads: int = 0):
+    """Forces of the softened potential on the given rows (all if None):
+    (F, S) with F float64[m, 3], F_i = sum_{j != i} (p_i - p_j)/(d^2 + eps2)^1.5,
+    and S float64[m] the sum of the terms' norms."""
+    x, y, z = (_c(a, np.float32) for a in (x, y, z))
+    n = x.shape[0]
+    if rows is None:
+        m, rp = n, None
+    else:
+        rows = _c(rows, np.int64)
+        m, rp = rows.shape[0], rows.ctypes.data_as(ctypes.c_void_p)
+    F = [np.zeros(m, np.float64) for _ in range(3)]
+    S = np.zeros(m, np.float64)
+    lib().oracle_force_rows(x, y, z, n, np.float32(eps2), rp, m, F[0], F[1], F[2], S, threads)
+    return np.stack(F, axis=1), S
 
 
 def count_i32_batched(x, y, z, r, offsets, threads: int = 0) -> np.ndarray:

@@ -31,7 +31,9 @@
  *     arithmetic in double.  total = sum over i < j of e_ij; the per-object
  *     value E_i = sum over j != i of e_ij receives the full e_ij from every
  *     partner, so sum_i E_i = 2 * total.  Both sums use Neumaier's compensated
- *     summation.
+ *     summation;
+ *   - forces of that potential, f_ij = (p_i - p_j) / (d2 + eps2)^(3/2), with
+ *     F_i = sum over j != i of f_ij (see oracle_force_rows).
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp (see build.py).
  * OpenMP only splits the outer loop over i between threads; the body is the
@@ -191,6 +193,42 @@ void oracle_energy_rows(const float *x, const float *y, const float *z, int64_t 
         for (int64_t j = 0; j < n; ++j)
             if (j != i) nsum_add(&acc, pair_energy(x, y, z, eps2, i, j));
         E[k] = nsum_value(&acc);
+    }
+}
+
+/* Forces of the same softened potential (a symmetric pairwise interaction
+ * with a vector value, Section 4's interact() returning a vector): the force
+ * on object i from object j is minus the gradient of e_ij in p_i,
+ *   f_ij = (p_i - p_j) / (|p_i - p_j|^2 + eps2)^(3/2),   f_ji = -f_ij,
+ * and F_i = sum over j != i of f_ij, each component summed with Neumaier's
+ * compensation in double.  S_i = sum over j != i of |f_ij| (the Euclidean
+ * norm of each term) is the scale against which cancellation in F_i is
+ * judged.  rows: the objects to compute (NULL: all n, in order). */
+void oracle_force_rows(const float *x, const float *y, const float *z, int64_t n, float eps2f,
+                       const int64_t *rows, int64_t nrows, double *Fx, double *Fy, double *Fz,
+                       double *S, int threads) {
+    const double eps2 = (double)eps2f;
+    int64_t m = rows ? nrows : n;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads_or_default(threads))
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        nsum_t ax = {0.0, 0.0}, ay = {0.0, 0.0}, az = {0.0, 0.0}, as = {0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = (double)x[i] - (double)x[j];
+            double dy = (double)y[i] - (double)y[j];
+            double dz = (double)z[i] - (double)z[j];
+            double d2 = dx * dx + dy * dy + dz * dz + eps2;
+            double w = 1.0 / (d2 * sqrt(d2));
+            nsum_add(&ax, dx * w);
+            nsum_add(&ay, dy * w);
+            nsum_add(&az, dz * w);
+            nsum_add(&as, sqrt(dx * dx + dy * dy + dz * dz) * w);
+        }
+        Fx[k] = nsum_value(&ax);
+        Fy[k] = nsum_value(&ay);
+        Fz[k] = nsum_value(&az);
+        S[k] = nsum_value(&as);
     }
 }
 
