@@ -37,7 +37,7 @@ VALU_PEAK = N_CU * VALU_LANES_PER_CU * SCLK_HZ          # lane-operations per se
 #   float32 energy with the pinned collision count: 3 sub + 1 mul + 2 fma
 #     (pinned squared distance) + add, mul, compare (radius test) + add
 #     (softening) + add
-C_ALG = {"count_i32": 5, "energy_f32": 8, "energy_count_f32": 11}
+C_ALG = {"count_i32": 5, "energy_f32": 8, "energy_count_f32": 11, "force_f32": 18}
 PLAIN_DEF_OPS = 12   # operations of the plain definition per pair (either kind)
 
 
@@ -497,6 +497,19 @@ def main():
         ms3b, _ = timed_steps(lambda: P.pairs_energy_f32(*t3, 1e-4, None, tot), max(3, a.steps // 2), 1)
         m3b = float(np.mean(ms3b))
         sec["energy_f32_2^18_total_only"] = {"ms": m3b, "G_pairs_per_s": pp3 / m3b / 1e6}
+        log(f"[bench] force_f32 N={n3}")
+        Fxyz = [torch.empty(n3, dtype=torch.float64, device=dev) for _ in range(3)]
+        ms4, _ = timed_steps(lambda: P.pairs_force_f32(*t3, 1e-4, *Fxyz), max(3, a.steps // 2), 1)
+        m4 = float(np.mean(ms4))
+        gf = golden()["config3_force_rows"]
+        got = np.stack([f[torch.tensor(gf["rows"], device=dev)].cpu().numpy() for f in Fxyz], 1)
+        err = float((np.abs(got - np.array(gf["F"])).max(axis=1) / np.array(gf["S"])).max())
+        sec["force_f32_2^18"] = {"ms": m4, "G_pairs_per_s": pp3 / m4 / 1e6,
+                                 "valu_frac": pp3 / (m4 * 1e-3) * C_ALG["force_f32"] / VALU_PEAK,
+                                 "per_pair_ops": C_ALG["force_f32"],
+                                 "max_err_over_norm_sum_vs_fp64_oracle": err,
+                                 "sampled_rows": len(gf["rows"])}
+        del Fxyz
         log("[bench] assignment comparison: balanced vs straightforward, N=2^20")
         sec["assignment_comparison_n2p20"] = assignment_comparison(torch, x, y, z, r, n, count,
                                                                    max(2, a.steps // 2))

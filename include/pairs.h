@@ -131,6 +131,23 @@ pairs_status_t pairs_energy_f32(const float *x, const float *y, const float *z, 
                                 float eps2, double *d_energy, double *d_total,
                                 unsigned flags, pairs_stream_t stream);
 
+/*
+ * Forces of the same softened potential on every object of one set, a
+ * symmetric interaction with a vector value (Section 4 leaves interact()
+ * open): the force on i from j is
+ *   f_ij = (p_i - p_j) / (|p_i - p_j|^2 + eps2)^(3/2),   f_ji = -f_ij,
+ * and d_f*[i] = the components of F_i = sum over j != i of f_ij (n doubles
+ * each).  Each unordered pair is evaluated once, in float32 with the
+ * hardware reciprocal square root, and added to i and subtracted from j
+ * (Newton's third law) in double accumulators.  Accuracy against an exact
+ * evaluation of the same inputs: every component within 1e-5 of
+ * S_i = sum over j != i of |f_ij| (the forces cancel, so their own size is
+ * no scale).  eps2 > 0; inputs finite (PAIRS_FLAG_VALIDATE checks it).
+ */
+pairs_status_t pairs_force_f32(const float *x, const float *y, const float *z, int64_t n,
+                               float eps2, double *d_fx, double *d_fy, double *d_fz,
+                               unsigned flags, pairs_stream_t stream);
+
 /* --------------------------------------------------------------- batches -- */
 /*
  * A batch is a CSR list of independent sets (the pruned sets that a spatial

@@ -17,7 +17,7 @@ import os
 __all__ = [
     "PairsError", "lib", "lib_path", "FLAG_VALIDATE",
     "KIND_COUNT_I32", "KIND_COUNT_F32", "KIND_ENERGY_F32",
-    "pairs_count_i32", "pairs_count_f32", "pairs_energy_f32",
+    "pairs_count_i32", "pairs_count_f32", "pairs_energy_f32", "pairs_force_f32",
     "pairs_batched_workspace_size", "pairs_count_i32_batched", "pairs_count_f32_batched",
     "pairs_energy_f32_batched", "pairs_jitter_f32", "pairs_debug_task_ranges",
     "pairs_debug_step_ranges", "FORM_BROADCAST", "FORM_STEPPING",
@@ -84,6 +84,7 @@ def _declare(L):
         "pairs_count_i32": [_vp, _vp, _vp, _vp, _i64, _vp, _u32, _vp],
         "pairs_count_f32": [_vp, _vp, _vp, _vp, _i64, _vp, _u32, _vp],
         "pairs_energy_f32": [_vp, _vp, _vp, _i64, _f32, _vp, _vp, _u32, _vp],
+        "pairs_force_f32": [_vp, _vp, _vp, _i64, _f32, _vp, _vp, _vp, _u32, _vp],
         "pairs_batched_workspace_size": [_i64, _i64, ctypes.POINTER(_sz)],
         "pairs_count_i32_batched": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _sz, _u32,
                                     _vp],
@@ -211,6 +212,17 @@ def pairs_energy_f32(x, y, z, eps2: float, energy, total, flags: int = 0, stream
         _require((energy,), torch.float64, n, "pairs_energy_f32 energy")
     _check(lib().pairs_energy_f32(_ptr(x), _ptr(y), _ptr(z), n, float(eps2), _ptr(energy),
                                   _ptr(total), flags, _stream(stream)), "pairs_energy_f32")
+
+
+def pairs_force_f32(x, y, z, eps2: float, fx, fy, fz, flags: int = 0, stream=None) -> None:
+    """Forces of the softened potential on one float32 particle set: the three
+    components into float64[n] tensors fx, fy, fz."""
+    import torch
+    n = int(x.shape[0])
+    _require((x, y, z), torch.float32, n, "pairs_force_f32")
+    _require((fx, fy, fz), torch.float64, n, "pairs_force_f32 forces")
+    _check(lib().pairs_force_f32(_ptr(x), _ptr(y), _ptr(z), n, float(eps2), _ptr(fx), _ptr(fy),
+                                 _ptr(fz), flags, _stream(stream)), "pairs_force_f32")
 
 
 def pairs_batched_workspace_size(n_sets: int, n_total: int) -> int:

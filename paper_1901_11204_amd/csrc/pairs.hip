@@ -264,6 +264,27 @@ __global__ __launch_bounds__(kBlock) void k_energy(const float *__restrict__ x,
     if (lane_id() == 0) atomicAdd(total, res.energy);
 }
 
+// Forces of the softened potential on every object (force_task).
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_force(const float *__restrict__ x,
+                                                  const float *__restrict__ y,
+                                                  const float *__restrict__ z, int n, int U,
+                                                  float eps2, double *Fx, double *Fy, double *Fz) {
+    __shared__ float lds[kWavesPerBlock * kForceLds];
+    const int wave = wave_id();
+    const Band band = Band::of(n);
+    const Tiling til = Tiling::of(band, K, U);
+    const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    if (task >= til.tasks()) return;
+    const int blk = (int)(task / til.nchunks), c = (int)(task % til.nchunks);
+    int ra, u0, u1;
+    task_range(band, til, blk, c, &ra, &u0, &u1);
+    if (u0 >= u1) return;
+    TaskInputs<float, K> in;
+    load_task_inputs<float, K, K, false>(x, y, z, nullptr, 0, band, ra, u0, u1, in);
+    force_task<K>(x, y, z, 0, band, ra, u0, u1, eps2, lds + wave * kForceLds, Fx, Fy, Fz, in);
+}
+
 // ---------------------------------------------------------- batched kernels --
 
 // One wave task of a plan, resolved on the host.
@@ -903,6 +924,14 @@ void launch_energy(const float *x, const float *y, const float *z, int n, int U,
         k_energy<K, false><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
 }
 
+template <int K>
+void launch_force(const float *x, const float *y, const float *z, int n, int U, float eps2,
+                  double *Fx, double *Fy, double *Fz, hipStream_t s) {
+    int64_t blocks = single_blocks(n, K, U);
+    if (blocks <= 0) return;
+    k_force<K><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, Fx, Fy, Fz);
+}
+
 int max_rows(const ClassTable &ct) {
     int m = 1;
     for (int c = 0; c < ct.count; ++c) m = std::max(m, ct.K[c]);
@@ -1199,6 +1228,33 @@ pairs_status_t pairs_energy_f32(const float *x, const float *y, const float *z, 
         case 2: launch_energy<2>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
         case 4: launch_energy<4>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
         default: launch_energy<8>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
+    }
+    PAIRS_HIP_CHECK(hipGetLastError());
+    return PAIRS_OK;
+}
+
+pairs_status_t pairs_force_f32(const float *x, const float *y, const float *z, int64_t n,
+                               float eps2, double *d_fx, double *d_fy, double *d_fz,
+                               unsigned flags, pairs_stream_t stream) {
+    if (n < 0 || n > PAIRS_MAX_SET_SIZE || (flags & ~PAIRS_FLAG_VALIDATE))
+        return PAIRS_ERR_INVALID_ARG;
+    if (!(eps2 > 0.0f) || !isfinite(eps2)) return PAIRS_ERR_INVALID_ARG;
+    if (n > 0 && (!x || !y || !z || !d_fx || !d_fy || !d_fz)) return PAIRS_ERR_INVALID_ARG;
+    int dev;
+    PAIRS_TRY(current_device(&dev));
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & PAIRS_FLAG_VALIDATE) PAIRS_TRY(validate_f32(x, y, z, nullptr, n, s));
+    PAIRS_TRY(fill_f64(d_fx, n, 0.0, s));
+    PAIRS_TRY(fill_f64(d_fy, n, 0.0, s));
+    PAIRS_TRY(fill_f64(d_fz, n, 0.0, s));
+    if (n < 2) return PAIRS_OK;
+    // the energy kernel's tile shapes, at most 4 rows per lane: three
+    // components per row and per partner sum need the registers of two
+    const Shape sh = single_set_shape(PAIRS_KIND_ENERGY_F32, n);
+    switch (std::min(sh.K, 4)) {
+        case 1: launch_force<1>(x, y, z, (int)n, sh.U, eps2, d_fx, d_fy, d_fz, s); break;
+        case 2: launch_force<2>(x, y, z, (int)n, sh.U, eps2, d_fx, d_fy, d_fz, s); break;
+        default: launch_force<4>(x, y, z, (int)n, sh.U, eps2, d_fx, d_fy, d_fz, s); break;
     }
     PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;

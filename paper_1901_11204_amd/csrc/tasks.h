@@ -552,4 +552,147 @@ __device__ __forceinline__ EnergyResult energy_task(const float *__restrict__ px
     return res;
 }
 
+// ---------------------------------------------------------------- forces --
+//
+// Forces of the softened potential, a symmetric interaction with a vector
+// value: f = (p_i - p_j) * e^3 with e = 1/sqrt(d2 + eps2) in float32 (the
+// hardware reciprocal square root), added to row i and subtracted from
+// partner j, so each unordered pair is evaluated once (Newton's third law on
+// the balanced assignment).  Row sums are float32 partials of at most
+// kFoldEvery terms per component folded into double accumulators; partner
+// sums are summed across the wave, 16 partners at a time per component
+// (reduce_scatter16), and added once per partner and task.
+//
+// Window entries past the task's partners hold a huge finite coordinate
+// (kForcePad), not an infinity: e is then exactly 0 and dx * e^3 is 0, where
+// an infinite dx would make it NaN.  Rows past the set use it too.
+
+// LDS window of one wave: x, y, z of 64 partners and their three partner sums.
+constexpr int kForceLds = 6 * kWave;
+constexpr float kForcePad = 1e30f;
+
+template <int K, bool Masked>
+__device__ __forceinline__ void force_group(const float (&xr)[K], const float (&yr)[K],
+                                            const float (&zr)[K], const int (&row)[K],
+                                            const int (&nsteps)[K], float (&part)[3][K],
+                                            double (&acc)[3][K], float *__restrict__ win,
+                                            int g0, int gn, float eps2, int slot) {
+    for (int t0 = 0; t0 < gn; t0 += kFoldEvery) {
+        float sx_all[kFoldEvery], sy_all[kFoldEvery], sz_all[kFoldEvery];
+#pragma unroll
+        for (int tt = 0; tt < kFoldEvery; ++tt) {
+            const int t = t0 + tt;
+            const float jx = win[t], jy = win[kWave + t], jz = win[2 * kWave + t];
+            const int u = g0 + t;
+            float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float dx = xr[k] - jx, dy = yr[k] - jy, dz = zr[k] - jz;
+                float d2 = __builtin_fmaf(dx, dx, eps2);
+                d2 = __builtin_fmaf(dy, dy, d2);
+                d2 = __builtin_fmaf(dz, dz, d2);
+                const float e = __builtin_amdgcn_rsqf(d2);
+                float e3 = e * e * e;
+                if (Masked) e3 = owns(u, row[k], nsteps[k]) ? e3 : 0.0f;
+                const float fx = dx * e3, fy = dy * e3, fz = dz * e3;
+                part[0][k] += fx;
+                part[1][k] += fy;
+                part[2][k] += fz;
+                sx += fx;
+                sy += fy;
+                sz += fz;
+            }
+            sx_all[tt] = sx;
+            sy_all[tt] = sy;
+            sz_all[tt] = sz;
+        }
+        // all 4 lanes of a group store the same value to the same slot
+        win[3 * kWave + t0 + slot] = reduce_scatter16(sx_all);
+        win[4 * kWave + t0 + slot] = reduce_scatter16(sy_all);
+        win[5 * kWave + t0 + slot] = reduce_scatter16(sz_all);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                acc[c][k] += (double)part[c][k];
+                part[c][k] = 0.0f;
+            }
+        }
+    }
+}
+
+// One wave task of the force kernel: rows [ra, ra + 64K) against partners
+// [u0, u1) of the band; F (three arrays of n doubles) receives the row sums
+// and, negated, the partner sums.
+template <int K>
+__device__ __forceinline__ void force_task(const float *__restrict__ px, const float *__restrict__ py,
+                                           const float *__restrict__ pz, int64_t base,
+                                           const Band band, int ra, int u0, int u1, float eps2,
+                                           float *__restrict__ win, double *__restrict__ Fx,
+                                           double *__restrict__ Fy, double *__restrict__ Fz,
+                                           const TaskInputs<float, K> &in) {
+    const int lane = lane_id();
+    float xr[K], yr[K], zr[K], part[3][K];
+    double acc[3][K];
+    int row[K], nsteps[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int i = ra + kWave * k + lane;
+        row[k] = i;
+        if (i < band.n) {
+            xr[k] = in.x[k]; yr[k] = in.y[k]; zr[k] = in.z[k];
+            nsteps[k] = band.steps(i);
+        } else {
+            xr[k] = kForcePad;
+            yr[k] = zr[k] = 0.0f;
+            nsteps[k] = 0;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            part[c][k] = 0.0f;
+            acc[c][k] = 0.0;
+        }
+    }
+    const int rlast = min(ra + kWave * K, band.n) - 1;
+    const int core_lo = rlast + 1, core_hi = ra + band.steps(ra);
+    const int slot = reduce_scatter16_slot();
+    float qx = in.px, qy = in.py, qz = in.pz;
+    for (int g0 = u0; g0 < u1; g0 += kWave) {
+        const bool pad = g0 + lane >= u1;
+        win[0 * kWave + lane] = pad ? kForcePad : qx;
+        win[1 * kWave + lane] = pad ? 0.0f : qy;
+        win[2 * kWave + lane] = pad ? 0.0f : qz;
+        {
+            int u = g0 + kWave + lane;
+            if (u < u1) {
+                int64_t g = partner_index(base, band, u);
+                qx = px[g]; qy = py[g]; qz = pz[g];
+            }
+        }
+        wave_sync();
+        const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
+        if (g0 >= core_lo && g0 + gn - 1 <= core_hi)
+            force_group<K, false>(xr, yr, zr, row, nsteps, part, acc, win, g0, gn, eps2, slot);
+        else
+            force_group<K, true>(xr, yr, zr, row, nsteps, part, acc, win, g0, gn, eps2, slot);
+        wave_sync();
+        if (lane < gn) {
+            const int64_t g = partner_index(base, band, g0 + lane);
+            atomicAdd(&Fx[g], -(double)win[3 * kWave + lane]);
+            atomicAdd(&Fy[g], -(double)win[4 * kWave + lane]);
+            atomicAdd(&Fz[g], -(double)win[5 * kWave + lane]);
+        }
+        wave_sync();
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int i = ra + kWave * k + lane;
+        if (i < band.n) {
+            atomicAdd(&Fx[base + i], acc[0][k]);
+            atomicAdd(&Fy[base + i], acc[1][k]);
+            atomicAdd(&Fz[base + i], acc[2][k]);
+        }
+    }
+}
+
 }  // namespace pairs_dev

@@ -24,6 +24,7 @@ import oracle  # noqa: E402
 import workloads as w  # noqa: E402
 
 OUT = os.path.join(HERE, "config_values.json")
+FORCE_ROWS = [0, 1, 4096, 65535, 131072, 200000, 262142, 262143]
 
 
 def compute(key, threads):
@@ -41,6 +42,11 @@ def compute(key, threads):
         return {"total": int(c.sum()),
                 "sha256_le_u64": hashlib.sha256(c.astype("<u8").tobytes()).hexdigest(),
                 "first16": [int(v) for v in c[:16]]}
+    if key == "config3_force_rows":
+        rows = np.array(FORCE_ROWS, np.int64)
+        F, S = oracle.force_rows(*w.config3().arrays(), np.float32(1e-4), rows=rows,
+                                 threads=threads)
+        return {"rows": FORCE_ROWS, "F": F.tolist(), "S": S.tolist()}
     if key in ("lattice_paper_counts", "lattice_large_counts"):
         b = w.lattice_paper() if key == "lattice_paper_counts" else w.lattice_large()
         coll, cont = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets, threads=threads)
@@ -52,7 +58,8 @@ def compute(key, threads):
 
 
 KEYS = ["config1_count", "config4_counts", "config3_energy_total", "config2_odd_count",
-        "config2_even_count", "lattice_paper_counts", "lattice_large_counts"]
+        "config2_even_count", "lattice_paper_counts", "lattice_large_counts",
+        "config3_force_rows"]
 
 
 def main():

@@ -156,3 +156,14 @@ def test_lattice_arguments_are_rejected_on_the_host():
                                          None) == WORKSPACE
     assert L.pairs_lattice_count_batched(x, y, z, off, 2, 10, 5000, c, k, ws, 64, 0,
                                          None) == WORKSPACE
+
+
+def test_force_arguments_are_rejected_on_the_host():
+    L = P.lib()
+    x, y, z, a, b, c = (fake(k) for k in range(6))
+    assert L.pairs_force_f32(x, y, z, -1, 1e-4, a, b, c, 0, None) == INVALID
+    assert L.pairs_force_f32(x, y, z, 10, 0.0, a, b, c, 0, None) == INVALID
+    assert L.pairs_force_f32(x, y, z, 10, float("inf"), a, b, c, 0, None) == INVALID
+    assert L.pairs_force_f32(x, y, z, 10, 1e-4, a, None, c, 0, None) == INVALID
+    assert L.pairs_force_f32(None, y, z, 10, 1e-4, a, b, c, 0, None) == INVALID
+    assert L.pairs_force_f32(x, y, z, 10, 1e-4, a, b, c, 0x40, None) == INVALID
