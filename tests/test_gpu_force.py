@@ -86,3 +86,35 @@ def test_config3_size_sampled_rows():
                           np.random.default_rng(0).integers(0, p.n, 253)])
     F, S = oracle.force_rows(*p.arrays(), EPS2, rows=rows)
     check(got[rows], F, S)
+
+
+def test_force_calls_captured_in_a_graph():
+    import torch
+    p = w.particles_f32(3000, 21)
+    q = w.particles_f32(1000, 22)
+    F, S = oracle.force_rows(*p.arrays(), EPS2)
+    Fq, Sq = oracle.force_rows(*q.arrays(), EPS2)
+    t = dev(*p.arrays())
+    tq = dev(*q.arrays())
+    out = [torch.empty(3000, dtype=torch.float64, device="cuda") for _ in range(3)]
+    outq = [torch.empty(1000, dtype=torch.float64, device="cuda") for _ in range(3)]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        P.pairs_force_f32(*t, float(EPS2), *out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    announce("force graph capture")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(4):
+            P.pairs_force_f32(*t, float(EPS2), *out)
+    for rep in range(3):
+        for o in out:
+            o.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        check(np.stack([o.cpu().numpy() for o in out], 1), F, S)
+        P.pairs_force_f32(*tq, float(EPS2), *outq)
+        torch.cuda.synchronize()
+        check(np.stack([o.cpu().numpy() for o in outq], 1), Fq, Sq)

@@ -242,3 +242,44 @@ def test_far_vectors_take_the_box_pass(want):
         np.testing.assert_array_equal(coll, c0)
     if want[1]:
         np.testing.assert_array_equal(cont, c1)
+
+
+def test_batched_calls_captured_in_a_graph():
+    # with max_n within the LDS tables a call needs no workspace and
+    # synchronises nothing: a graph holds it, and each replay, with eager
+    # calls on other data in between, gives the oracle's counts
+    import torch
+    b = w.lattice_walks(200, 1000, 13)
+    o = w.lattice_normal(50, 900, 3.0, 14)
+    c0, k0 = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets)
+    c1, k1 = oracle.lattice_counts_batched(*o.objs.arrays(), o.offsets)
+    x, y, z = dev(*b.objs.arrays())
+    off, = dev(b.offsets)
+    ox, oy, oz = dev(*o.objs.arrays())
+    ooff, = dev(o.offsets)
+    coll = torch.empty(200, dtype=torch.int64, device="cuda")
+    cont = torch.empty_like(coll)
+    oc = torch.empty(50, dtype=torch.int64, device="cuda")
+    ok = torch.empty_like(oc)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        P.pairs_lattice_count_batched(x, y, z, off, 1000, coll, cont)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    announce("lattice graph capture")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(5):
+            P.pairs_lattice_count_batched(x, y, z, off, 1000, coll, cont)
+    for rep in range(3):
+        coll.fill_(-1)
+        cont.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(coll.cpu().numpy().astype(np.uint64), c0)
+        np.testing.assert_array_equal(cont.cpu().numpy().astype(np.uint64), k0)
+        P.pairs_lattice_count_batched(ox, oy, oz, ooff, 900, oc, ok)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(oc.cpu().numpy().astype(np.uint64), c1)
+        np.testing.assert_array_equal(ok.cpu().numpy().astype(np.uint64), k1)
