@@ -56,6 +56,11 @@ def lib():
                                                                ctypes.c_void_p, ctypes.c_void_p,
                                                                _INT]
     L.oracle_energy_count_f32_batched.restype = None
+    L.oracle_energy_f64_total.argtypes = [_f64p] * 3 + [_I64, ctypes.c_double, _INT]
+    L.oracle_energy_f64_total.restype = ctypes.c_double
+    L.oracle_energy_f64_rows.argtypes = [_f64p] * 3 + [_I64, ctypes.c_double, ctypes.c_void_p,
+                                                       _I64, _f64p, _INT]
+    L.oracle_energy_f64_rows.restype = None
     L.oracle_force_rows.argtypes = [_f32p] * 3 + [_I64, ctypes.c_float, ctypes.c_void_p, _I64,
                                              _f64p, _f64p, _f64p, _f64p, _INT]
     L.oracle_force_rows.restype = None
@@ -119,6 +124,28 @@ def energy_rows(x, y, z, eps2=np.float32(1e-4), rows=None, threads: int = 0) -> 
         lib().oracle_energy_rows(x, y, z, n, np.float32(eps2),
                                  rows.ctypes.data_as(ctypes.c_void_p), rows.shape[0], out,
                                  threads)
+    return out
+
+
+def energy_f64_total(x, y, z, eps2=1e-4, threads: int = 0) -> float:
+    """sum_{i<j} 1/sqrt(|p_i - p_j|^2 + eps2) for float64 inputs, Neumaier-compensated."""
+    x, y, z = (_c(a, np.float64) for a in (x, y, z))
+    return float(lib().oracle_energy_f64_total(x, y, z, x.shape[0], float(eps2), threads))
+
+
+def energy_f64_rows(x, y, z, eps2=1e-4, rows=None, threads: int = 0) -> np.ndarray:
+    """E_i = sum_{j != i} e_ij for float64 inputs, for the given rows (all if None)."""
+    x, y, z = (_c(a, np.float64) for a in (x, y, z))
+    n = x.shape[0]
+    if rows is None:
+        out = np.zeros(n, np.float64)
+        lib().oracle_energy_f64_rows(x, y, z, n, float(eps2), None, 0, out, threads)
+    else:
+        rows = _c(rows, np.int64)
+        out = np.zeros(rows.shape[0], np.float64)
+        lib().oracle_energy_f64_rows(x, y, z, n, float(eps2),
+                                     rows.ctypes.data_as(ctypes.c_void_p), rows.shape[0], out,
+                                     threads)
     return out
 
 

@@ -196,6 +196,57 @@ void oracle_energy_rows(const float *x, const float *y, const float *z, int64_t 
     }
 }
 
+/* The same potential for double inputs (the double-precision variant): the
+ * pair term and the sums exactly as above, the inputs used as given. */
+static inline double pair_energy64(const double *x, const double *y, const double *z,
+                                   double eps2, int64_t i, int64_t j) {
+    double dx = x[i] - x[j];
+    double dy = y[i] - y[j];
+    double dz = z[i] - z[j];
+    double d2 = dx * dx + dy * dy + dz * dz;
+    return 1.0 / sqrt(d2 + eps2);
+}
+
+double oracle_energy_f64_total(const double *x, const double *y, const double *z, int64_t n,
+                               double eps2, int threads) {
+    int nt = nthreads_or_default(threads);
+    nsum_t *part = (nsum_t *)calloc((size_t)nt, sizeof(nsum_t));
+#pragma omp parallel num_threads(nt)
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        nsum_t acc = {0.0, 0.0};
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j)
+                nsum_add(&acc, pair_energy64(x, y, z, eps2, i, j));
+        part[t] = acc;
+    }
+    nsum_t tot = {0.0, 0.0};
+    for (int t = 0; t < nt; ++t) {
+        nsum_add(&tot, part[t].s);
+        nsum_add(&tot, part[t].c);
+    }
+    free(part);
+    return nsum_value(&tot);
+}
+
+void oracle_energy_f64_rows(const double *x, const double *y, const double *z, int64_t n,
+                            double eps2, const int64_t *rows, int64_t nrows, double *E,
+                            int threads) {
+    int64_t m = rows ? nrows : n;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads_or_default(threads))
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        nsum_t acc = {0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i) nsum_add(&acc, pair_energy64(x, y, z, eps2, i, j));
+        E[k] = nsum_value(&acc);
+    }
+}
+
 /* Forces of the same softened potential (a symmetric pairwise interaction
  * with a vector value, Section 4's interact() returning a vector): the force
  * on object i from object j is minus the gradient of e_ij in p_i,
