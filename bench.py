@@ -37,7 +37,8 @@ VALU_PEAK = N_CU * VALU_LANES_PER_CU * SCLK_HZ          # lane-operations per se
 #   float32 energy with the pinned collision count: 3 sub + 1 mul + 2 fma
 #     (pinned squared distance) + add, mul, compare (radius test) + add
 #     (softening) + add
-C_ALG = {"count_i32": 5, "energy_f32": 8, "energy_count_f32": 11, "force_f32": 18}
+C_ALG = {"count_i32": 5, "energy_f32": 8, "energy_count_f32": 11, "force_f32": 18,
+         "energy_f64": 13}
 PLAIN_DEF_OPS = 12   # operations of the plain definition per pair (either kind)
 
 
@@ -497,6 +498,19 @@ def main():
         ms3b, _ = timed_steps(lambda: P.pairs_energy_f32(*t3, 1e-4, None, tot), max(3, a.steps // 2), 1)
         m3b = float(np.mean(ms3b))
         sec["energy_f32_2^18_total_only"] = {"ms": m3b, "G_pairs_per_s": pp3 / m3b / 1e6}
+        log(f"[bench] energy_f64 N={n3}")
+        t3d = [v.to(torch.float64) for v in t3]
+        ms5, _ = timed_steps(lambda: P.pairs_energy_f64(*t3d, float(np.float32(1e-4)), E, tot),
+                             max(3, a.steps // 2), 1)
+        m5 = float(np.mean(ms5))
+        sec["energy_f64_2^18"] = {"ms": m5, "G_pairs_per_s": pp3 / m5 / 1e6,
+                                  "valu_frac": pp3 / (m5 * 1e-3) * C_ALG["energy_f64"] / VALU_PEAK,
+                                  "per_pair_ops": C_ALG["energy_f64"],
+                                  "rel_err_total_vs_fp64_oracle":
+                                      abs(float(tot.item()) - golden()["config3_energy_total"])
+                                      / golden()["config3_energy_total"],
+                                  "inputs": "config 3's float32 positions promoted to double"}
+        del t3d
         log(f"[bench] force_f32 N={n3}")
         Fxyz = [torch.empty(n3, dtype=torch.float64, device=dev) for _ in range(3)]
         ms4, _ = timed_steps(lambda: P.pairs_force_f32(*t3, 1e-4, *Fxyz), max(3, a.steps // 2), 1)

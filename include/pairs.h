@@ -132,6 +132,19 @@ pairs_status_t pairs_energy_f32(const float *x, const float *y, const float *z, 
                                 unsigned flags, pairs_stream_t stream);
 
 /*
+ * The same softened potential with double inputs and double arithmetic:
+ * e_ij = 1/sqrt(|p_i - p_j|^2 + eps2) from the hardware reciprocal square
+ * root refined by one Newton step, summed in double; outputs as for
+ * pairs_energy_f32 (d_energy may be NULL).  Accuracy against an exact
+ * evaluation: relative error at most 1e-12 for the total and for each
+ * d_energy[i].  eps2 > 0; inputs finite with |coordinates| well below 1e150
+ * (PAIRS_FLAG_VALIDATE checks finiteness).
+ */
+pairs_status_t pairs_energy_f64(const double *x, const double *y, const double *z, int64_t n,
+                                double eps2, double *d_energy, double *d_total,
+                                unsigned flags, pairs_stream_t stream);
+
+/*
  * Forces of the same softened potential on every object of one set, a
  * symmetric interaction with a vector value (Section 4 leaves interact()
  * open): the force on i from j is

@@ -17,7 +17,8 @@ import os
 __all__ = [
     "PairsError", "lib", "lib_path", "FLAG_VALIDATE",
     "KIND_COUNT_I32", "KIND_COUNT_F32", "KIND_ENERGY_F32",
-    "pairs_count_i32", "pairs_count_f32", "pairs_energy_f32", "pairs_force_f32",
+    "pairs_count_i32", "pairs_count_f32", "pairs_energy_f32", "pairs_energy_f64",
+    "pairs_force_f32",
     "pairs_batched_workspace_size", "pairs_count_i32_batched", "pairs_count_f32_batched",
     "pairs_energy_f32_batched", "pairs_jitter_f32", "pairs_debug_task_ranges",
     "pairs_debug_step_ranges", "FORM_BROADCAST", "FORM_STEPPING",
@@ -85,6 +86,7 @@ def _declare(L):
         "pairs_count_f32": [_vp, _vp, _vp, _vp, _i64, _vp, _u32, _vp],
         "pairs_energy_f32": [_vp, _vp, _vp, _i64, _f32, _vp, _vp, _u32, _vp],
         "pairs_force_f32": [_vp, _vp, _vp, _i64, _f32, _vp, _vp, _vp, _u32, _vp],
+        "pairs_energy_f64": [_vp, _vp, _vp, _i64, ctypes.c_double, _vp, _vp, _u32, _vp],
         "pairs_batched_workspace_size": [_i64, _i64, ctypes.POINTER(_sz)],
         "pairs_count_i32_batched": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _sz, _u32,
                                     _vp],
@@ -212,6 +214,19 @@ def pairs_energy_f32(x, y, z, eps2: float, energy, total, flags: int = 0, stream
         _require((energy,), torch.float64, n, "pairs_energy_f32 energy")
     _check(lib().pairs_energy_f32(_ptr(x), _ptr(y), _ptr(z), n, float(eps2), _ptr(energy),
                                   _ptr(total), flags, _stream(stream)), "pairs_energy_f32")
+
+
+def pairs_energy_f64(x, y, z, eps2: float, energy, total, flags: int = 0, stream=None) -> None:
+    """Softened potential of one float64 particle set in double arithmetic: total
+    (float64[1]) and, if energy is not None, the per-particle sums (float64[n])."""
+    import torch
+    n = int(x.shape[0])
+    _require((x, y, z), torch.float64, n, "pairs_energy_f64")
+    _require((total,), torch.float64, 1, "pairs_energy_f64 total")
+    if energy is not None:
+        _require((energy,), torch.float64, n, "pairs_energy_f64 energy")
+    _check(lib().pairs_energy_f64(_ptr(x), _ptr(y), _ptr(z), n, float(eps2), _ptr(energy),
+                                  _ptr(total), flags, _stream(stream)), "pairs_energy_f64")
 
 
 def pairs_force_f32(x, y, z, eps2: float, fx, fy, fz, flags: int = 0, stream=None) -> None:

@@ -126,6 +126,60 @@ __device__ __forceinline__ int reduce_scatter16_slot() {
     return (int)reduce_scatter16(probe);
 }
 
+// reduce_scatter16 on doubles: every data movement of the float version is
+// applied to the low and the high 32-bit words alike, so it moves whole
+// doubles; the additions are in double.
+__device__ __forceinline__ double dbl_of(uint32_t lo, uint32_t hi) {
+    return __hiloint2double((int)hi, (int)lo);
+}
+
+template <int Ctrl>
+__device__ __forceinline__ double dpp_full_f64(double v) {
+    const uint32_t lo = (uint32_t)__double2loint(v), hi = (uint32_t)__double2hiint(v);
+    return dbl_of((uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, Ctrl, 0xf, 0xf, true),
+                  (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, Ctrl, 0xf, 0xf, true));
+}
+
+__device__ __forceinline__ double reduce_scatter16_f64(const double (&v)[16]) {
+    const int lane = lane_id();
+    double r1[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)__double2loint(v[2 * p]),
+                                                   (uint32_t)__double2loint(v[2 * p + 1]), false,
+                                                   false);
+        auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)__double2hiint(v[2 * p]),
+                                                   (uint32_t)__double2hiint(v[2 * p + 1]), false,
+                                                   false);
+        r1[p] = dbl_of(lo[0], hi[0]) + dbl_of(lo[1], hi[1]);
+    }
+    double r2[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)__double2loint(r1[2 * q]),
+                                                   (uint32_t)__double2loint(r1[2 * q + 1]), false,
+                                                   false);
+        auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)__double2hiint(r1[2 * q]),
+                                                   (uint32_t)__double2hiint(r1[2 * q + 1]), false,
+                                                   false);
+        r2[q] = dbl_of(lo[0], hi[0]) + dbl_of(lo[1], hi[1]);
+    }
+    const bool hi8 = (lane & 8) != 0, hi4 = (lane & 4) != 0;
+    double r3[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const double e = r2[2 * h] + dpp_full_f64<kDppRowRor8>(r2[2 * h]);
+        const double f = r2[2 * h + 1] + dpp_full_f64<kDppRowRor8>(r2[2 * h + 1]);
+        r3[h] = hi8 ? f : e;
+    }
+    const double g0 = r3[0] + dpp_full_f64<kDppRowHalfMirror>(r3[0]);
+    const double g1 = r3[1] + dpp_full_f64<kDppRowHalfMirror>(r3[1]);
+    double r = hi4 ? g1 : g0;
+    r += dpp_full_f64<kDppQuadSwap1>(r);
+    r += dpp_full_f64<kDppQuadSwap2>(r);
+    return r;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;

@@ -183,6 +183,13 @@ __global__ void k_validate_f32(const float *x, const float *y, const float *z, c
     if (!ok) atomicOr(bad, 1);
 }
 
+__global__ void k_validate_f64(const double *x, const double *y, const double *z, int64_t n,
+                               int *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!(isfinite(x[i]) && isfinite(y[i]) && isfinite(z[i]))) atomicOr(bad, 1);
+}
+
 __global__ void k_validate_offsets(const int64_t *off, int64_t n_sets, int64_t n_total, int *bad) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s > n_sets) return;
@@ -262,6 +269,29 @@ __global__ __launch_bounds__(kBlock) void k_energy(const float *__restrict__ x,
     EnergyResult res = energy_task<K, K, PerObject, false>(x, y, z, nullptr, 0, band, ra, u0, u1,
                                                            eps2, lds + wave * kEnergyLds, E, in);
     if (lane_id() == 0) atomicAdd(total, res.energy);
+}
+
+// The softened potential in double precision (energy64_task).
+template <int K, bool PerObject>
+__global__ __launch_bounds__(kBlock) void k_energy64(const double *__restrict__ x,
+                                                     const double *__restrict__ y,
+                                                     const double *__restrict__ z, int n, int U,
+                                                     double eps2, double *E, double *total) {
+    __shared__ double lds[kWavesPerBlock * kEnergy64Lds];
+    const int wave = wave_id();
+    const Band band = Band::of(n);
+    const Tiling til = Tiling::of(band, K, U);
+    const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    if (task >= til.tasks()) return;
+    const int blk = (int)(task / til.nchunks), c = (int)(task % til.nchunks);
+    int ra, u0, u1;
+    task_range(band, til, blk, c, &ra, &u0, &u1);
+    if (u0 >= u1) return;
+    TaskInputs<double, K> in;
+    load_task_inputs<double, K, K, false>(x, y, z, nullptr, 0, band, ra, u0, u1, in);
+    const double e = energy64_task<K, PerObject>(x, y, z, 0, band, ra, u0, u1, eps2,
+                                                 lds + wave * kEnergy64Lds, E, in);
+    if (lane_id() == 0) atomicAdd(total, e);
 }
 
 // Forces of the softened potential on every object (force_task).
@@ -925,6 +955,17 @@ void launch_energy(const float *x, const float *y, const float *z, int n, int U,
 }
 
 template <int K>
+void launch_energy64(const double *x, const double *y, const double *z, int n, int U, double eps2,
+                     double *E, double *total, hipStream_t s) {
+    int64_t blocks = single_blocks(n, K, U);
+    if (blocks <= 0) return;
+    if (E)
+        k_energy64<K, true><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
+    else
+        k_energy64<K, false><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
+}
+
+template <int K>
 void launch_force(const float *x, const float *y, const float *z, int n, int U, float eps2,
                   double *Fx, double *Fy, double *Fz, hipStream_t s) {
     int64_t blocks = single_blocks(n, K, U);
@@ -1228,6 +1269,35 @@ pairs_status_t pairs_energy_f32(const float *x, const float *y, const float *z, 
         case 2: launch_energy<2>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
         case 4: launch_energy<4>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
         default: launch_energy<8>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
+    }
+    PAIRS_HIP_CHECK(hipGetLastError());
+    return PAIRS_OK;
+}
+
+pairs_status_t pairs_energy_f64(const double *x, const double *y, const double *z, int64_t n,
+                                double eps2, double *d_energy, double *d_total, unsigned flags,
+                                pairs_stream_t stream) {
+    if (!d_total || n < 0 || n > PAIRS_MAX_SET_SIZE || (flags & ~PAIRS_FLAG_VALIDATE))
+        return PAIRS_ERR_INVALID_ARG;
+    if (!(eps2 > 0.0) || !isfinite(eps2)) return PAIRS_ERR_INVALID_ARG;
+    if (n > 0 && (!x || !y || !z)) return PAIRS_ERR_INVALID_ARG;
+    int dev;
+    PAIRS_TRY(current_device(&dev));
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & PAIRS_FLAG_VALIDATE)
+        PAIRS_TRY(run_validation(s, [&](int *flag) {
+            if (n > 0) k_validate_f64<<<blocks_for(n, 256), 256, 0, s>>>(x, y, z, n, flag);
+        }));
+    PAIRS_TRY(fill_f64(d_total, 1, 0.0, s));
+    PAIRS_TRY(fill_f64(d_energy, n, 0.0, s));
+    if (n < 2) return PAIRS_OK;
+    // the float32 energy kernel's tile shapes, at most 4 rows per lane:
+    // double rows and partner sums take twice the registers
+    const Shape sh = single_set_shape(PAIRS_KIND_ENERGY_F32, n);
+    switch (std::min(sh.K, 4)) {
+        case 1: launch_energy64<1>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
+        case 2: launch_energy64<2>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
+        default: launch_energy64<4>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
     }
     PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;

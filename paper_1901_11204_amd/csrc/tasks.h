@@ -695,4 +695,129 @@ __device__ __forceinline__ void force_task(const float *__restrict__ px, const f
     }
 }
 
+// --------------------------------------------------------- energy, fp64 --
+//
+// The softened potential with double inputs and double arithmetic:
+// e = 1/sqrt(d2 + eps2) from the hardware double reciprocal square root and
+// one Newton step, y <- y (3/2 - (d2 + eps2) y^2 / 2), which takes its
+// relative error to the order of the double rounding.  Row sums accumulate
+// in double; with PerObject the partner side of each pair is summed across
+// the wave, 16 partners at a time (reduce_scatter16_f64), and added once per
+// partner and task, as in the float32 kernel.
+
+// Window entries past the task's partners and rows past the set hold a huge
+// finite coordinate: an infinity would give rsq(inf) = 0 and then 0 * inf =
+// NaN in the Newton step.  A pair with one such coordinate has d2 near
+// 1e300 and e near 1e-150, which masked groups replace by 0 and unmasked
+// ones add to partner sums (at most 256 such terms per partner and task,
+// some 1e-148 against sums of order 1).
+//
+// LDS window of one wave: x, y, z of 64 partners and their partner sums.
+constexpr int kEnergy64Lds = 4 * kWave;
+constexpr double kEnergy64Pad = 1e150;
+
+__device__ __forceinline__ double rsq_f64(double a) {
+    const double y = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a * y;
+    return y * __builtin_fma(-h, y, 1.5);
+}
+
+template <int K, bool PerObject, bool Masked>
+__device__ __forceinline__ void energy64_group(const double (&xr)[K], const double (&yr)[K],
+                                               const double (&zr)[K], const int (&row)[K],
+                                               const int (&nsteps)[K], double (&acc)[K],
+                                               double *__restrict__ win, int g0, int gn,
+                                               double eps2, int slot) {
+    for (int t0 = 0; t0 < gn; t0 += 16) {
+        double js_all[16];
+#pragma unroll
+        for (int tt = 0; tt < 16; ++tt) {
+            const int t = t0 + tt;
+            const double jx = win[t], jy = win[kWave + t], jz = win[2 * kWave + t];
+            const int u = g0 + t;
+            double js = 0.0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double dx = xr[k] - jx, dy = yr[k] - jy, dz = zr[k] - jz;
+                double d2 = __builtin_fma(dx, dx, eps2);
+                d2 = __builtin_fma(dy, dy, d2);
+                d2 = __builtin_fma(dz, dz, d2);
+                double e = rsq_f64(d2);
+                if (Masked) e = owns(u, row[k], nsteps[k]) ? e : 0.0;
+                acc[k] += e;
+                if (PerObject) js += e;
+            }
+            if (PerObject) js_all[tt] = js;
+        }
+        if (PerObject) win[3 * kWave + t0 + slot] = reduce_scatter16_f64(js_all);
+    }
+}
+
+template <int K, bool PerObject>
+__device__ __forceinline__ double energy64_task(const double *__restrict__ px,
+                                                const double *__restrict__ py,
+                                                const double *__restrict__ pz, int64_t base,
+                                                const Band band, int ra, int u0, int u1,
+                                                double eps2, double *__restrict__ win,
+                                                double *__restrict__ E,
+                                                const TaskInputs<double, K> &in) {
+    const int lane = lane_id();
+    double xr[K], yr[K], zr[K], acc[K];
+    int row[K], nsteps[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int i = ra + kWave * k + lane;
+        row[k] = i;
+        if (i < band.n) {
+            xr[k] = in.x[k]; yr[k] = in.y[k]; zr[k] = in.z[k];
+            nsteps[k] = band.steps(i);
+        } else {
+            xr[k] = kEnergy64Pad;
+            yr[k] = zr[k] = 0.0;
+            nsteps[k] = 0;
+        }
+        acc[k] = 0.0;
+    }
+    const int rlast = min(ra + kWave * K, band.n) - 1;
+    const int core_lo = rlast + 1, core_hi = ra + band.steps(ra);
+    const int slot = PerObject ? reduce_scatter16_slot() : 0;
+    double qx = in.px, qy = in.py, qz = in.pz;
+    for (int g0 = u0; g0 < u1; g0 += kWave) {
+        const bool pad = g0 + lane >= u1;
+        win[0 * kWave + lane] = pad ? -kEnergy64Pad : qx;
+        win[1 * kWave + lane] = pad ? 0.0 : qy;
+        win[2 * kWave + lane] = pad ? 0.0 : qz;
+        {
+            int u = g0 + kWave + lane;
+            if (u < u1) {
+                int64_t g = partner_index(base, band, u);
+                qx = px[g]; qy = py[g]; qz = pz[g];
+            }
+        }
+        wave_sync();
+        const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
+        if (g0 >= core_lo && g0 + gn - 1 <= core_hi)
+            energy64_group<K, PerObject, false>(xr, yr, zr, row, nsteps, acc, win, g0, gn, eps2,
+                                                slot);
+        else
+            energy64_group<K, PerObject, true>(xr, yr, zr, row, nsteps, acc, win, g0, gn, eps2,
+                                               slot);
+        if (PerObject) {
+            wave_sync();
+            if (lane < gn) atomicAdd(&E[partner_index(base, band, g0 + lane)], win[3 * kWave + lane]);
+        }
+        wave_sync();
+    }
+    double tot = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int i = ra + kWave * k + lane;
+        if (i < band.n) {
+            if (PerObject) atomicAdd(&E[base + i], acc[k]);
+            tot += acc[k];
+        }
+    }
+    return wave_sum(tot);
+}
+
 }  // namespace pairs_dev

@@ -167,3 +167,13 @@ def test_force_arguments_are_rejected_on_the_host():
     assert L.pairs_force_f32(x, y, z, 10, 1e-4, a, None, c, 0, None) == INVALID
     assert L.pairs_force_f32(None, y, z, 10, 1e-4, a, b, c, 0, None) == INVALID
     assert L.pairs_force_f32(x, y, z, 10, 1e-4, a, b, c, 0x40, None) == INVALID
+
+
+def test_energy64_arguments_are_rejected_on_the_host():
+    L = P.lib()
+    x, y, z, e, t = (fake(k) for k in range(5))
+    assert L.pairs_energy_f64(x, y, z, 10, 1e-4, e, None, 0, None) == INVALID
+    assert L.pairs_energy_f64(x, y, z, -1, 1e-4, e, t, 0, None) == INVALID
+    assert L.pairs_energy_f64(x, y, z, 10, 0.0, e, t, 0, None) == INVALID
+    assert L.pairs_energy_f64(x, y, z, 10, float("nan"), e, t, 0, None) == INVALID
+    assert L.pairs_energy_f64(None, y, z, 10, 1e-4, e, t, 0, None) == INVALID
