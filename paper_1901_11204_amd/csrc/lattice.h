@@ -478,18 +478,25 @@ constexpr uint32_t kNearMul = 0x9E3779B1u;
 // f + 1 < 2^bits, so that the +1 neighbour stays in the field.
 template <int Bits>
 __device__ __forceinline__ bool near_field(int v, int v0, uint32_t &f) {
-    const int64_t d = (int64_t)v - (int64_t)v0 + (int64_t(1) << (Bits - 1));
-    f = (uint32_t)d;
-    return d >= 1 && d <= (int64_t(1) << Bits) - 2;
+    int d;
+    const bool wrapped = __builtin_sub_overflow(v, v0, &d);  // 32-bit, overflow detected
+    f = (uint32_t)d + (1u << (Bits - 1));
+    return !wrapped & (f - 1u <= (1u << Bits) - 3u);  // 1 <= f <= 2^Bits - 2
 }
 
 // Where `key` stands in a bucket of four keys: j < 4 if slot j holds it,
 // 4 + j if it is absent and slot j is the first empty one, 8 if the bucket
 // is full of other keys.
+// Every comparison is made and combined with bitwise operators, so the
+// result is a few selects on the comparison masks: chains of conditional
+// operators become branches that wait out each LDS read in turn.
 __device__ __forceinline__ uint32_t bucket_pick(const uint4 &v, uint32_t key) {
-    const uint32_t f = v.x == key ? 0u : v.y == key ? 1u : v.z == key ? 2u : v.w == key ? 3u : 8u;
-    const uint32_t e = v.x == 0 ? 4u : v.y == 0 ? 5u : v.z == 0 ? 6u : v.w == 0 ? 7u : 8u;
-    return f < 4 ? f : e;
+    const bool k0 = v.x == key, k1 = v.y == key, k2 = v.z == key, k3 = v.w == key;
+    const bool z0 = v.x == 0, z1 = v.y == 0, z2 = v.z == 0, z3 = v.w == 0;
+    const uint32_t f = k0 ? 0u : k1 ? 1u : k2 ? 2u : 3u;
+    const uint32_t e = z0 ? 4u : z1 ? 5u : z2 ? 6u : 7u;
+    const bool any_k = k0 | k1 | k2 | k3, any_z = z0 | z1 | z2 | z3;
+    return any_k ? f : any_z ? e : 8u;
 }
 
 // Sum of the lanes' values into *out with one device atomic per wave.
@@ -525,18 +532,21 @@ __global__ __launch_bounds__(kBlock) void k_lattice_near(IO io, int tlog, int de
             }
             continue;
         }
-        const int x0 = io.x[b], y0 = io.y[b], z0 = io.z[b];
+        // the vector's arrays from its first bead; n <= 4096, so 32-bit indices
+        const int32_t *xb = io.x + b, *yb = io.y + b, *zb = io.z + b;
+        const int x0 = xb[0], y0 = yb[0], z0 = zb[0];
         uint32_t key[BPT], hk[BPT];
         bool valid[BPT], far = false;
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
-            const int64_t i = t + (int64_t)k * kBlock;
-            const int64_t ii = i < n ? b + i : b;
+            const int i = t + k * kBlock;
+            const int ii = i < n ? i : 0;
             uint32_t fx, fy, fz;
-            const bool ok = near_field<kNearXBits>(io.x[ii], x0, fx) &
-                            near_field<kNearYBits>(io.y[ii], y0, fy) &
-                            near_field<kNearZBits>(io.z[ii], z0, fz);            far |= i < n && !ok;
-            valid[k] = i < n && ok;
+            const bool ok = near_field<kNearXBits>(xb[ii], x0, fx) &
+                            near_field<kNearYBits>(yb[ii], y0, fy) &
+                            near_field<kNearZBits>(zb[ii], z0, fz);
+            far |= (i < n) & !ok;
+            valid[k] = (i < n) & ok;
             key[k] = (fx << (kNearZBits + kNearYBits)) | (fy << kNearZBits) | fz;
             hk[k] = key[k] * kNearMul;
         }
