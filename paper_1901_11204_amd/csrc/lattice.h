@@ -499,6 +499,15 @@ __device__ __forceinline__ uint32_t bucket_pick(const uint4 &v, uint32_t key) {
     return any_k ? f : any_z ? e : 8u;
 }
 
+// Lookup of `key` in a bucket once insertion is over: j < 4 if slot j holds
+// it, 4 if it is absent (the bucket has an empty slot; slots fill in order,
+// so the last one tells), 8 if the bucket is full of other keys.
+__device__ __forceinline__ uint32_t bucket_find(const uint4 &v, uint32_t key) {
+    const bool k0 = v.x == key, k1 = v.y == key, k2 = v.z == key, k3 = v.w == key;
+    const uint32_t f = k0 ? 0u : k1 ? 1u : k2 ? 2u : 3u;
+    return (k0 | k1 | k2 | k3) ? f : v.w == 0 ? 4u : 8u;
+}
+
 // Sum of the lanes' values into *out with one device atomic per wave.
 __device__ __forceinline__ void wave_add_to(uint64_t *out, uint32_t v) {
     const uint32_t s = wave_add(v);
@@ -646,10 +655,10 @@ __global__ __launch_bounds__(kBlock) void k_lattice_near(IO io, int tlog, int de
                     const int k = g + j / 3, d = j % 3;
                     const uint32_t h4 = 4 * ((hk[k] + dK[d] * kNearMul) >> qshift);
                     const uint4 v = *(const uint4 *)&keys[h4];
-                    const uint32_t p = bucket_pick(v, key[k] + dK[d]);
-                    hit[j] = valid[k] && p < 4;
+                    const uint32_t p = bucket_find(v, key[k] + dK[d]);
+                    hit[j] = valid[k] & (p < 4);
                     cs[j] = h4 + (p & 3);
-                    lp |= (valid[k] && p >= 8) ? uint64_t(1) << (3 * k + d) : uint64_t(0);
+                    lp |= (valid[k] & (p >= 8)) ? uint64_t(1) << (3 * k + d) : uint64_t(0);
                 }
 #pragma unroll
                 for (int j = 0; j < 3 * G; ++j) {
@@ -678,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_lattice_near(IO io, int tlog, int de
                 }
                 if (busy) {
                     const uint4 v = *(const uint4 *)&keys[4 * cq];
-                    const uint32_t p = bucket_pick(v, ck);
+                    const uint32_t p = bucket_find(v, ck);
                     if (p < 4) cont += occ[4 * cq + p];
                     busy = p >= 8;
                     cq = (cq + 1) & qmask;
