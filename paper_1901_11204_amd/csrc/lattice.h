@@ -522,16 +522,36 @@ constexpr uint64_t kFarBit = uint64_t(1) << 63;
 
 __device__ __forceinline__ uint64_t *marker(const IO &io) { return io.coll ? io.coll : io.cont; }
 
-template <int BPT, bool Contacts>
+// Barrier of the threads that count one vector together.
+template <int Waves>
+__device__ __forceinline__ void group_sync() {
+    if (Waves == 1)
+        pairs_dev::wave_sync();
+    else
+        __syncthreads();
+}
+
+// Waves = 4: the workgroup counts one vector at a time (kBlock threads, one
+// table, workgroup barriers).  Waves = 1: each wave counts its own vectors
+// with its own table (2^tlog slots per wave) and orders its LDS accesses
+// with wave-local fences instead of barriers; for short vectors, which
+// would leave most of a workgroup idle.
+template <int BPT, bool Contacts, int Waves>
 __global__ __launch_bounds__(kBlock) void k_lattice_near(IO io, int tlog, int defer) {
-    extern __shared__ uint64_t table[];
+    static_assert(Waves == 1 || Waves == kWaves, "a wave or the whole workgroup per vector");
+    constexpr int G = kWave * Waves;  // threads per vector
+    extern __shared__ uint64_t lds_tables[];
     constexpr uint32_t kNever32 = ~0u;  // no key equals it: keys are below 2^32 - 1
-    const int t = threadIdx.x;
+    const int t = threadIdx.x % G;
     const uint32_t T = 1u << tlog, qmask = (T >> 2) - 1;
     const int qshift = 32 - (tlog - 2);  // home bucket = top tlog - 2 bits of the hash
-    const int64_t cap = min((int64_t)(T / 2), (int64_t)BPT * kBlock);
+    const int64_t cap = min((int64_t)(T / 2), (int64_t)BPT * G);
+    const int group = Waves == 1 ? pairs_dev::wave_id() : 0;
+    uint64_t *table = lds_tables + (size_t)group * T;
+    const int64_t first = (int64_t)blockIdx.x * (kWaves / Waves) + group;
+    const int64_t stride = (int64_t)gridDim.x * (kWaves / Waves);
 
-    for (int64_t s = blockIdx.x; s < io.n_sets; s += gridDim.x) {
+    for (int64_t s = first; s < io.n_sets; s += stride) {
         int64_t b, n;
         vector_range(io, s, b, n);
         if (n < 2 || n > cap) {
@@ -548,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_lattice_near(IO io, int tlog, int de
         bool valid[BPT], far = false;
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
-            const int i = t + k * kBlock;
+            const int i = t + k * G;
             const int ii = i < n ? i : 0;
             uint32_t fx, fy, fz;
             const bool ok = near_field<kNearXBits>(xb[ii], x0, fx) &
@@ -561,9 +581,9 @@ __global__ __launch_bounds__(kBlock) void k_lattice_near(IO io, int tlog, int de
         }
         if (__builtin_amdgcn_ballot_w64(far) && (t & (kWave - 1)) == 0)
             atomicOr((ull *)marker(io) + s, (ull)kFarBit);
-        __syncthreads();  // the previous vector's lookups are done
-        for (uint32_t e = t; e < T; e += kBlock) table[e] = 0;
-        __syncthreads();
+        group_sync<Waves>();  // the previous vector's lookups are done
+        for (uint32_t e = t; e < T; e += G) table[e] = 0;
+        group_sync<Waves>();
 
         uint32_t *keys = (uint32_t *)table, *occ = keys + T;
 
@@ -637,7 +657,7 @@ __global__ __launch_bounds__(kBlock) void k_lattice_near(IO io, int tlog, int de
             }
             if (pend || busy) atomicOr(io.flag, kFlagTable);
         }
-        __syncthreads();
+        group_sync<Waves>();
 
         // Contacts: the three positive neighbours of every bead, one batched
         // round over their home buckets (two beads at a time), then the

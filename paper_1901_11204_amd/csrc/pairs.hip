@@ -1103,11 +1103,23 @@ int lattice_tlog(int64_t m) {
 template <bool C, typename F>
 void with_lattice_kernels(int bpt, F f) {
     switch (bpt) {
-        case 1: f(lat::k_lattice_near<1, C>, lat::k_lattice<1, C, uint64_t>); break;
-        case 2: f(lat::k_lattice_near<2, C>, lat::k_lattice<2, C, uint64_t>); break;
-        case 4: f(lat::k_lattice_near<4, C>, lat::k_lattice<4, C, uint64_t>); break;
-        case 8: f(lat::k_lattice_near<8, C>, lat::k_lattice<8, C, uint64_t>); break;
-        default: f(lat::k_lattice_near<16, C>, lat::k_lattice<16, C, uint64_t>); break;
+        case 1: f(lat::k_lattice_near<1, C, lat::kWaves>, lat::k_lattice<1, C, uint64_t>); break;
+        case 2: f(lat::k_lattice_near<2, C, lat::kWaves>, lat::k_lattice<2, C, uint64_t>); break;
+        case 4: f(lat::k_lattice_near<4, C, lat::kWaves>, lat::k_lattice<4, C, uint64_t>); break;
+        case 8: f(lat::k_lattice_near<8, C, lat::kWaves>, lat::k_lattice<8, C, uint64_t>); break;
+        default: f(lat::k_lattice_near<16, C, lat::kWaves>, lat::k_lattice<16, C, uint64_t>); break;
+    }
+}
+
+// Vectors of at most kWaveBeads beads are counted one per wave.
+constexpr int64_t kWaveBeads = 256;
+
+template <bool C, typename F>
+void with_lattice_wave_kernel(int bpt, F f) {
+    switch (bpt) {
+        case 1: f(lat::k_lattice_near<1, C, 1>); break;
+        case 2: f(lat::k_lattice_near<2, C, 1>); break;
+        default: f(lat::k_lattice_near<4, C, 1>); break;
     }
 }
 
@@ -1151,15 +1163,34 @@ pairs_status_t lattice_lds(const lat::IO &io, int64_t m, bool defer, const Devic
         return (unsigned)std::min<int64_t>(io.n_sets, resident * 4);
     };
     // keys relative to the first bead for every vector whose beads stay near
-    // it, then box-based 64-bit keys for the vectors the first pass marked
+    // it, then box-based 64-bit keys for the vectors the first pass marked;
+    // short vectors take the wave-per-vector near pass (four tables per block)
+    const bool per_wave = m <= kWaveBeads;
     auto launch = [&](auto near, auto wide) {
-        near<<<grid(near), lat::kBlock, lds, s>>>(io, tlog, defer ? 1 : 0);
+        if (!per_wave) near<<<grid(near), lat::kBlock, lds, s>>>(io, tlog, defer ? 1 : 0);
         wide<<<grid(wide), lat::kBlock, lds, s>>>(io, tlog, defer ? 1 : 0);
     };
-    if (io.cont)
+    auto launch_wave = [&](auto near) {
+        const size_t lds4 = lds * lat::kWaves;
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, near, lat::kBlock, lds4) !=
+                hipSuccess ||
+            per_cu <= 0)
+            per_cu = 1;
+        const int64_t resident = (int64_t)per_cu * (st->n_cu > 0 ? st->n_cu : 1);
+        const int64_t need = (io.n_sets + lat::kWaves - 1) / lat::kWaves;
+        near<<<(unsigned)std::min<int64_t>(need, resident * 4), lat::kBlock, lds4, s>>>(
+            io, tlog, defer ? 1 : 0);
+    };
+    const int wbpt = (int)std::min<int64_t>(4, (m + lat::kWave - 1) / lat::kWave);
+    const int wb = wbpt <= 1 ? 1 : wbpt <= 2 ? 2 : 4;
+    if (io.cont) {
+        if (per_wave) with_lattice_wave_kernel<true>(wb, launch_wave);
         with_lattice_kernels<true>(bpt, launch);
-    else
+    } else {
+        if (per_wave) with_lattice_wave_kernel<false>(wb, launch_wave);
         with_lattice_kernels<false>(bpt, launch);
+    }
     PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;
 }

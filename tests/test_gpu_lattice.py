@@ -283,3 +283,26 @@ def test_batched_calls_captured_in_a_graph():
         torch.cuda.synchronize()
         np.testing.assert_array_equal(oc.cpu().numpy().astype(np.uint64), c1)
         np.testing.assert_array_equal(ok.cpu().numpy().astype(np.uint64), k1)
+
+
+@pytest.mark.parametrize("max_n", [64, 128, 256])
+def test_short_vectors_one_wave_each(max_n):
+    # vectors of at most 256 beads are counted one per wave, four tables per
+    # workgroup; ragged lengths, dense clouds, and far vectors (box pass)
+    sizes = [s for s in [0, 1, 2, 3, 31, 63, 64, 65, 100, 127, 128, 129, 200, 255, 256]
+             if s <= max_n]
+    walks = w.lattice_walks(len(sizes) * 7, sizes * 7, 30 + max_n)
+    dense = w.lattice_normal(40, max_n, 1.0, 31)
+    far = w.lattice_normal(9, max_n, 800.0, 32)
+    parts = [walks, dense, far]
+    arrs = [np.concatenate([p.objs.arrays()[a] for p in parts]) for a in range(3)]
+    szs = np.concatenate([np.diff(p.offsets) for p in parts])
+    b = w.Batch(w.offsets_from_sizes(szs), w.Beads(*arrs))
+    c0, c1 = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets)
+    for want in [(True, True), (True, False), (False, True)]:
+        announce("lattice per-wave", max_n, want)
+        coll, cont = run_batched(b, max_n, want=want)
+        if want[0]:
+            np.testing.assert_array_equal(coll, c0)
+        if want[1]:
+            np.testing.assert_array_equal(cont, c1)
