@@ -213,32 +213,35 @@ LATTICE_BYTES_PER_BEAD = 12  # three int32 coordinates, read once
 
 def bench_lattice(P, w, torch, np, dev, steps):
     """Lattice-bead collision and contact counts (Section 3): the paper's batch of
-    1000 chains of 1920 beads, and 65536 such chains for throughput.  The
-    per-vector counts are checked against the oracle's stored values."""
+    1000 chains of 1920 beads, 65536 such chains for throughput, and 131072
+    chains of 128 beads (the common protein length of its structure
+    prediction runs).  The per-vector counts are checked against the oracle's
+    stored values."""
     def sha(t):
         return hashlib.sha256(t.cpu().numpy().astype("<u8").tobytes()).hexdigest()
 
     out = {}
-    for name, make, key, nsteps in [("paper_1000x1920", w.lattice_paper, "lattice_paper_counts", 50),
-                                    ("large_65536x1920", w.lattice_large, "lattice_large_counts",
-                                     max(3, steps))]:
+    for name, make, key, nsteps, maxn in [
+            ("paper_1000x1920", w.lattice_paper, "lattice_paper_counts", 50, 1920),
+            ("large_65536x1920", w.lattice_large, "lattice_large_counts", max(3, steps), 1920),
+            ("short_131072x128", w.lattice_short, "lattice_short_counts", max(3, steps), 128)]:
         b = make()
         log(f"[bench] lattice {name}: {b.n_sets} chains, {b.n_total} beads")
         x, y, z = (torch.from_numpy(v).to(dev) for v in b.objs.arrays())
         off = torch.from_numpy(b.offsets).to(dev)
         coll = torch.empty(b.n_sets, dtype=torch.int64, device=dev)
         cont = torch.empty_like(coll)
-        ms, _ = timed_steps(lambda: P.pairs_lattice_count_batched(x, y, z, off, 1920, coll, cont),
+        ms, _ = timed_steps(lambda: P.pairs_lattice_count_batched(x, y, z, off, maxn, coll, cont),
                             nsteps, 3)
         m = float(np.median(ms))
-        ms1, _ = timed_steps(lambda: P.pairs_lattice_count_batched(x, y, z, off, 1920, coll, None),
+        ms1, _ = timed_steps(lambda: P.pairs_lattice_count_batched(x, y, z, off, maxn, coll, None),
                              nsteps, 3)
-        P.pairs_lattice_count_batched(x, y, z, off, 1920, coll, cont)
+        P.pairs_lattice_count_batched(x, y, z, off, maxn, coll, cont)
         g = golden()[key]
         beads = b.n_total
         gbs = beads * LATTICE_BYTES_PER_BEAD / (m * 1e-3)
         out[name] = {
-            "workload": f"{b.n_sets} random chains of 1920 unit steps from the origin on Z^3",
+            "workload": f"{b.n_sets} random chains of {maxn} beads (unit steps from the origin on Z^3)",
             "beads": beads, "ms": m, "G_beads_per_s": beads / m / 1e6,
             "ms_collisions_only": float(np.median(ms1)),
             "roofline": {"bound": "hbm", "achieved": gbs / 1e9, "peak": HBM_PEAK / 1e9,

@@ -47,8 +47,9 @@ def compute(key, threads):
         F, S = oracle.force_rows(*w.config3().arrays(), np.float32(1e-4), rows=rows,
                                  threads=threads)
         return {"rows": FORCE_ROWS, "F": F.tolist(), "S": S.tolist()}
-    if key in ("lattice_paper_counts", "lattice_large_counts"):
-        b = w.lattice_paper() if key == "lattice_paper_counts" else w.lattice_large()
+    if key in ("lattice_paper_counts", "lattice_large_counts", "lattice_short_counts"):
+        b = {"lattice_paper_counts": w.lattice_paper, "lattice_large_counts": w.lattice_large,
+             "lattice_short_counts": w.lattice_short}[key]()
         coll, cont = oracle.lattice_counts_batched(*b.objs.arrays(), b.offsets, threads=threads)
         return {"collisions_total": int(coll.sum()), "contacts_total": int(cont.sum()),
                 "collisions_sha256_le_u64": hashlib.sha256(coll.astype("<u8").tobytes()).hexdigest(),
@@ -59,7 +60,7 @@ def compute(key, threads):
 
 KEYS = ["config1_count", "config4_counts", "config3_energy_total", "config2_odd_count",
         "config2_even_count", "lattice_paper_counts", "lattice_large_counts",
-        "config3_force_rows"]
+        "config3_force_rows", "lattice_short_counts"]
 
 
 def main():

@@ -25,6 +25,7 @@ __all__ = [
     "config1", "config2", "config3", "config4", "config5",
     "lognormal_sizes", "offsets_from_sizes",
     "Beads", "lattice_walks", "lattice_normal", "lattice_paper", "lattice_large",
+    "lattice_short",
 ]
 
 
@@ -214,3 +215,9 @@ def lattice_large(seed: int = 8) -> Batch:
     """65536 chains of 1920 beads (126 M beads, 1.5 GB of int32 coordinates): the
     throughput workload of the lattice counts."""
     return lattice_walks(65536, 1920, seed)
+
+
+def lattice_short(seed: int = 9) -> Batch:
+    """131072 chains of 128 beads, the common protein length of the paper's
+    structure-prediction experiments (16.8 M beads)."""
+    return lattice_walks(131072, 128, seed)
