@@ -527,6 +527,25 @@ def main():
                                  "max_err_over_norm_sum_vs_fp64_oracle": err,
                                  "sampled_rows": len(gf["rows"])}
         del Fxyz
+        log("[bench] binned count_i32 N=2^20, cells of 2^15")
+        wsb = torch.empty(P.pairs_binned_workspace_size(n), dtype=torch.uint8, device=dev)
+        outb = torch.empty(1, dtype=torch.int64, device=dev)
+        msb, _ = timed_steps(lambda: P.pairs_count_i32_binned(x, y, z, r, 1 << 15, outb, wsb),
+                             max(5, a.steps), 2)
+        mb = float(np.median(msb))
+        # algorithmic HBM bytes per object: read 16 B of input and write 12 B
+        # of key and index; eight 8-bit radix passes read and write 12 B
+        # each; the gather reads 4 + 16 B and writes 16 B; run-length
+        # encoding and scan about 24 B; the count reads 16 B
+        bpo = 16 + 12 + 8 * 24 + 36 + 24 + 16
+        sec["count_i32_binned_2^20"] = {
+            "ms": mb, "cell": 1 << 15, "count": int(outb.item()),
+            "matches_oracle": int(outb.item()) == golden()["config2_even_count"],
+            "speedup_vs_all_pairs": ms_step / mb,
+            "roofline": {"bound": "hbm", "achieved": n * bpo / (mb * 1e-3) / 1e9,
+                         "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                         "frac": n * bpo / (mb * 1e-3) / HBM_PEAK, "bytes_per_object": bpo}}
+        del wsb
         log("[bench] assignment comparison: balanced vs straightforward, N=2^20")
         sec["assignment_comparison_n2p20"] = assignment_comparison(torch, x, y, z, r, n, count,
                                                                    max(2, a.steps // 2))

@@ -306,6 +306,36 @@ typedef struct {
 pairs_status_t pairs_get_shapes(int kind, int batched, pairs_shape_table_t *out);
 pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t *table);
 
+/* ----------------------------------------------------------- binned count -- */
+/*
+ * Collision count of one set of int32 spheres (the same result as
+ * pairs_count_i32) through a uniform grid of cubic cells of side `cell`:
+ * the pruning step that produces the paper's pruned sets (Sections 1 and 6),
+ * with the pairwise count inside each cell on the balanced assignment.  With
+ * every radius at most cell/2, touching spheres lie in the same or in
+ * neighbouring cells, so only the pairs inside a cell and between each cell
+ * and its 13 forward neighbours are tested.  The objects are sorted by cell
+ * on the device (a radix sort), so the time grows with n times the objects
+ * per cell rather than with n^2.
+ *
+ * Domain: coordinates in [-2^24, 2^24], radii in [0, cell/2],
+ * PAIRS_BINNED_MIN_CELL <= cell <= PAIRS_BINNED_MAX_CELL, at most
+ * PAIRS_BINNED_MAX_SET_SIZE objects.  Outside it the result is undefined
+ * unless PAIRS_FLAG_VALIDATE is given (then PAIRS_ERR_DOMAIN).
+ * Workspace: pairs_binned_workspace_size(n) bytes of device memory, owned by
+ * the caller (about 60 bytes per object plus the sort's temporary storage).
+ */
+#define PAIRS_BINNED_MIN_CELL 32
+#define PAIRS_BINNED_MAX_CELL (1 << 25)
+#define PAIRS_BINNED_MAX_SET_SIZE (((int64_t)1 << 31) - 1)
+
+pairs_status_t pairs_binned_workspace_size(int64_t n, size_t *bytes);
+
+pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const int32_t *z,
+                                      const int32_t *r, int64_t n, int32_t cell,
+                                      uint64_t *d_count, void *d_ws, size_t ws_bytes,
+                                      unsigned flags, pairs_stream_t stream);
+
 /* --------------------------------------------------------- lattice beads -- */
 /*
  * Collision and contact counts of bead vectors on the integer lattice Z^3

@@ -25,6 +25,7 @@ __all__ = [
     "Plan", "Graph", "ShapeTable", "pairs_get_shapes", "pairs_set_shapes",
     "count_i32", "count_f32", "energy_f32",
     "pairs_lattice_workspace_size", "pairs_lattice_count", "pairs_lattice_count_batched",
+    "pairs_binned_workspace_size", "pairs_count_i32_binned",
     "LATTICE_LDS_BEADS", "LATTICE_MAX_BEADS",
 ]
 
@@ -108,6 +109,9 @@ def _declare(L):
         "pairs_debug_step_ranges": [_int, _int, _int, _vp, _i64, ctypes.POINTER(_i64)],
         "pairs_get_shapes": [_int, _int, ctypes.POINTER(ShapeTable)],
         "pairs_lattice_workspace_size": [_i64, _i64, _i64, ctypes.POINTER(_sz)],
+        "pairs_binned_workspace_size": [_i64, ctypes.POINTER(_sz)],
+        "pairs_count_i32_binned": [_vp, _vp, _vp, _vp, _i64, ctypes.c_int32, _vp, _vp, _sz, _u32,
+                                   _vp],
         "pairs_lattice_count": [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _u32, _vp],
         "pairs_lattice_count_batched": [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _sz,
                                         _u32, _vp],
@@ -308,6 +312,30 @@ def pairs_energy_f32_batched(x, y, z, r, offsets, eps2, energy, counts=None, ws=
                                           n_sets, n_total, float(eps2), _ptr(energy),
                                           _ptr(counts), _ptr(ws), nbytes, flags,
                                           _stream(stream)), "pairs_energy_f32_batched")
+
+
+def pairs_binned_workspace_size(n: int) -> int:
+    """Bytes of device workspace a binned count of n objects needs."""
+    b = _sz(0)
+    _check(lib().pairs_binned_workspace_size(n, ctypes.byref(b)), "pairs_binned_workspace_size")
+    return int(b.value)
+
+
+def pairs_count_i32_binned(x, y, z, r, cell: int, out, ws=None, flags: int = 0,
+                           stream=None) -> None:
+    """Exact collision count of one int32 sphere set through a uniform grid of
+    cells of side `cell` (every radius at most cell/2) into out (int64[1])."""
+    import torch
+    n = int(x.shape[0])
+    _require((x, y, z, r), torch.int32, n, "pairs_count_i32_binned")
+    _require((out,), torch.int64, 1, "pairs_count_i32_binned out")
+    need = pairs_binned_workspace_size(n)
+    if ws is None and need > 0:
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    nbytes = 0 if ws is None else int(ws.numel() * ws.element_size())
+    _check(lib().pairs_count_i32_binned(_ptr(x), _ptr(y), _ptr(z), _ptr(r), n, int(cell),
+                                        _ptr(out), _ptr(ws), nbytes, flags, _stream(stream)),
+           "pairs_count_i32_binned")
 
 
 def pairs_lattice_workspace_size(n_sets: int, n_total: int, max_n: int) -> int:

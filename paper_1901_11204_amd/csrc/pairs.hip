@@ -10,6 +10,9 @@
 //                kernel, searched by each wave;
 //   jitter     : the per-step perturbation of the repeated-step workload;
 //   lattice    : collision and contact counts of lattice beads (lattice.h);
+//   binned     : the count of one set through a uniform grid of cells
+//                (binning.h; the sort, run-length encoding and scan are
+//                rocPRIM's);
 //   helpers    : fills (in place of memsets, so every launch can be
 //                captured into a graph), validation.
 #include <hip/hip_runtime.h>
@@ -27,7 +30,12 @@
 #include <new>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_run_length_encode.hpp>
+#include <rocprim/device/device_scan.hpp>
+
 #include "band.h"
+#include "binning.h"
 #include "device.h"
 #include "lattice.h"
 #include "pairs.h"
@@ -1078,6 +1086,54 @@ pairs_status_t batched_args(const void *x, const void *y, const void *z,
     return PAIRS_OK;
 }
 
+// ----------------------------------------------------------- binned count --
+
+namespace bin = pairs_binning;
+
+// Workspace layout of a binned count of n objects.
+struct BinnedLayout {
+    size_t keys_in, keys_out, idx_in, idx_out, sx, sy, sz, sr, ukeys, sizes, off, runs, temp;
+    size_t temp_bytes, total;
+};
+
+pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
+    size_t t1 = 0, t2 = 0, t3 = 0;
+    if (n > 0) {
+        if (rocprim::radix_sort_pairs(nullptr, t1, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                      (const uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)n, 0,
+                                      63) != hipSuccess ||
+            rocprim::run_length_encode(nullptr, t2, (const uint64_t *)nullptr, (unsigned)n,
+                                       (uint64_t *)nullptr, (uint32_t *)nullptr,
+                                       (uint32_t *)nullptr) != hipSuccess ||
+            rocprim::exclusive_scan(nullptr, t3, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                    0u, (size_t)n + 1, rocprim::plus<uint32_t>()) != hipSuccess)
+            return PAIRS_ERR_HIP;
+    }
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = p;
+        p += align256(bytes);
+        return at;
+    };
+    const size_t un = (size_t)n;
+    L->keys_in = take(8 * un);
+    L->keys_out = take(8 * un);
+    L->idx_in = take(4 * un);
+    L->idx_out = take(4 * un);
+    L->sx = take(4 * un);
+    L->sy = take(4 * un);
+    L->sz = take(4 * un);
+    L->sr = take(4 * un);
+    L->ukeys = take(8 * un);
+    L->sizes = take(4 * (un + 1));
+    L->off = take(4 * (un + 1));
+    L->runs = take(4);
+    L->temp_bytes = std::max(t1, std::max(t2, t3));
+    L->temp = take(L->temp_bytes);
+    L->total = p;
+    return PAIRS_OK;
+}
+
 // ---------------------------------------------------------- lattice beads --
 
 namespace lat = pairs_lattice;
@@ -1880,6 +1936,67 @@ pairs_status_t pairs_debug_task_ranges(int n, int rows_per_lane, int chunk, int3
             out[3 * k + 1] = u0;
             out[3 * k + 2] = u1;
         }
+    return PAIRS_OK;
+}
+
+pairs_status_t pairs_binned_workspace_size(int64_t n, size_t *bytes) {
+    if (!bytes || n < 0 || n > PAIRS_BINNED_MAX_SET_SIZE) return PAIRS_ERR_INVALID_ARG;
+    BinnedLayout L;
+    PAIRS_TRY(binned_layout(n, &L));
+    *bytes = L.total;
+    return PAIRS_OK;
+}
+
+pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const int32_t *z,
+                                      const int32_t *r, int64_t n, int32_t cell,
+                                      uint64_t *d_count, void *d_ws, size_t ws_bytes,
+                                      unsigned flags, pairs_stream_t stream) {
+    if (n < 0 || n > PAIRS_BINNED_MAX_SET_SIZE || !d_count || (flags & ~PAIRS_FLAG_VALIDATE))
+        return PAIRS_ERR_INVALID_ARG;
+    if (cell < PAIRS_BINNED_MIN_CELL || cell > PAIRS_BINNED_MAX_CELL) return PAIRS_ERR_INVALID_ARG;
+    if (n > 0 && (!x || !y || !z || !r)) return PAIRS_ERR_INVALID_ARG;
+    BinnedLayout L;
+    PAIRS_TRY(binned_layout(n, &L));
+    if (n > 0 && (!d_ws || ws_bytes < L.total)) return PAIRS_ERR_WORKSPACE;
+    DeviceState *st;
+    PAIRS_TRY(device_state(&st));
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & PAIRS_FLAG_VALIDATE)
+        PAIRS_TRY(run_validation(s, [&](int *flag) {
+            if (n > 0)
+                bin::k_bin_validate<<<blocks_for(n, 256), 256, 0, s>>>(x, y, z, r, n, cell, flag);
+        }));
+    PAIRS_TRY(fill_u64(d_count, 1, 0, s));
+    if (n < 2) return PAIRS_OK;
+    unsigned char *w = (unsigned char *)d_ws;
+    uint64_t *keys_in = (uint64_t *)(w + L.keys_in), *keys_out = (uint64_t *)(w + L.keys_out);
+    uint32_t *idx_in = (uint32_t *)(w + L.idx_in), *idx_out = (uint32_t *)(w + L.idx_out);
+    int32_t *sx = (int32_t *)(w + L.sx), *sy = (int32_t *)(w + L.sy), *sz = (int32_t *)(w + L.sz),
+            *sr = (int32_t *)(w + L.sr);
+    uint64_t *ukeys = (uint64_t *)(w + L.ukeys);
+    uint32_t *sizes = (uint32_t *)(w + L.sizes), *off = (uint32_t *)(w + L.off);
+    uint32_t *runs = (uint32_t *)(w + L.runs);
+    void *temp = w + L.temp;
+    size_t tb = L.temp_bytes;
+    const int nb = blocks_for(n, 256);
+    bin::k_bin_keys<<<nb, 256, 0, s>>>(x, y, z, n, cell, keys_in, idx_in);
+    PAIRS_HIP_CHECK(hipGetLastError());
+    PAIRS_HIP_CHECK(rocprim::radix_sort_pairs(temp, tb, keys_in, keys_out, idx_in, idx_out,
+                                              (size_t)n, 0, 63, s));
+    bin::k_bin_gather<<<nb, 256, 0, s>>>(x, y, z, r, idx_out, n, sx, sy, sz, sr);
+    bin::k_bin_clear_u32<<<blocks_for(n + 1, 256), 256, 0, s>>>(sizes, n + 1);
+    PAIRS_HIP_CHECK(hipGetLastError());
+    tb = L.temp_bytes;
+    PAIRS_HIP_CHECK(rocprim::run_length_encode(temp, tb, keys_out, (unsigned)n, ukeys, sizes,
+                                               runs, s));
+    tb = L.temp_bytes;
+    PAIRS_HIP_CHECK(rocprim::exclusive_scan(temp, tb, sizes, off, 0u, (size_t)n + 1,
+                                            rocprim::plus<uint32_t>(), s));
+    // one wave per occupied cell, at most a few waves per SIMD of the device
+    const int64_t blocks = std::min<int64_t>((n + 3) / 4, (int64_t)st->n_cu * 16);
+    bin::k_bin_count<<<(unsigned)blocks, bin::kBlock, 0, s>>>(sx, sy, sz, sr, ukeys, off, runs,
+                                                             d_count);
+    PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;
 }
 

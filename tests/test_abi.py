@@ -177,3 +177,17 @@ def test_energy64_arguments_are_rejected_on_the_host():
     assert L.pairs_energy_f64(x, y, z, 10, 0.0, e, t, 0, None) == INVALID
     assert L.pairs_energy_f64(x, y, z, 10, float("nan"), e, t, 0, None) == INVALID
     assert L.pairs_energy_f64(None, y, z, 10, 1e-4, e, t, 0, None) == INVALID
+
+
+def test_binned_arguments_are_rejected_on_the_host():
+    L = P.lib()
+    x, y, z, r, out, ws = (fake(k) for k in range(6))
+    n_sz = ctypes.c_size_t(0)
+    assert L.pairs_binned_workspace_size(-1, ctypes.byref(n_sz)) == INVALID
+    assert L.pairs_binned_workspace_size(0, ctypes.byref(n_sz)) == OK
+    assert L.pairs_count_i32_binned(x, y, z, r, -1, 64, out, ws, 0, 0, None) == INVALID
+    assert L.pairs_count_i32_binned(x, y, z, r, 10, 16, out, ws, 0, 0, None) == INVALID
+    assert L.pairs_count_i32_binned(x, y, z, r, 10, 1 << 26, out, ws, 0, 0, None) == INVALID
+    assert L.pairs_count_i32_binned(x, y, z, r, 10, 64, None, ws, 0, 0, None) == INVALID
+    assert L.pairs_count_i32_binned(None, y, z, r, 10, 64, out, ws, 0, 0, None) == INVALID
+    assert L.pairs_count_i32_binned(x, y, z, r, 10, 64, out, ws, 0, 0x10, None) == INVALID
