@@ -19,8 +19,12 @@
 //   4. run-length encoding of the sorted keys (rocPRIM) into the occupied
 //      cells' keys and sizes, and an exclusive scan of the sizes into cell
 //      offsets;
-//   5. k_bin_count: one wave per occupied cell.  Lanes 0..12 binary-search
-//      the 13 forward neighbours among the occupied keys; the pairs inside
+//   5. k_bin_hash_build: a hash table from occupied cell keys to their
+//      indices;
+//   6. k_bin_count: 16 lanes per occupied cell (cells of more than 64
+//      objects go to a list that k_bin_count_big counts, one wave per cell).
+//      Lanes 0..12 of a group look up the 13 forward neighbours in the
+//      table; the pairs inside
 //      the cell run on the balanced circular assignment (each lane takes rows
 //      and their steps s = 1 .. floor((n-1)/2), rows i < n/2 also s = n/2
 //      when n is even); the pairs with each neighbour run with the lanes
@@ -95,18 +99,44 @@ __device__ __forceinline__ bool touch(int xi, int yi, int zi, int ri, int xj, in
     return dx * dx + dy * dy + dz * dz <= R * R;
 }
 
-// Index of `key` among the m sorted occupied keys, or -1.
-__device__ __forceinline__ int64_t find_cell(const uint64_t *__restrict__ ukeys, int64_t m,
-                                             uint64_t key) {
-    int64_t lo = 0, hi = m;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (ukeys[mid] < key)
-            lo = mid + 1;
-        else
-            hi = mid;
+// Cell index by key: an open-addressing table of 2^hlog slots (at least
+// twice the objects, so at most half full), keys in hkeys (0 = empty; no
+// cell key is 0, its fields being at least 1) and cell indices in hvals.
+// A neighbour lookup is then one or two dependent loads, not the twenty of a
+// binary search over a million keys.
+__device__ __forceinline__ uint32_t cell_slot(uint64_t key, int hlog) {
+    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - hlog));
+}
+
+__global__ void k_bin_hash_build(const uint64_t *__restrict__ ukeys,
+                                 const uint32_t *__restrict__ m_ptr, uint64_t *hkeys,
+                                 uint32_t *hvals, int hlog) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (int64_t)*m_ptr) return;
+    const uint64_t key = ukeys[c];
+    const uint32_t mask = (1u << hlog) - 1;
+    uint32_t sl = cell_slot(key, hlog);
+    for (uint32_t p = 0; p <= mask; ++p, sl = (sl + 1) & mask) {
+        // keys are distinct, so a claim either succeeds or meets another key
+        if (atomicCAS((unsigned long long *)&hkeys[sl], 0ull, (unsigned long long)key) == 0) {
+            hvals[sl] = (uint32_t)c;
+            return;
+        }
     }
-    return (lo < m && ukeys[lo] == key) ? lo : -1;
+}
+
+// Index of the occupied cell with `key`, or -1.
+__device__ __forceinline__ int64_t find_cell(const uint64_t *__restrict__ hkeys,
+                                             const uint32_t *__restrict__ hvals, int hlog,
+                                             uint64_t key) {
+    const uint32_t mask = (1u << hlog) - 1;
+    uint32_t sl = cell_slot(key, hlog);
+    for (uint32_t p = 0; p <= mask; ++p, sl = (sl + 1) & mask) {
+        const uint64_t k = hkeys[sl];
+        if (k == key) return hvals[sl];
+        if (k == 0) return -1;
+    }
+    return -1;
 }
 
 // Key of forward neighbour d of a cell.  Cell coordinates are at least 1
@@ -122,9 +152,65 @@ __device__ __forceinline__ uint64_t neighbour_key(uint64_t key, int d) {
     return cell_key((uint32_t)(cx + dx), (uint32_t)(cy + dy), (uint32_t)(cz + dz));
 }
 
-// One wave per occupied cell, grid-stride over the cells.  m_ptr: number of
-// occupied cells (device); ukeys: their keys; off: their first object in
-// the sorted arrays, off[m] = n.
+// Pairs of one occupied cell c, counted by the G lanes of a group (gl = lane
+// in the group, g0 = the group's first lane in the wave): its 13 forward
+// neighbours are looked up by lanes 0..12 of the group, the pairs inside the
+// cell run on the balanced circular assignment, and the pairs with each
+// occupied neighbour with the lanes taking the cell's objects against all of
+// the neighbour's.
+template <int G>
+__device__ __forceinline__ uint64_t count_cell(int64_t c, int gl, int g0,
+                                               const int32_t *__restrict__ sx,
+                                               const int32_t *__restrict__ sy,
+                                               const int32_t *__restrict__ sz,
+                                               const int32_t *__restrict__ sr,
+                                               const uint64_t *__restrict__ ukeys,
+                                               const uint32_t *__restrict__ off,
+                                               const uint64_t *__restrict__ hkeys,
+                                               const uint32_t *__restrict__ hvals, int hlog) {
+    static_assert(G >= 13 && kWave % G == 0, "13 neighbour lookups per group");
+    uint64_t cnt = 0;
+    const int64_t a0 = off[c], n = (int64_t)off[c + 1] - a0;
+    int64_t nb = -1;
+    if (gl < 13) nb = find_cell(hkeys, hvals, hlog, neighbour_key(ukeys[c], gl));
+    const int64_t h = (n - 1) / 2;
+    for (int64_t i = gl; i < n; i += G) {
+        const int xi = sx[a0 + i], yi = sy[a0 + i], zi = sz[a0 + i], ri = sr[a0 + i];
+        const int64_t steps = h + ((n % 2 == 0 && i < n / 2) ? 1 : 0);
+        for (int64_t s = 1; s <= steps; ++s) {
+            int64_t j = i + s;
+            j = j >= n ? j - n : j;
+            cnt += touch(xi, yi, zi, ri, sx[a0 + j], sy[a0 + j], sz[a0 + j], sr[a0 + j]);
+        }
+    }
+    for (int d = 0; d < 13; ++d) {
+        const int64_t b = __shfl(nb, g0 + d, kWave);
+        if (b < 0) continue;
+        const int64_t b0 = off[b], nbn = (int64_t)off[b + 1] - b0;
+        for (int64_t i = gl; i < n; i += G) {
+            const int xi = sx[a0 + i], yi = sy[a0 + i], zi = sz[a0 + i], ri = sr[a0 + i];
+            for (int64_t j = 0; j < nbn; ++j)
+                cnt += touch(xi, yi, zi, ri, sx[b0 + j], sy[b0 + j], sz[b0 + j], sr[b0 + j]);
+        }
+    }
+    return cnt;
+}
+
+__device__ __forceinline__ void wave_count_to(uint64_t *count, uint64_t cnt) {
+    for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0 && cnt)
+        atomicAdd((unsigned long long *)count, (unsigned long long)cnt);
+}
+
+// Small cells: 16 lanes per occupied cell, four cells per wave in flight,
+// which hides the latency of a cell's dependent loads.  Cells of more than
+// kBigCell objects are appended to `big` (their number in big_n) for
+// k_bin_count_big.  m_ptr: number of occupied cells (device); ukeys: their
+// keys; off: their first object in the sorted arrays, off[m] = n; hkeys,
+// hvals, hlog: the table from keys to cell indices.
+constexpr int kGroup = 16;
+constexpr int64_t kBigCell = 64;
+
 __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t *__restrict__ sx,
                                                       const int32_t *__restrict__ sy,
                                                       const int32_t *__restrict__ sz,
@@ -132,43 +218,46 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t *__restrict_
                                                       const uint64_t *__restrict__ ukeys,
                                                       const uint32_t *__restrict__ off,
                                                       const uint32_t *__restrict__ m_ptr,
+                                                      const uint64_t *__restrict__ hkeys,
+                                                      const uint32_t *__restrict__ hvals,
+                                                      int hlog, uint32_t *big, uint32_t *big_n,
                                                       uint64_t *count) {
     const int lane = threadIdx.x & (kWave - 1);
+    const int gl = lane % kGroup, g0 = lane - gl;
     const int64_t m = *m_ptr;
+    const int64_t groups = (int64_t)gridDim.x * (kBlock / kGroup);
+    uint64_t cnt = 0;
+    for (int64_t c = (int64_t)blockIdx.x * (kBlock / kGroup) + threadIdx.x / kGroup; c < m;
+         c += groups) {
+        if ((int64_t)off[c + 1] - off[c] > kBigCell) {
+            if (gl == 0) big[atomicAdd(big_n, 1u)] = (uint32_t)c;
+            continue;
+        }
+        cnt += count_cell<kGroup>(c, gl, g0, sx, sy, sz, sr, ukeys, off, hkeys, hvals, hlog);
+    }
+    wave_count_to(count, cnt);
+}
+
+// Big cells: one wave per cell of the list.
+__global__ __launch_bounds__(kBlock) void k_bin_count_big(const int32_t *__restrict__ sx,
+                                                          const int32_t *__restrict__ sy,
+                                                          const int32_t *__restrict__ sz,
+                                                          const int32_t *__restrict__ sr,
+                                                          const uint64_t *__restrict__ ukeys,
+                                                          const uint32_t *__restrict__ off,
+                                                          const uint64_t *__restrict__ hkeys,
+                                                          const uint32_t *__restrict__ hvals,
+                                                          int hlog, const uint32_t *big,
+                                                          const uint32_t *big_n,
+                                                          uint64_t *count) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nbig = *big_n;
     const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
     uint64_t cnt = 0;
-    for (int64_t c = (int64_t)blockIdx.x * (kBlock / kWave) + pairs_dev::wave_id(); c < m;
-         c += waves) {
-        const int64_t a0 = off[c], n = (int64_t)off[c + 1] - a0;
-        // neighbour cells, one lane each
-        int64_t nb = -1;
-        if (lane < 13) nb = find_cell(ukeys, m, neighbour_key(ukeys[c], lane));
-        // pairs inside the cell on the balanced circular assignment
-        const int64_t h = (n - 1) / 2;
-        for (int64_t i = lane; i < n; i += kWave) {
-            const int xi = sx[a0 + i], yi = sy[a0 + i], zi = sz[a0 + i], ri = sr[a0 + i];
-            const int64_t steps = h + ((n % 2 == 0 && i < n / 2) ? 1 : 0);
-            for (int64_t s = 1; s <= steps; ++s) {
-                int64_t j = i + s;
-                j = j >= n ? j - n : j;
-                cnt += touch(xi, yi, zi, ri, sx[a0 + j], sy[a0 + j], sz[a0 + j], sr[a0 + j]);
-            }
-        }
-        // pairs with each occupied forward neighbour
-        for (int d = 0; d < 13; ++d) {
-            const int64_t b = __shfl(nb, d, kWave);
-            if (b < 0) continue;
-            const int64_t b0 = off[b], nbn = (int64_t)off[b + 1] - b0;
-            for (int64_t i = lane; i < n; i += kWave) {
-                const int xi = sx[a0 + i], yi = sy[a0 + i], zi = sz[a0 + i], ri = sr[a0 + i];
-                for (int64_t j = 0; j < nbn; ++j)
-                    cnt += touch(xi, yi, zi, ri, sx[b0 + j], sy[b0 + j], sz[b0 + j], sr[b0 + j]);
-            }
-        }
-    }
-    // one atomic per wave
-    for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, kWave);
-    if (lane == 0 && cnt) atomicAdd((unsigned long long *)count, (unsigned long long)cnt);
+    for (int64_t q = (int64_t)blockIdx.x * (kBlock / kWave) + pairs_dev::wave_id(); q < nbig;
+         q += waves)
+        cnt += count_cell<kWave>(big[q], lane, 0, sx, sy, sz, sr, ukeys, off, hkeys, hvals, hlog);
+    wave_count_to(count, cnt);
 }
 
 // Clears the cell sizes before the run-length encoding: the scan then runs

@@ -1093,7 +1093,9 @@ namespace bin = pairs_binning;
 // Workspace layout of a binned count of n objects.
 struct BinnedLayout {
     size_t keys_in, keys_out, idx_in, idx_out, sx, sy, sz, sr, ukeys, sizes, off, runs, temp;
+    size_t hkeys, hvals, big, big_n;
     size_t temp_bytes, total;
+    int hlog;  // cell table of 2^hlog slots, at least 2n
 };
 
 pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
@@ -1128,6 +1130,12 @@ pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
     L->sizes = take(4 * (un + 1));
     L->off = take(4 * (un + 1));
     L->runs = take(4);
+    L->hlog = 1;
+    while ((int64_t(1) << L->hlog) < 2 * std::max<int64_t>(n, 1)) ++L->hlog;
+    L->hkeys = take(8 * (size_t(1) << L->hlog));
+    L->hvals = take(4 * (size_t(1) << L->hlog));
+    L->big = take(4 * un);
+    L->big_n = take(8);
     L->temp_bytes = std::max(t1, std::max(t2, t3));
     L->temp = take(L->temp_bytes);
     L->total = p;
@@ -1992,10 +2000,21 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
     tb = L.temp_bytes;
     PAIRS_HIP_CHECK(rocprim::exclusive_scan(temp, tb, sizes, off, 0u, (size_t)n + 1,
                                             rocprim::plus<uint32_t>(), s));
-    // one wave per occupied cell, at most a few waves per SIMD of the device
-    const int64_t blocks = std::min<int64_t>((n + 3) / 4, (int64_t)st->n_cu * 16);
-    bin::k_bin_count<<<(unsigned)blocks, bin::kBlock, 0, s>>>(sx, sy, sz, sr, ukeys, off, runs,
-                                                             d_count);
+    uint64_t *hkeys = (uint64_t *)(w + L.hkeys);
+    uint32_t *hvals = (uint32_t *)(w + L.hvals);
+    PAIRS_TRY(fill_u64(hkeys, int64_t(1) << L.hlog, 0, s));
+    bin::k_bin_hash_build<<<nb, 256, 0, s>>>(ukeys, runs, hkeys, hvals, L.hlog);
+    uint32_t *big = (uint32_t *)(w + L.big), *big_n = (uint32_t *)(w + L.big_n);
+    PAIRS_TRY(fill_u64((uint64_t *)big_n, 1, 0, s));
+    // 16 lanes per small cell, one wave per big one, at most a few waves per
+    // SIMD of the device
+    const int64_t blocks = std::min<int64_t>((n + 15) / 16, (int64_t)st->n_cu * 16);
+    bin::k_bin_count<<<(unsigned)blocks, bin::kBlock, 0, s>>>(
+        sx, sy, sz, sr, ukeys, off, runs, hkeys, hvals, L.hlog, big, big_n, d_count);
+    const int64_t big_blocks = std::min<int64_t>((n / bin::kBigCell + 3) / 4 + 1,
+                                                 (int64_t)st->n_cu * 16);
+    bin::k_bin_count_big<<<(unsigned)big_blocks, bin::kBlock, 0, s>>>(
+        sx, sy, sz, sr, ukeys, off, hkeys, hvals, L.hlog, big, big_n, d_count);
     PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;
 }
