@@ -323,8 +323,11 @@ pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t
  * PAIRS_BINNED_MAX_SET_SIZE objects.  Outside it the result is undefined
  * unless PAIRS_FLAG_VALIDATE is given (then PAIRS_ERR_DOMAIN).
  * Workspace: pairs_binned_workspace_size(n) bytes of device memory, owned by
- * the caller (about 60 to 110 bytes per object plus the sort's temporary
- * storage).
+ * the caller (about 110 to 150 bytes per object, the sort's temporary
+ * storage included).
+ * Stream-ordered, with no host synchronisation, but not to be captured into
+ * a HIP graph: the radix sort (rocPRIM) clears its own state with
+ * hipMemsetAsync.
  */
 #define PAIRS_BINNED_MIN_CELL 32
 #define PAIRS_BINNED_MAX_CELL (1 << 25)

@@ -12,15 +12,17 @@
 //
 // Pipeline (all on the device, no host synchronisation):
 //   1. k_bin_keys: cell coordinates (x + 2^24) / L + 1 per axis (the +1 keeps
-//      the -1 neighbours of cell 0 in range), packed 21 bits per axis into a
-//      64-bit key, and the object index;
-//   2. radix sort of (key, index) (rocPRIM);
+//      the -1 neighbours of cell 0 in range), packed fb bits per axis into a
+//      64-bit key, and the object index.  fb is the fewest bits that hold
+//      2^25 / L + 2, the largest neighbour coordinate: 21 for L = 32, 11 for
+//      L = 2^15;
+//   2. radix sort of (key, index) over the key's 3 fb bits (rocPRIM);
 //   3. k_bin_gather: the objects in key order, structure of arrays;
 //   4. run-length encoding of the sorted keys (rocPRIM) into the occupied
 //      cells' keys and sizes, and an exclusive scan of the sizes into cell
 //      offsets;
-//   5. k_bin_hash_build: a hash table from occupied cell keys to their
-//      indices;
+//   5. k_bin_hash_build: a hash table of 8-slot buckets from occupied cell
+//      keys to their indices;
 //   6. k_bin_count: 16 lanes per occupied cell (cells of more than 64
 //      objects go to a list that k_bin_count_big counts, one wave per cell).
 //      Lanes 0..12 of a group look up the 13 forward neighbours in the
@@ -42,8 +44,7 @@ namespace pairs_binning {
 using pairs_dev::kWave;
 
 constexpr int kBlock = 256;
-constexpr int kCellBits = 21;  // per axis
-constexpr uint64_t kAxisMask = (uint64_t(1) << kCellBits) - 1;
+constexpr int kMaxCellBits = 21;  // per axis, for the smallest cell of 32
 constexpr int kOffsetBias = 1 << 24;  // coordinates in [-2^24, 2^24]
 
 // Cell coordinate of a coordinate, offset by one.
@@ -51,8 +52,10 @@ __device__ __forceinline__ uint32_t cell_of(int v, int L) {
     return (uint32_t)(v + kOffsetBias) / (uint32_t)L + 1;
 }
 
-__device__ __forceinline__ uint64_t cell_key(uint32_t cx, uint32_t cy, uint32_t cz) {
-    return ((uint64_t)cx << (2 * kCellBits)) | ((uint64_t)cy << kCellBits) | (uint64_t)cz;
+// Key of a cell: fb bits per axis, x in the high field.  Sorting by key sorts
+// the cells in (x, y, z) lexicographic order.
+__device__ __forceinline__ uint64_t cell_key(uint32_t cx, uint32_t cy, uint32_t cz, int fb) {
+    return ((uint64_t)cx << (2 * fb)) | ((uint64_t)cy << fb) | (uint64_t)cz;
 }
 
 // Domain check of the binned count: coordinates in [-2^24, 2^24] and radii
@@ -67,130 +70,161 @@ __global__ void k_bin_validate(const int32_t *x, const int32_t *y, const int32_t
     if (!ok) atomicOr(bad, 1);
 }
 
+// Keys and indices for the sort, and each object as one 16-byte record
+// (x, y, z, r), so that the gather after the sort reads one record per
+// object rather than four scattered words.
 __global__ void k_bin_keys(const int32_t *__restrict__ x, const int32_t *__restrict__ y,
-                           const int32_t *__restrict__ z, int64_t n, int L,
-                           uint64_t *__restrict__ keys, uint32_t *__restrict__ idx) {
+                           const int32_t *__restrict__ z, const int32_t *__restrict__ r,
+                           int64_t n, int L, int fb, uint64_t *__restrict__ keys,
+                           uint32_t *__restrict__ idx, int4 *__restrict__ rec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    keys[i] = cell_key(cell_of(x[i], L), cell_of(y[i], L), cell_of(z[i], L));
+    const int xi = x[i], yi = y[i], zi = z[i];
+    keys[i] = cell_key(cell_of(xi, L), cell_of(yi, L), cell_of(zi, L), fb);
     idx[i] = (uint32_t)i;
+    rec[i] = make_int4(xi, yi, zi, r[i]);
 }
 
-__global__ void k_bin_gather(const int32_t *__restrict__ x, const int32_t *__restrict__ y,
-                             const int32_t *__restrict__ z, const int32_t *__restrict__ r,
-                             const uint32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ sx,
-                             int32_t *__restrict__ sy, int32_t *__restrict__ sz,
-                             int32_t *__restrict__ sr) {
+// The records in key order.
+__global__ void k_bin_gather(const int4 *__restrict__ rec, const uint32_t *__restrict__ perm,
+                             int64_t n, int4 *__restrict__ so) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint32_t p = perm[i];
-    sx[i] = x[p];
-    sy[i] = y[p];
-    sz[i] = z[p];
-    sr[i] = r[p];
+    so[i] = rec[perm[i]];
 }
 
 // Touch test in 64-bit integers: coordinates lie in [-2^24, 2^24] and radii
 // in [0, 2^24], so every square and sum stays below 2^53.
-__device__ __forceinline__ bool touch(int xi, int yi, int zi, int ri, int xj, int yj, int zj,
-                                      int rj) {
-    const int64_t dx = (int64_t)xi - xj, dy = (int64_t)yi - yj, dz = (int64_t)zi - zj;
-    const int64_t R = (int64_t)ri + rj;
+__device__ __forceinline__ bool touch(int4 a, int4 b) {
+    const int64_t dx = (int64_t)a.x - b.x, dy = (int64_t)a.y - b.y, dz = (int64_t)a.z - b.z;
+    const int64_t R = (int64_t)a.w + b.w;
     return dx * dx + dy * dy + dz * dz <= R * R;
 }
 
-// Cell index by key: an open-addressing table of 2^hlog slots (at least
-// twice the objects, so at most half full), keys in hkeys (0 = empty; no
-// cell key is 0, its fields being at least 1) and cell indices in hvals.
-// A neighbour lookup is then one or two dependent loads, not the twenty of a
-// binary search over a million keys.
-__device__ __forceinline__ uint32_t cell_slot(uint64_t key, int hlog) {
-    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - hlog));
+// Cells by key: a table of 2^blog buckets of kSlots slots (at least twice as
+// many slots as objects).  Per slot: a tag byte in htags (0 = empty, else 8
+// bits of the key's hash), the key in hkeys and the cell's first object and
+// size in hvals; per bucket, the number of claims in hcnt.  A key goes to the
+// first bucket, from its home bucket on, whose claim count is below kSlots,
+// so a bucket's slots fill in order and a key can be further on only if its
+// home bucket is full.
+//
+// A lookup reads the bucket's eight tags as one 8-byte word, from a tag array
+// of one byte per slot that the L2 cache holds, and reads a key only where
+// its tag matches.  In a sparse grid most neighbours are empty, and most
+// lookups end at the tag word.
+constexpr int kSlots = 8;
+
+__device__ __forceinline__ uint64_t cell_hash(uint64_t key) {
+    return key * 0x9E3779B97F4A7C15ull;
+}
+
+__device__ __forceinline__ uint32_t home_bucket(uint64_t h, int blog) {
+    return (uint32_t)(h >> (64 - blog));
+}
+
+// The 8 hash bits below the bucket bits, never 0.
+__device__ __forceinline__ uint32_t cell_tag(uint64_t h, int blog) {
+    const uint32_t t = (uint32_t)(h >> (56 - blog)) & 0xFFu;
+    return t ? t : 1u;
 }
 
 __global__ void k_bin_hash_build(const uint64_t *__restrict__ ukeys,
-                                 const uint32_t *__restrict__ m_ptr, uint64_t *hkeys,
-                                 uint32_t *hvals, int hlog) {
+                                 const uint32_t *__restrict__ off,
+                                 const uint32_t *__restrict__ m_ptr, uint8_t *htags,
+                                 uint64_t *hkeys, uint2 *hvals, uint32_t *hcnt, int blog) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= (int64_t)*m_ptr) return;
-    const uint64_t key = ukeys[c];
-    const uint32_t mask = (1u << hlog) - 1;
-    uint32_t sl = cell_slot(key, hlog);
-    for (uint32_t p = 0; p <= mask; ++p, sl = (sl + 1) & mask) {
-        // keys are distinct, so a claim either succeeds or meets another key
-        if (atomicCAS((unsigned long long *)&hkeys[sl], 0ull, (unsigned long long)key) == 0) {
-            hvals[sl] = (uint32_t)c;
+    const uint64_t key = ukeys[c], h = cell_hash(key);
+    const uint2 val = make_uint2(off[c], off[c + 1] - off[c]);
+    const uint32_t mask = (1u << blog) - 1;
+    uint32_t b = home_bucket(h, blog);
+    // the slots outnumber the cells, so some bucket has room
+    for (uint32_t p = 0; p <= mask; ++p, b = (b + 1) & mask) {
+        const uint32_t at = atomicAdd(&hcnt[b], 1u);
+        if (at < (uint32_t)kSlots) {
+            const size_t slot = (size_t)b * kSlots + at;
+            htags[slot] = (uint8_t)cell_tag(h, blog);
+            hkeys[slot] = key;
+            hvals[slot] = val;
             return;
         }
     }
 }
 
-// Index of the occupied cell with `key`, or -1.
-__device__ __forceinline__ int64_t find_cell(const uint64_t *__restrict__ hkeys,
-                                             const uint32_t *__restrict__ hvals, int hlog,
-                                             uint64_t key) {
-    const uint32_t mask = (1u << hlog) - 1;
-    uint32_t sl = cell_slot(key, hlog);
-    for (uint32_t p = 0; p <= mask; ++p, sl = (sl + 1) & mask) {
-        const uint64_t k = hkeys[sl];
-        if (k == key) return hvals[sl];
-        if (k == 0) return -1;
+// First object and size of the occupied cell with `key`, or size 0.
+__device__ __forceinline__ uint2 find_cell(const uint64_t *__restrict__ htags,
+                                           const uint64_t *__restrict__ hkeys,
+                                           const uint2 *__restrict__ hvals, int blog,
+                                           uint64_t key) {
+    const uint64_t h = cell_hash(key);
+    const uint32_t mask = (1u << blog) - 1, tag = cell_tag(h, blog);
+    uint32_t b = home_bucket(h, blog);
+    for (uint32_t p = 0; p <= mask; ++p, b = (b + 1) & mask) {
+        const uint64_t tw = htags[b];
+        bool room = false;
+        for (int i = 0; i < kSlots; ++i) {
+            const uint32_t t = (uint32_t)(tw >> (8 * i)) & 0xFFu;
+            room |= t == 0;
+            if (t == tag && hkeys[(size_t)b * kSlots + i] == key)
+                return hvals[(size_t)b * kSlots + i];
+        }
+        if (room) break;
     }
-    return -1;
+    return make_uint2(0, 0);
 }
 
 // Key of forward neighbour d of a cell.  Cell coordinates are at least 1
-// (the +1 offset) and at most 2^20 + 1, so every neighbour's coordinates stay
-// inside their 21-bit fields.
-__device__ __forceinline__ uint64_t neighbour_key(uint64_t key, int d) {
+// (the +1 offset) and at most 2^25 / L + 1, so every neighbour's coordinates
+// stay inside their fb-bit fields.
+__device__ __forceinline__ uint64_t neighbour_key(uint64_t key, int d, int fb) {
     // d = 0..12 enumerates (dx, dy, dz) > (0, 0, 0) lexicographically
     const int e = d + 14;  // index in the 3x3x3 cube, 13 being the centre
     const int dx = e / 9 - 1, dy = (e / 3) % 3 - 1, dz = e % 3 - 1;
-    const uint64_t cx = (key >> (2 * kCellBits)) & kAxisMask;
-    const uint64_t cy = (key >> kCellBits) & kAxisMask;
-    const uint64_t cz = key & kAxisMask;
-    return cell_key((uint32_t)(cx + dx), (uint32_t)(cy + dy), (uint32_t)(cz + dz));
+    const uint64_t mask = (uint64_t(1) << fb) - 1;
+    const uint64_t cx = (key >> (2 * fb)) & mask;
+    const uint64_t cy = (key >> fb) & mask;
+    const uint64_t cz = key & mask;
+    return cell_key((uint32_t)(cx + dx), (uint32_t)(cy + dy), (uint32_t)(cz + dz), fb);
 }
 
-// Pairs of one occupied cell c, counted by the G lanes of a group (gl = lane
-// in the group, g0 = the group's first lane in the wave): its 13 forward
-// neighbours are looked up by lanes 0..12 of the group, the pairs inside the
-// cell run on the balanced circular assignment, and the pairs with each
-// occupied neighbour with the lanes taking the cell's objects against all of
-// the neighbour's.
+// Pairs of one occupied cell (first object a0, n objects, key `key`),
+// counted by the G lanes of a group (gl = lane in the group, g0 = the group's
+// first lane in the wave): its 13 forward neighbours are looked up by lanes
+// 0..12 of the group, the pairs inside the cell run on the balanced circular
+// assignment, and the pairs with each occupied neighbour with the lanes
+// taking the cell's objects against all of the neighbour's.
 template <int G>
-__device__ __forceinline__ uint64_t count_cell(int64_t c, int gl, int g0,
-                                               const int32_t *__restrict__ sx,
-                                               const int32_t *__restrict__ sy,
-                                               const int32_t *__restrict__ sz,
-                                               const int32_t *__restrict__ sr,
-                                               const uint64_t *__restrict__ ukeys,
-                                               const uint32_t *__restrict__ off,
+__device__ __forceinline__ uint64_t count_cell(int64_t a0, int64_t n, uint64_t key, int gl, int g0,
+                                               const int4 *__restrict__ so,
+                                               const uint64_t *__restrict__ htags,
                                                const uint64_t *__restrict__ hkeys,
-                                               const uint32_t *__restrict__ hvals, int hlog) {
+                                               const uint2 *__restrict__ hvals, int blog,
+                                               int fb) {
     static_assert(G >= 13 && kWave % G == 0, "13 neighbour lookups per group");
     uint64_t cnt = 0;
-    const int64_t a0 = off[c], n = (int64_t)off[c + 1] - a0;
-    int64_t nb = -1;
-    if (gl < 13) nb = find_cell(hkeys, hvals, hlog, neighbour_key(ukeys[c], gl));
+    uint2 nb = make_uint2(0, 0);
+    if (gl < 13) nb = find_cell(htags, hkeys, hvals, blog, neighbour_key(key, gl, fb));
     const int64_t h = (n - 1) / 2;
-    for (int64_t i = gl; i < n; i += G) {
-        const int xi = sx[a0 + i], yi = sy[a0 + i], zi = sz[a0 + i], ri = sr[a0 + i];
+    for (int64_t i = gl; n >= 2 && i < n; i += G) {
+        const int4 oi = so[a0 + i];
         const int64_t steps = h + ((n % 2 == 0 && i < n / 2) ? 1 : 0);
         for (int64_t s = 1; s <= steps; ++s) {
             int64_t j = i + s;
             j = j >= n ? j - n : j;
-            cnt += touch(xi, yi, zi, ri, sx[a0 + j], sy[a0 + j], sz[a0 + j], sr[a0 + j]);
+            cnt += touch(oi, so[a0 + j]);
         }
     }
-    for (int d = 0; d < 13; ++d) {
-        const int64_t b = __shfl(nb, g0 + d, kWave);
-        if (b < 0) continue;
-        const int64_t b0 = off[b], nbn = (int64_t)off[b + 1] - b0;
+    // only the occupied neighbours, usually none in a sparse grid
+    uint32_t occ = (uint32_t)(__ballot(nb.y != 0) >> g0) & ((1u << 13) - 1);
+    while (occ) {
+        const int d = __builtin_ctz(occ);
+        occ &= occ - 1;
+        const int64_t nbn = (uint32_t)__shfl((int)nb.y, g0 + d, kWave);
+        const int64_t b0 = (uint32_t)__shfl((int)nb.x, g0 + d, kWave);
         for (int64_t i = gl; i < n; i += G) {
-            const int xi = sx[a0 + i], yi = sy[a0 + i], zi = sz[a0 + i], ri = sr[a0 + i];
-            for (int64_t j = 0; j < nbn; ++j)
-                cnt += touch(xi, yi, zi, ri, sx[b0 + j], sy[b0 + j], sz[b0 + j], sr[b0 + j]);
+            const int4 oi = so[a0 + i];
+            for (int64_t j = 0; j < nbn; ++j) cnt += touch(oi, so[b0 + j]);
         }
     }
     return cnt;
@@ -206,48 +240,54 @@ __device__ __forceinline__ void wave_count_to(uint64_t *count, uint64_t cnt) {
 // which hides the latency of a cell's dependent loads.  Cells of more than
 // kBigCell objects are appended to `big` (their number in big_n) for
 // k_bin_count_big.  m_ptr: number of occupied cells (device); ukeys: their
-// keys; off: their first object in the sorted arrays, off[m] = n; hkeys,
-// hvals, hlog: the table from keys to cell indices.
+// keys; off: their first object in the sorted arrays, off[m] = n; htags,
+// hkeys, hvals, blog: the table from keys to cell ranges; fb: bits per axis of a
+// key; so: the object records in key order.
 constexpr int kGroup = 16;
 constexpr int64_t kBigCell = 64;
 
-__global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t *__restrict__ sx,
-                                                      const int32_t *__restrict__ sy,
-                                                      const int32_t *__restrict__ sz,
-                                                      const int32_t *__restrict__ sr,
-                                                      const uint64_t *__restrict__ ukeys,
-                                                      const uint32_t *__restrict__ off,
-                                                      const uint32_t *__restrict__ m_ptr,
-                                                      const uint64_t *__restrict__ hkeys,
-                                                      const uint32_t *__restrict__ hvals,
-                                                      int hlog, uint32_t *big, uint32_t *big_n,
-                                                      uint64_t *count) {
+// Eight waves per SIMD: the loop waits on loads, so occupancy pays.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_bin_count(
+    const int4 *__restrict__ so, const uint64_t *__restrict__ ukeys,
+    const uint32_t *__restrict__ off, const uint32_t *__restrict__ m_ptr,
+    const uint64_t *__restrict__ htags, const uint64_t *__restrict__ hkeys,
+    const uint2 *__restrict__ hvals, int blog, int fb, uint32_t *big, uint32_t *big_n,
+    uint64_t *count) {
     const int lane = threadIdx.x & (kWave - 1);
     const int gl = lane % kGroup, g0 = lane - gl;
     const int64_t m = *m_ptr;
     const int64_t groups = (int64_t)gridDim.x * (kBlock / kGroup);
     uint64_t cnt = 0;
-    for (int64_t c = (int64_t)blockIdx.x * (kBlock / kGroup) + threadIdx.x / kGroup; c < m;
-         c += groups) {
-        if ((int64_t)off[c + 1] - off[c] > kBigCell) {
+    int64_t c = (int64_t)blockIdx.x * (kBlock / kGroup) + threadIdx.x / kGroup;
+    // the next cell's offsets and key are loaded one iteration ahead, so that
+    // they are in flight together with the current cell's lookups
+    uint32_t o0 = 0, o1 = 0;
+    uint64_t key = 0;
+    if (c < m) o0 = off[c], o1 = off[c + 1], key = ukeys[c];
+    for (; c < m; c += groups) {
+        const int64_t cn = c + groups;
+        uint32_t p0 = 0, p1 = 0;
+        uint64_t pk = 0;
+        if (cn < m) p0 = off[cn], p1 = off[cn + 1], pk = ukeys[cn];
+        const int64_t n = (int64_t)o1 - o0;
+        if (n > kBigCell) {
             if (gl == 0) big[atomicAdd(big_n, 1u)] = (uint32_t)c;
-            continue;
+        } else {
+            cnt += count_cell<kGroup>(o0, n, key, gl, g0, so, htags, hkeys, hvals, blog, fb);
         }
-        cnt += count_cell<kGroup>(c, gl, g0, sx, sy, sz, sr, ukeys, off, hkeys, hvals, hlog);
+        o0 = p0, o1 = p1, key = pk;
     }
     wave_count_to(count, cnt);
 }
 
 // Big cells: one wave per cell of the list.
-__global__ __launch_bounds__(kBlock) void k_bin_count_big(const int32_t *__restrict__ sx,
-                                                          const int32_t *__restrict__ sy,
-                                                          const int32_t *__restrict__ sz,
-                                                          const int32_t *__restrict__ sr,
+__global__ __launch_bounds__(kBlock) void k_bin_count_big(const int4 *__restrict__ so,
                                                           const uint64_t *__restrict__ ukeys,
                                                           const uint32_t *__restrict__ off,
+                                                          const uint64_t *__restrict__ htags,
                                                           const uint64_t *__restrict__ hkeys,
-                                                          const uint32_t *__restrict__ hvals,
-                                                          int hlog, const uint32_t *big,
+                                                          const uint2 *__restrict__ hvals,
+                                                          int blog, int fb, const uint32_t *big,
                                                           const uint32_t *big_n,
                                                           uint64_t *count) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -255,8 +295,11 @@ __global__ __launch_bounds__(kBlock) void k_bin_count_big(const int32_t *__restr
     const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
     uint64_t cnt = 0;
     for (int64_t q = (int64_t)blockIdx.x * (kBlock / kWave) + pairs_dev::wave_id(); q < nbig;
-         q += waves)
-        cnt += count_cell<kWave>(big[q], lane, 0, sx, sy, sz, sr, ukeys, off, hkeys, hvals, hlog);
+         q += waves) {
+        const uint32_t c = big[q];
+        cnt += count_cell<kWave>(off[c], (int64_t)off[c + 1] - off[c], ukeys[c], lane, 0, so,
+                                 htags, hkeys, hvals, blog, fb);
+    }
     wave_count_to(count, cnt);
 }
 

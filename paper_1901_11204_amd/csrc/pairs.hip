@@ -1092,18 +1092,40 @@ namespace bin = pairs_binning;
 
 // Workspace layout of a binned count of n objects.
 struct BinnedLayout {
-    size_t keys_in, keys_out, idx_in, idx_out, sx, sy, sz, sr, ukeys, sizes, off, runs, temp;
-    size_t hkeys, hvals, big, big_n;
+    size_t keys_in, keys_out, idx_in, idx_out, so, ukeys, sizes, off, runs, temp;
+    size_t htags, hkeys, hvals, hcnt, big, big_n;
     size_t temp_bytes, total;
-    int hlog;  // cell table of 2^hlog slots, at least 2n
+    int blog;  // cell table of 2^blog buckets of 8 slots, at least 2n slots
 };
+
+// The key sort always runs as radix passes over the key's bits (rocPRIM's
+// onesweep).  By default rocPRIM merge-sorts up to 2^20 keys, in a block sort
+// and ten merge passes whatever the key width.
+using BinSortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                                 rocprim::default_config, 0>;
+
+// Bits per axis of a cell key: the fewest that hold the largest neighbour
+// coordinate, 2^25 / cell + 2.
+int binned_field_bits(int32_t cell) {
+    const int64_t top = ((int64_t)1 << 25) / cell + 2;
+    int fb = 1;
+    while (((int64_t)1 << fb) <= top) ++fb;
+    return fb;
+}
+
+hipError_t binned_sort(void *temp, size_t &bytes, const uint64_t *keys_in, uint64_t *keys_out,
+                       const uint32_t *idx_in, uint32_t *idx_out, int64_t n, int end_bit,
+                       hipStream_t s) {
+    return rocprim::radix_sort_pairs<BinSortConfig>(temp, bytes, keys_in, keys_out, idx_in,
+                                                    idx_out, (size_t)n, 0u, (unsigned)end_bit, s);
+}
 
 pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
     size_t t1 = 0, t2 = 0, t3 = 0;
     if (n > 0) {
-        if (rocprim::radix_sort_pairs(nullptr, t1, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                                      (const uint32_t *)nullptr, (uint32_t *)nullptr, (size_t)n, 0,
-                                      63) != hipSuccess ||
+        // the widest keys (cells of 32) need the most temporary storage
+        if (binned_sort(nullptr, t1, nullptr, nullptr, nullptr, nullptr, n,
+                        3 * bin::kMaxCellBits, 0) != hipSuccess ||
             rocprim::run_length_encode(nullptr, t2, (const uint64_t *)nullptr, (unsigned)n,
                                        (uint64_t *)nullptr, (uint32_t *)nullptr,
                                        (uint32_t *)nullptr) != hipSuccess ||
@@ -1122,18 +1144,20 @@ pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
     L->keys_out = take(8 * un);
     L->idx_in = take(4 * un);
     L->idx_out = take(4 * un);
-    L->sx = take(4 * un);
-    L->sy = take(4 * un);
-    L->sz = take(4 * un);
-    L->sr = take(4 * un);
+    L->so = take(16 * un);
     L->ukeys = take(8 * un);
     L->sizes = take(4 * (un + 1));
     L->off = take(4 * (un + 1));
     L->runs = take(4);
-    L->hlog = 1;
-    while ((int64_t(1) << L->hlog) < 2 * std::max<int64_t>(n, 1)) ++L->hlog;
-    L->hkeys = take(8 * (size_t(1) << L->hlog));
-    L->hvals = take(4 * (size_t(1) << L->hlog));
+    L->blog = 1;
+    while ((int64_t(bin::kSlots) << L->blog) < 2 * std::max<int64_t>(n, 1)) ++L->blog;
+    const size_t slots = size_t(bin::kSlots) << L->blog;
+    L->htags = take(slots);
+    // hkeys also holds the unsorted object records (16 bytes each, at most
+    // 8 * slots) until the gather, before the table is cleared
+    L->hkeys = take(8 * slots);
+    L->hvals = take(8 * slots);
+    L->hcnt = take(4 * (size_t(1) << L->blog));
     L->big = take(4 * un);
     L->big_n = take(8);
     L->temp_bytes = std::max(t1, std::max(t2, t3));
@@ -1979,19 +2003,21 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
     unsigned char *w = (unsigned char *)d_ws;
     uint64_t *keys_in = (uint64_t *)(w + L.keys_in), *keys_out = (uint64_t *)(w + L.keys_out);
     uint32_t *idx_in = (uint32_t *)(w + L.idx_in), *idx_out = (uint32_t *)(w + L.idx_out);
-    int32_t *sx = (int32_t *)(w + L.sx), *sy = (int32_t *)(w + L.sy), *sz = (int32_t *)(w + L.sz),
-            *sr = (int32_t *)(w + L.sr);
+    int4 *so = (int4 *)(w + L.so), *rec = (int4 *)(w + L.hkeys);
     uint64_t *ukeys = (uint64_t *)(w + L.ukeys);
     uint32_t *sizes = (uint32_t *)(w + L.sizes), *off = (uint32_t *)(w + L.off);
     uint32_t *runs = (uint32_t *)(w + L.runs);
     void *temp = w + L.temp;
     size_t tb = L.temp_bytes;
     const int nb = blocks_for(n, 256);
-    bin::k_bin_keys<<<nb, 256, 0, s>>>(x, y, z, n, cell, keys_in, idx_in);
+    const int fb = binned_field_bits(cell);
+    size_t need = 0;
+    PAIRS_HIP_CHECK(binned_sort(nullptr, need, nullptr, nullptr, nullptr, nullptr, n, 3 * fb, s));
+    if (need > tb) return PAIRS_ERR_WORKSPACE;
+    bin::k_bin_keys<<<nb, 256, 0, s>>>(x, y, z, r, n, cell, fb, keys_in, idx_in, rec);
     PAIRS_HIP_CHECK(hipGetLastError());
-    PAIRS_HIP_CHECK(rocprim::radix_sort_pairs(temp, tb, keys_in, keys_out, idx_in, idx_out,
-                                              (size_t)n, 0, 63, s));
-    bin::k_bin_gather<<<nb, 256, 0, s>>>(x, y, z, r, idx_out, n, sx, sy, sz, sr);
+    PAIRS_HIP_CHECK(binned_sort(temp, tb, keys_in, keys_out, idx_in, idx_out, n, 3 * fb, s));
+    bin::k_bin_gather<<<nb, 256, 0, s>>>(rec, idx_out, n, so);
     bin::k_bin_clear_u32<<<blocks_for(n + 1, 256), 256, 0, s>>>(sizes, n + 1);
     PAIRS_HIP_CHECK(hipGetLastError());
     tb = L.temp_bytes;
@@ -2001,20 +2027,25 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
     PAIRS_HIP_CHECK(rocprim::exclusive_scan(temp, tb, sizes, off, 0u, (size_t)n + 1,
                                             rocprim::plus<uint32_t>(), s));
     uint64_t *hkeys = (uint64_t *)(w + L.hkeys);
-    uint32_t *hvals = (uint32_t *)(w + L.hvals);
-    PAIRS_TRY(fill_u64(hkeys, int64_t(1) << L.hlog, 0, s));
-    bin::k_bin_hash_build<<<nb, 256, 0, s>>>(ukeys, runs, hkeys, hvals, L.hlog);
+    uint2 *hvals = (uint2 *)(w + L.hvals);
+    uint32_t *hcnt = (uint32_t *)(w + L.hcnt);
+    uint8_t *htags = (uint8_t *)(w + L.htags);
+    PAIRS_TRY(fill_u64((uint64_t *)htags, int64_t(1) << L.blog, 0, s));
+    bin::k_bin_clear_u32<<<blocks_for(int64_t(1) << L.blog, 256), 256, 0, s>>>(
+        hcnt, int64_t(1) << L.blog);
+    bin::k_bin_hash_build<<<nb, 256, 0, s>>>(ukeys, off, runs, htags, hkeys, hvals, hcnt, L.blog);
     uint32_t *big = (uint32_t *)(w + L.big), *big_n = (uint32_t *)(w + L.big_n);
     PAIRS_TRY(fill_u64((uint64_t *)big_n, 1, 0, s));
     // 16 lanes per small cell, one wave per big one, at most a few waves per
     // SIMD of the device
     const int64_t blocks = std::min<int64_t>((n + 15) / 16, (int64_t)st->n_cu * 16);
     bin::k_bin_count<<<(unsigned)blocks, bin::kBlock, 0, s>>>(
-        sx, sy, sz, sr, ukeys, off, runs, hkeys, hvals, L.hlog, big, big_n, d_count);
+        so, ukeys, off, runs, (const uint64_t *)htags, hkeys, hvals, L.blog, fb, big, big_n,
+        d_count);
     const int64_t big_blocks = std::min<int64_t>((n / bin::kBigCell + 3) / 4 + 1,
                                                  (int64_t)st->n_cu * 16);
     bin::k_bin_count_big<<<(unsigned)big_blocks, bin::kBlock, 0, s>>>(
-        sx, sy, sz, sr, ukeys, off, hkeys, hvals, L.hlog, big, big_n, d_count);
+        so, ukeys, off, (const uint64_t *)htags, hkeys, hvals, L.blog, fb, big, big_n, d_count);
     PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;
 }
