@@ -152,24 +152,33 @@ __global__ void k_bin_hash_build(const uint64_t *__restrict__ ukeys,
     }
 }
 
-// First object and size of the occupied cell with `key`, or size 0.
+// 0x80 in each byte of x that is zero, 0 elsewhere (exact: no carry crosses
+// a byte, since (b & 0x7F) + 0x7F <= 0xFE).
+__device__ __forceinline__ uint64_t zero_bytes(uint64_t x) {
+    constexpr uint64_t lo7 = 0x7F7F7F7F7F7F7F7Full;
+    return ~(((x & lo7) + lo7) | x | lo7);
+}
+
+// First object and size of the occupied cell with `key`, or size 0.  The
+// tag word is matched with whole-word arithmetic, so the common case (no
+// matching tag) takes no per-slot branch.
 __device__ __forceinline__ uint2 find_cell(const uint64_t *__restrict__ htags,
                                            const uint64_t *__restrict__ hkeys,
                                            const uint2 *__restrict__ hvals, int blog,
                                            uint64_t key) {
     const uint64_t h = cell_hash(key);
-    const uint32_t mask = (1u << blog) - 1, tag = cell_tag(h, blog);
+    const uint32_t mask = (1u << blog) - 1;
+    const uint64_t tags = 0x0101010101010101ull * cell_tag(h, blog);
     uint32_t b = home_bucket(h, blog);
     for (uint32_t p = 0; p <= mask; ++p, b = (b + 1) & mask) {
         const uint64_t tw = htags[b];
-        bool room = false;
-        for (int i = 0; i < kSlots; ++i) {
-            const uint32_t t = (uint32_t)(tw >> (8 * i)) & 0xFFu;
-            room |= t == 0;
-            if (t == tag && hkeys[(size_t)b * kSlots + i] == key)
-                return hvals[(size_t)b * kSlots + i];
+        uint64_t hit = zero_bytes(tw ^ tags);
+        while (hit) {
+            const size_t slot = (size_t)b * kSlots + (__builtin_ctzll(hit) >> 3);
+            hit &= hit - 1;
+            if (hkeys[slot] == key) return hvals[slot];
         }
-        if (room) break;
+        if (zero_bytes(tw)) break;  // the bucket has room: the key is nowhere further
     }
     return make_uint2(0, 0);
 }
