@@ -11,27 +11,28 @@
 // order), which meets every pair of neighbouring cells once.
 //
 // Pipeline (all on the device, no host synchronisation):
+//   0. k_bin_clear: every buffer that has to start at zero, in one launch;
 //   1. k_bin_keys: cell coordinates (x + 2^24) / L + 1 per axis (the +1 keeps
 //      the -1 neighbours of cell 0 in range), packed fb bits per axis into a
 //      64-bit key, and the object index.  fb is the fewest bits that hold
 //      2^25 / L + 2, the largest neighbour coordinate: 21 for L = 32, 11 for
-//      L = 2^15;
+//      L = 2^15.  Each object is also written as one 16-byte record;
 //   2. radix sort of (key, index) over the key's 3 fb bits (rocPRIM);
-//   3. k_bin_gather: the objects in key order, structure of arrays;
+//   3. k_bin_gather: the records in key order;
 //   4. run-length encoding of the sorted keys (rocPRIM) into the occupied
 //      cells' keys and sizes, and an exclusive scan of the sizes into cell
 //      offsets;
 //   5. k_bin_hash_build: a hash table of 8-slot buckets from occupied cell
-//      keys to their indices;
+//      keys to each cell's first object and size;
 //   6. k_bin_count: 16 lanes per occupied cell (cells of more than 64
 //      objects go to a list that k_bin_count_big counts, one wave per cell).
 //      Lanes 0..12 of a group look up the 13 forward neighbours in the
-//      table; the pairs inside
-//      the cell run on the balanced circular assignment (each lane takes rows
-//      and their steps s = 1 .. floor((n-1)/2), rows i < n/2 also s = n/2
-//      when n is even); the pairs with each neighbour run with the lanes
-//      taking the cell's objects against all of the neighbour's.  Wave sums
-//      go to the count with one atomic per wave.
+//      table; the pairs inside the cell run on the balanced circular
+//      assignment (each lane takes rows and their steps s = 1 ..
+//      floor((n-1)/2), rows i < n/2 also s = n/2 when n is even); the pairs
+//      with each occupied neighbour run with the lanes taking the cell's
+//      objects against all of the neighbour's.  Wave sums go to the count
+//      with one atomic per wave.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -312,11 +313,22 @@ __global__ __launch_bounds__(kBlock) void k_bin_count_big(const int4 *__restrict
     wave_count_to(count, cnt);
 }
 
-// Clears the cell sizes before the run-length encoding: the scan then runs
-// over n + 1 sizes, zero past the m occupied cells, so that off[m] = n.
-__global__ void k_bin_clear_u32(uint32_t *p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
+// Ranges of 32-bit words that the pipeline needs zeroed, cleared by one
+// launch (blockIdx.y picks the range): the count, the cell sizes (the scan
+// runs over n + 1 sizes, zero past the m occupied cells, so that off[m] = n),
+// the table's tags and claim counts, and the number of big cells.
+constexpr int kClearRanges = 5;
+struct ClearRanges {
+    uint32_t *p[kClearRanges];
+    int64_t n[kClearRanges];
+};
+
+__global__ void k_bin_clear(ClearRanges r) {
+    uint32_t *p = r.p[blockIdx.y];
+    const int64_t n = r.n[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 }  // namespace pairs_binning

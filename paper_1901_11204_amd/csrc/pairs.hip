@@ -1101,8 +1101,12 @@ struct BinnedLayout {
 // The key sort always runs as radix passes over the key's bits (rocPRIM's
 // onesweep).  By default rocPRIM merge-sorts up to 2^20 keys, in a block sort
 // and ten merge passes whatever the key width.
-using BinSortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
-                                                 rocprim::default_config, 0>;
+using BinSortConfig = rocprim::radix_sort_config<
+    rocprim::default_config, rocprim::default_config,
+    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<512, 32>,
+                                        rocprim::kernel_config<512, 12>, 10,
+                                        rocprim::block_radix_rank_algorithm::match>,
+    0>;
 
 // Bits per axis of a cell key: the fewest that hold the largest neighbour
 // coordinate, 2^25 / cell + 2.
@@ -1998,8 +2002,7 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
             if (n > 0)
                 bin::k_bin_validate<<<blocks_for(n, 256), 256, 0, s>>>(x, y, z, r, n, cell, flag);
         }));
-    PAIRS_TRY(fill_u64(d_count, 1, 0, s));
-    if (n < 2) return PAIRS_OK;
+    if (n < 2) return fill_u64(d_count, 1, 0, s);
     unsigned char *w = (unsigned char *)d_ws;
     uint64_t *keys_in = (uint64_t *)(w + L.keys_in), *keys_out = (uint64_t *)(w + L.keys_out);
     uint32_t *idx_in = (uint32_t *)(w + L.idx_in), *idx_out = (uint32_t *)(w + L.idx_out);
@@ -2014,11 +2017,21 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
     size_t need = 0;
     PAIRS_HIP_CHECK(binned_sort(nullptr, need, nullptr, nullptr, nullptr, nullptr, n, 3 * fb, s));
     if (need > tb) return PAIRS_ERR_WORKSPACE;
+    uint64_t *hkeys = (uint64_t *)(w + L.hkeys);
+    uint2 *hvals = (uint2 *)(w + L.hvals);
+    uint32_t *hcnt = (uint32_t *)(w + L.hcnt);
+    uint8_t *htags = (uint8_t *)(w + L.htags);
+    uint32_t *big = (uint32_t *)(w + L.big), *big_n = (uint32_t *)(w + L.big_n);
+    const int64_t buckets = int64_t(1) << L.blog;
+    bin::ClearRanges cr = {{(uint32_t *)d_count, sizes, (uint32_t *)htags, hcnt, big_n},
+                           {2, n + 1, buckets * bin::kSlots / 4, buckets, 1}};
+    bin::k_bin_clear<<<dim3((unsigned)std::min<int64_t>(blocks_for(n + 1, 256), 2048),
+                            bin::kClearRanges),
+                       256, 0, s>>>(cr);
     bin::k_bin_keys<<<nb, 256, 0, s>>>(x, y, z, r, n, cell, fb, keys_in, idx_in, rec);
     PAIRS_HIP_CHECK(hipGetLastError());
     PAIRS_HIP_CHECK(binned_sort(temp, tb, keys_in, keys_out, idx_in, idx_out, n, 3 * fb, s));
     bin::k_bin_gather<<<nb, 256, 0, s>>>(rec, idx_out, n, so);
-    bin::k_bin_clear_u32<<<blocks_for(n + 1, 256), 256, 0, s>>>(sizes, n + 1);
     PAIRS_HIP_CHECK(hipGetLastError());
     tb = L.temp_bytes;
     PAIRS_HIP_CHECK(rocprim::run_length_encode(temp, tb, keys_out, (unsigned)n, ukeys, sizes,
@@ -2026,16 +2039,7 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
     tb = L.temp_bytes;
     PAIRS_HIP_CHECK(rocprim::exclusive_scan(temp, tb, sizes, off, 0u, (size_t)n + 1,
                                             rocprim::plus<uint32_t>(), s));
-    uint64_t *hkeys = (uint64_t *)(w + L.hkeys);
-    uint2 *hvals = (uint2 *)(w + L.hvals);
-    uint32_t *hcnt = (uint32_t *)(w + L.hcnt);
-    uint8_t *htags = (uint8_t *)(w + L.htags);
-    PAIRS_TRY(fill_u64((uint64_t *)htags, int64_t(1) << L.blog, 0, s));
-    bin::k_bin_clear_u32<<<blocks_for(int64_t(1) << L.blog, 256), 256, 0, s>>>(
-        hcnt, int64_t(1) << L.blog);
     bin::k_bin_hash_build<<<nb, 256, 0, s>>>(ukeys, off, runs, htags, hkeys, hvals, hcnt, L.blog);
-    uint32_t *big = (uint32_t *)(w + L.big), *big_n = (uint32_t *)(w + L.big_n);
-    PAIRS_TRY(fill_u64((uint64_t *)big_n, 1, 0, s));
     // 16 lanes per small cell, one wave per big one, at most a few waves per
     // SIMD of the device
     const int64_t blocks = std::min<int64_t>((n + 15) / 16, (int64_t)st->n_cu * 16);
