@@ -533,11 +533,14 @@ def main():
         msb, _ = timed_steps(lambda: P.pairs_count_i32_binned(x, y, z, r, 1 << 15, outb, wsb),
                              max(5, a.steps), 2)
         mb = float(np.median(msb))
-        # algorithmic HBM bytes per object: read 16 B of input and write 12 B
-        # of key and index; eight 8-bit radix passes read and write 12 B
-        # each; the gather reads 4 + 16 B and writes 16 B; run-length
-        # encoding and scan about 24 B; the count reads 16 B
-        bpo = 16 + 12 + 8 * 24 + 36 + 24 + 16
+        # algorithmic HBM bytes per object: read 16 B of input and write 28 B
+        # of key, index and record; the histogram reads the 8 B keys; four
+        # 10-bit radix passes over the 33 key bits read and write 12 B each;
+        # the gather reads 4 + 16 B and writes 16 B; run-length encoding
+        # reads 8 B and writes 12 B and the scan reads and writes 4 B; the
+        # table reads 16 B and writes 17 B per cell (about one per object
+        # here); the count reads the 16 B records
+        bpo = 16 + 28 + 8 + 4 * 24 + 36 + 20 + 8 + 33 + 16
         sec["count_i32_binned_2^20"] = {
             "ms": mb, "cell": 1 << 15, "count": int(outb.item()),
             "matches_oracle": int(outb.item()) == golden()["config2_even_count"],
