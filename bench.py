@@ -364,6 +364,32 @@ def bench_batched(P, w, torch, np, dev, steps):
     return out
 
 
+def bench_binned(P, torch, np, dev, xyzr, steps, ms_all_pairs=None):
+    """The binned count of the 2^20-sphere set with cells of 2^15."""
+    n = xyzr[0].numel()
+    log("[bench] binned count_i32 N=2^20, cells of 2^15")
+    wsb = torch.empty(P.pairs_binned_workspace_size(n), dtype=torch.uint8, device=dev)
+    outb = torch.empty(1, dtype=torch.int64, device=dev)
+    msb, _ = timed_steps(lambda: P.pairs_count_i32_binned(*xyzr, 1 << 15, outb, wsb), steps, 2)
+    mb = float(np.median(msb))
+    # algorithmic HBM bytes per object: read 16 B of input and write 28 B
+    # of key, index and record; the histogram reads the 8 B keys; four
+    # 10-bit radix passes over the 33 key bits read and write 12 B each;
+    # the gather reads 4 + 16 B and writes 16 B; run-length encoding
+    # reads 8 B and writes 12 B and the scan reads and writes 4 B; the
+    # table reads 16 B and writes 17 B per cell (about one per object
+    # here); the count reads the 16 B records
+    bpo = 16 + 28 + 8 + 4 * 24 + 36 + 20 + 8 + 33 + 16
+    res = {"ms": mb, "cell": 1 << 15, "count": int(outb.item()),
+           "matches_oracle": int(outb.item()) == golden()["config2_even_count"],
+           "roofline": {"bound": "hbm", "achieved": n * bpo / (mb * 1e-3) / 1e9,
+                        "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                        "frac": n * bpo / (mb * 1e-3) / HBM_PEAK, "bytes_per_object": bpo}}
+    if ms_all_pairs:
+        res["speedup_vs_all_pairs"] = ms_all_pairs / mb
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -380,6 +406,8 @@ def main():
                     help="only run the batched lines (for profiling their kernels)")
     ap.add_argument("--lattice-only", action="store_true",
                     help="only the lattice-bead counts (for profiling)")
+    ap.add_argument("--binned-only", action="store_true",
+                    help="only the binned count of the 2^20 set (for profiling)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
@@ -414,6 +442,10 @@ def main():
         return
     if a.lattice_only:
         print(json.dumps({"lattice": bench_lattice(P, w, torch, np, dev, a.steps)}), flush=True)
+        return
+    if a.binned_only:
+        xyzr = tuple(torch.from_numpy(v).to(dev) for v in w.config2(2 ** 20).arrays())
+        print(json.dumps({"binned": bench_binned(P, torch, np, dev, xyzr, a.steps)}), flush=True)
         return
 
     # headline workload
@@ -527,28 +559,8 @@ def main():
                                  "max_err_over_norm_sum_vs_fp64_oracle": err,
                                  "sampled_rows": len(gf["rows"])}
         del Fxyz
-        log("[bench] binned count_i32 N=2^20, cells of 2^15")
-        wsb = torch.empty(P.pairs_binned_workspace_size(n), dtype=torch.uint8, device=dev)
-        outb = torch.empty(1, dtype=torch.int64, device=dev)
-        msb, _ = timed_steps(lambda: P.pairs_count_i32_binned(x, y, z, r, 1 << 15, outb, wsb),
-                             max(5, a.steps), 2)
-        mb = float(np.median(msb))
-        # algorithmic HBM bytes per object: read 16 B of input and write 28 B
-        # of key, index and record; the histogram reads the 8 B keys; four
-        # 10-bit radix passes over the 33 key bits read and write 12 B each;
-        # the gather reads 4 + 16 B and writes 16 B; run-length encoding
-        # reads 8 B and writes 12 B and the scan reads and writes 4 B; the
-        # table reads 16 B and writes 17 B per cell (about one per object
-        # here); the count reads the 16 B records
-        bpo = 16 + 28 + 8 + 4 * 24 + 36 + 20 + 8 + 33 + 16
-        sec["count_i32_binned_2^20"] = {
-            "ms": mb, "cell": 1 << 15, "count": int(outb.item()),
-            "matches_oracle": int(outb.item()) == golden()["config2_even_count"],
-            "speedup_vs_all_pairs": ms_step / mb,
-            "roofline": {"bound": "hbm", "achieved": n * bpo / (mb * 1e-3) / 1e9,
-                         "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                         "frac": n * bpo / (mb * 1e-3) / HBM_PEAK, "bytes_per_object": bpo}}
-        del wsb
+        sec["count_i32_binned_2^20"] = bench_binned(P, torch, np, dev, (x, y, z, r),
+                                                    max(5, a.steps), ms_step)
         log("[bench] assignment comparison: balanced vs straightforward, N=2^20")
         sec["assignment_comparison_n2p20"] = assignment_comparison(torch, x, y, z, r, n, count,
                                                                    max(2, a.steps // 2))
