@@ -42,17 +42,43 @@ def test_binned_matches_oracle(n, span, cell):
     assert binned(a, cell) == oracle.count_i32(*a)
 
 
-def test_cell_boundaries_and_domain_edges():
+# cells of 32 give the widest keys (21 bits per axis, 63 in all), cells of
+# 2^15 the 33-bit keys of the 2^20 set, cells of 2^16 keys of 30 bits and
+# cells of 2^25 keys of 6 bits
+@pytest.mark.parametrize("cell", [32, 64, 1 << 15, 1 << 16, 1 << 25])
+def test_cell_boundaries_and_domain_edges(cell):
     # objects exactly on cell faces and at both ends of the domain, touching
     # across faces with radii of exactly half a cell
-    cell = 64
     B = 1 << 24
-    base = np.array([-B, -B + 63, -B + 64, -1, 0, 63, 64, 65, B - 64, B - 1, B], np.int64)
+    base = np.array([-B, -B + cell - 1, -B + cell, -1, 0, cell - 1, cell, cell + 1, B - cell,
+                     B - 1, B], np.int64)
+    base = np.clip(base, -B, B)
     g = np.stack(np.meshgrid(base, base[::3], base[::5], indexing="ij"), -1).reshape(-1, 3)
     x, y, z = (np.ascontiguousarray(g[:, k].astype(np.int32)) for k in range(3))
     r = np.full(x.shape[0], cell // 2, np.int32)
-    announce("binned boundaries")
+    announce("binned boundaries", cell)
     assert binned([x, y, z, r], cell) == oracle.count_i32(x, y, z, r)
+
+
+@pytest.mark.parametrize("cell", [32, 1 << 16, 1 << 25])
+def test_corner_clusters_over_the_whole_domain(cell):
+    # a third of the objects spread over the whole domain and a third in a
+    # block of 6 x 6 x 6 cells at each corner, where the cell keys take
+    # their lowest and highest values
+    B = 1 << 24
+    rng = np.random.default_rng(cell)
+    k = 6000
+    side = min(6 * cell, 2 * B)
+    spread = rng.integers(-B, B, (k, 3), endpoint=True)
+    low = rng.integers(-B, -B + side, (k, 3), endpoint=True)
+    high = rng.integers(B - side, B, (k, 3), endpoint=True)
+    xyz = np.vstack([spread, low, high]).astype(np.int32)
+    r = rng.integers(0, cell // 2, xyz.shape[0], dtype=np.int32, endpoint=True)
+    a = [np.ascontiguousarray(xyz[:, j]) for j in range(3)] + [r]
+    announce("binned corner clusters", cell)
+    want = oracle.count_i32(*a)
+    assert want > 1000
+    assert binned(a, cell) == want
 
 
 def test_one_dense_cell_and_clusters():
