@@ -323,8 +323,10 @@ pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t
  * PAIRS_BINNED_MAX_SET_SIZE objects.  Outside it the result is undefined
  * unless PAIRS_FLAG_VALIDATE is given (then PAIRS_ERR_DOMAIN).
  * Workspace: pairs_binned_workspace_size(n) bytes of device memory, owned by
- * the caller (about 110 to 150 bytes per object, the sort's temporary
- * storage included).
+ * the caller (about 110 bytes per object at 2^20 objects, the sort's
+ * temporary storage included).  The size query asks rocPRIM for the sort's
+ * storage on the current device, so it needs a HIP device (PAIRS_ERR_HIP
+ * otherwise, with the HIP error in pairs_last_hip_error()).
  * Stream-ordered, with no host synchronisation, but not to be captured into
  * a HIP graph: the radix sort (rocPRIM) clears its own state with
  * hipMemsetAsync.

@@ -94,12 +94,12 @@ __global__ void k_bin_gather(const int4 *__restrict__ rec, const uint32_t *__res
     so[i] = rec[perm[i]];
 }
 
-// Touch test in 64-bit integers: coordinates lie in [-2^24, 2^24] and radii
-// in [0, 2^24], so every square and sum stays below 2^53.
+// Touch test: coordinates lie in [-2^24, 2^24] and radii in [0, 2^24], so
+// the differences and the radius sum fit 32 bits (at most 2^25 in size) and
+// the squares and their sum fit 64 bits exactly.
 __device__ __forceinline__ bool touch(int4 a, int4 b) {
-    const int64_t dx = (int64_t)a.x - b.x, dy = (int64_t)a.y - b.y, dz = (int64_t)a.z - b.z;
-    const int64_t R = (int64_t)a.w + b.w;
-    return dx * dx + dy * dy + dz * dz <= R * R;
+    const int dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, R = a.w + b.w;
+    return (int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz <= (int64_t)R * R;
 }
 
 // Cells by key: a table of 2^blog buckets of kSlots slots (at least twice as
@@ -230,10 +230,17 @@ __device__ __forceinline__ uint64_t count_cell(int64_t a0, int64_t n, uint64_t k
     while (occ) {
         const int d = __builtin_ctz(occ);
         occ &= occ - 1;
-        const int64_t nbn = (uint32_t)__shfl((int)nb.y, g0 + d, kWave);
-        const int64_t b0 = (uint32_t)__shfl((int)nb.x, g0 + d, kWave);
+        int nbn32 = __shfl((int)nb.y, g0 + d, kWave), b032 = __shfl((int)nb.x, g0 + d, kWave);
+        if constexpr (G == kWave) {
+            // one cell per wave: the neighbour's records are wave-uniform
+            // reads, which go through the scalar unit
+            nbn32 = __builtin_amdgcn_readfirstlane(nbn32);
+            b032 = __builtin_amdgcn_readfirstlane(b032);
+        }
+        const int64_t nbn = (uint32_t)nbn32, b0 = (uint32_t)b032;
         for (int64_t i = gl; i < n; i += G) {
             const int4 oi = so[a0 + i];
+#pragma unroll 4
             for (int64_t j = 0; j < nbn; ++j) cnt += touch(oi, so[b0 + j]);
         }
     }

@@ -1127,15 +1127,16 @@ hipError_t binned_sort(void *temp, size_t &bytes, const uint64_t *keys_in, uint6
 pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
     size_t t1 = 0, t2 = 0, t3 = 0;
     if (n > 0) {
-        // the widest keys (cells of 32) need the most temporary storage
-        if (binned_sort(nullptr, t1, nullptr, nullptr, nullptr, nullptr, n,
-                        3 * bin::kMaxCellBits, 0) != hipSuccess ||
-            rocprim::run_length_encode(nullptr, t2, (const uint64_t *)nullptr, (unsigned)n,
-                                       (uint64_t *)nullptr, (uint32_t *)nullptr,
-                                       (uint32_t *)nullptr) != hipSuccess ||
-            rocprim::exclusive_scan(nullptr, t3, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                    0u, (size_t)n + 1, rocprim::plus<uint32_t>()) != hipSuccess)
-            return PAIRS_ERR_HIP;
+        // the widest keys (cells of 32) need the most temporary storage;
+        // rocPRIM sizes it for the current device's architecture
+        PAIRS_HIP_CHECK(binned_sort(nullptr, t1, nullptr, nullptr, nullptr, nullptr, n,
+                                    3 * bin::kMaxCellBits, 0));
+        PAIRS_HIP_CHECK(rocprim::run_length_encode(nullptr, t2, (const uint64_t *)nullptr,
+                                                   (unsigned)n, (uint64_t *)nullptr,
+                                                   (uint32_t *)nullptr, (uint32_t *)nullptr));
+        PAIRS_HIP_CHECK(rocprim::exclusive_scan(nullptr, t3, (const uint32_t *)nullptr,
+                                                (uint32_t *)nullptr, 0u, (size_t)n + 1,
+                                                rocprim::plus<uint32_t>()));
     }
     size_t p = 0;
     auto take = [&](size_t bytes) {
