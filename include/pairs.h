@@ -324,9 +324,9 @@ pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t
  * unless PAIRS_FLAG_VALIDATE is given (then PAIRS_ERR_DOMAIN).
  * Workspace: pairs_binned_workspace_size(n) bytes of device memory, owned by
  * the caller (about 110 bytes per object at 2^20 objects, the sort's
- * temporary storage included).  The size query asks rocPRIM for the sort's
- * storage on the current device, so it needs a HIP device (PAIRS_ERR_HIP
- * otherwise, with the HIP error in pairs_last_hip_error()).
+ * temporary storage included).  For n > 0 the size query asks rocPRIM for
+ * the sort's storage on the current device, so it needs a HIP device
+ * (PAIRS_ERR_NO_DEVICE without one).
  * Stream-ordered, with no host synchronisation, but not to be captured into
  * a HIP graph: the radix sort (rocPRIM) clears its own state with
  * hipMemsetAsync.

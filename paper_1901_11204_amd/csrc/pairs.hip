@@ -1978,6 +1978,11 @@ pairs_status_t pairs_debug_task_ranges(int n, int rows_per_lane, int chunk, int3
 
 pairs_status_t pairs_binned_workspace_size(int64_t n, size_t *bytes) {
     if (!bytes || n < 0 || n > PAIRS_BINNED_MAX_SET_SIZE) return PAIRS_ERR_INVALID_ARG;
+    if (n > 0) {
+        // the sort's storage is sized for the current device
+        int dev;
+        PAIRS_TRY(current_device(&dev));
+    }
     BinnedLayout L;
     PAIRS_TRY(binned_layout(n, &L));
     *bytes = L.total;

@@ -185,6 +185,13 @@ def test_binned_arguments_are_rejected_on_the_host():
     n_sz = ctypes.c_size_t(0)
     assert L.pairs_binned_workspace_size(-1, ctypes.byref(n_sz)) == INVALID
     assert L.pairs_binned_workspace_size(0, ctypes.byref(n_sz)) == OK
+    # n > 0 sizes the sort's storage for the current device
+    st = L.pairs_binned_workspace_size(1000, ctypes.byref(n_sz))
+    import torch
+    if torch.cuda.device_count() == 0:
+        assert st == NODEV
+    else:
+        assert st == OK and n_sz.value >= 1000 * 100
     assert L.pairs_count_i32_binned(x, y, z, r, -1, 64, out, ws, 0, 0, None) == INVALID
     assert L.pairs_count_i32_binned(x, y, z, r, 10, 16, out, ws, 0, 0, None) == INVALID
     assert L.pairs_count_i32_binned(x, y, z, r, 10, 1 << 26, out, ws, 0, 0, None) == INVALID
