@@ -81,6 +81,25 @@ def test_corner_clusters_over_the_whole_domain(cell):
     assert binned(a, cell) == want
 
 
+def test_workspace_reused_by_calls_in_a_row():
+    # one workspace for several calls: every call clears what it needs at the
+    # start (count, sizes, table tags and claims, big-cell count), so what an
+    # earlier call left there must not change a later count; the later calls
+    # are smaller, with other cell sizes, and one has big cells
+    import torch
+    cases = [(20000, 1 << 16, 1 << 12, 31), (3000, 60, 32, 32), (5000, 4096, 256, 33),
+             (20000, 1 << 16, 1 << 12, 31)]
+    ws = torch.empty(P.pairs_binned_workspace_size(20000), dtype=torch.uint8, device="cuda")
+    ws.fill_(0xA5)
+    out = torch.empty(1, dtype=torch.int64, device="cuda")
+    for n, span, cell, seed in cases:
+        a = spheres(n, seed, -span, span, cell // 2)
+        announce("binned reuse", n, span, cell)
+        P.pairs_count_i32_binned(*dev(*a), cell, out, ws)
+        torch.cuda.synchronize()
+        assert int(out.item()) == oracle.count_i32(*a)
+
+
 def test_one_dense_cell_and_clusters():
     rng = np.random.default_rng(4)
     c1 = rng.integers(0, 50, (3000, 3))           # one crowded cell
