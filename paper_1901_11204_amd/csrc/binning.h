@@ -258,8 +258,8 @@ __device__ __forceinline__ void wave_count_to(uint64_t *count, uint64_t cnt) {
 // kBigCell objects are appended to `big` (their number in big_n) for
 // k_bin_count_big.  m_ptr: number of occupied cells (device); ukeys: their
 // keys; off: their first object in the sorted arrays, off[m] = n; htags,
-// hkeys, hvals, blog: the table from keys to cell ranges; fb: bits per axis of a
-// key; so: the object records in key order.
+// hkeys, hvals, blog: the table from keys to cell ranges; fb: bits per axis
+// of a key; so: the object records in key order.
 constexpr int kGroup = 16;
 constexpr int64_t kBigCell = 64;
 
