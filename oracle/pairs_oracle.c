@@ -254,7 +254,7 @@ void oracle_energy_f64_rows(const double *x, const double *y, const double *z, i
  * and F_i = sum over j != i of f_ij, each component summed with Neumaier's
  * compensation in double.  S_i = sum over j != i of |f_ij| (the Euclidean
  * norm of each term) is the scale against which cancellation in F_i is
- * judged.  rows: the objects to compute (NULL: all n, in order). */
+ * measured.  rows: the objects to compute (NULL: all n, in order). */
 void oracle_force_rows(const float *x, const float *y, const float *z, int64_t n, float eps2f,
                        const int64_t *rows, int64_t nrows, double *Fx, double *Fy, double *Fz,
                        double *S, int threads) {
