@@ -87,23 +87,18 @@ def test_cubic_lattice_face_neighbours(m):
     assert oracle.count_i32(x - 2 ** 30, y - 12345, z + 2 ** 29, r) == 3 * m * m * (m - 1)
 
 
-def count_colls_lattice(x, y, z):
-    """The paper's O(N) collision count for point beads on a lattice (Section 3,
-    algorithm "Counting number of collisions among a vector of beads"): each
-    bead adds the number of beads already placed at its site, then is placed."""
-    space = {}
-    collisions = 0
-    for b in zip(x.tolist(), y.tolist(), z.tolist()):
-        bead_cnt = space.get(b, 0)
-        collisions += bead_cnt
-        space[b] = bead_cnt + 1
-    return collisions
+def collisions_by_site(x, y, z):
+    """Collisions of point beads from their site multiplicities (Section 3
+    counts collisions from the occupancy of lattice sites): the m beads that
+    share a site give C(m, 2) pairs."""
+    _, m = np.unique(np.stack([x, y, z], 1), axis=0, return_counts=True)
+    return int(sum(comb(int(k), 2) for k in m))
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_point_beads_match_linear_lattice_count(seed):
-    # radius 0: a collision is two beads on the same site; the paper's linear
-    # algorithm is an independent way to count them
+def test_point_beads_match_site_multiplicities(seed):
+    # radius 0: a collision is two beads on the same site; counting site
+    # multiplicities is an independent way to count them
     rng = np.random.default_rng(seed)
     n = 3000
     # random walk of beads, as in the paper's experiments (Section 5)
@@ -112,7 +107,7 @@ def test_point_beads_match_linear_lattice_count(seed):
     walk[0] = 0
     x, y, z = (walk[:, k].astype(np.int32) for k in range(3))
     r = np.zeros(n, np.int32)
-    expect = count_colls_lattice(x, y, z)
+    expect = collisions_by_site(x, y, z)
     assert expect > 0
     assert oracle.count_i32(x, y, z, r) == expect
 

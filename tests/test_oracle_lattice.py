@@ -3,9 +3,9 @@
 The oracle is the plain pairwise definition (oracle_lattice_counts in
 oracle/pairs_oracle.c).  These tests check it against facts fixed outside
 it: closed forms of regular bead arrangements, a hand-worked walk (a fixture
-under tests/golden/), the paper's own occupancy-array algorithms (countColls
-and countContacts, Section 3) written here in numpy over a dense array, and
-invariants.  A swapped predicate (collision for contact), a missing axis, a
+under tests/golden/), counts from site multiplicities (Section 3 counts from
+site occupancy; here each occupied site's multiplicity is found with
+np.unique and neighbouring sites by a sorted search), and invariants.  A swapped predicate (collision for contact), a missing axis, a
 diagonal counted as a contact, a halving error or a pair counted twice each
 fail one of them.  All run on the CPU.
 """
@@ -86,38 +86,43 @@ def test_hand_worked_walks(golden_dir):
         assert got == (c["collisions"], c["contacts"]), c["name"]
 
 
-# ------------------------------------------ the paper's algorithms, dense --
-
-def count_colls_dense(p):
-    """Section 3, countColls: one pass; each bead adds the occupancy of its
-    site so far, then occupies it.  The space is a dense array over the box."""
-    lo = p.min(axis=0) - 1
-    space = np.zeros(tuple(p.max(axis=0) - lo + 2), np.int64)
-    collisions = 0
-    for b in p - lo:
-        collisions += space[tuple(b)]
-        space[tuple(b)] += 1
-    return int(collisions)
+# --------------------------------------- site multiplicities (Section 3) --
+#
+# Section 3 counts both quantities from the occupancy of lattice sites.  The
+# same numbers follow from the multiplicity m(s) of each occupied site s:
+# the beads sharing a site give C(m(s), 2) collisions, and a site and its
+# neighbour one unit further along an axis give m(s) m(s + e) contacts (each
+# unordered pair of neighbouring sites taken once, from its lower site).
 
 
-def count_contacts_dense(p):
-    """Section 3, countContacts: place every bead, then sum the occupancy of
-    the six neighbours of every bead and halve."""
-    lo = p.min(axis=0) - 1
-    space = np.zeros(tuple(p.max(axis=0) - lo + 2), np.int64)
-    q = p - lo
-    for b in q:
-        space[tuple(b)] += 1
-    contacts = 0
-    for b in q:
-        for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
-            contacts += space[tuple(b + np.array(d))]
-    assert contacts % 2 == 0
-    return int(contacts // 2)
+def site_multiplicities(p):
+    sites, mult = np.unique(np.asarray(p, np.int64), axis=0, return_counts=True)
+    return sites, mult.astype(np.int64)
+
+
+def collisions_from_multiplicities(p):
+    _, m = site_multiplicities(p)
+    return int(np.sum(m * (m - 1) // 2))
+
+
+def contacts_from_multiplicities(p):
+    sites, m = site_multiplicities(p)
+    # encode each site as one integer so that membership is a sorted search
+    lo = sites.min(axis=0) - 1
+    span = sites.max(axis=0) - lo + 2
+    key = ((sites[:, 0] - lo[0]) * span[1] + (sites[:, 1] - lo[1])) * span[2] + (sites[:, 2] - lo[2])
+    order = np.argsort(key)
+    key, m = key[order], m[order]
+    total = 0
+    for step in (span[1] * span[2], span[2], 1):  # +x, +y, +z neighbours
+        at = np.searchsorted(key, key + step)
+        found = (at < len(key)) & (key[np.minimum(at, len(key) - 1)] == key + step)
+        total += int(np.sum(m[found] * m[at[found]]))
+    return total
 
 
 @pytest.mark.parametrize("seed", range(6))
-def test_matches_the_papers_occupancy_algorithms(seed):
+def test_matches_site_multiplicity_counts(seed):
     rng = np.random.default_rng(seed)
     n = int(rng.integers(2, 300))
     if seed % 2:
@@ -126,7 +131,7 @@ def test_matches_the_papers_occupancy_algorithms(seed):
     else:
         p = np.rint(rng.normal(0, 1.5, (n, 3))).astype(np.int64)
     got = oracle.lattice_counts(*beads(p))
-    assert got == (count_colls_dense(p), count_contacts_dense(p))
+    assert got == (collisions_from_multiplicities(p), contacts_from_multiplicities(p))
 
 
 # --------------------------------------------------------------- invariants --
