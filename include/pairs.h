@@ -59,14 +59,32 @@ enum {
     /* Check the inputs against the exact domain on the device before the
      * computation and return PAIRS_ERR_DOMAIN if any object is outside it.
      * This waits for the stream (a synchronous call). */
-    PAIRS_FLAG_VALIDATE = 1u
+    PAIRS_FLAG_VALIDATE = 1u,
+    /* Sums of doubles (energies, forces; not counts, which are exact
+     * integers in any order) reproducible bit for bit from run to run, in
+     * graphs as in eager calls: every partial sum is rounded once to a
+     * multiple of 2^-S and added as a 64-bit integer, where 2^S is the
+     * largest power of two that keeps the output's largest possible sum
+     * below 2^61 units (a bound computed from n and eps2: (n-1)/sqrt(eps2)
+     * per object, n(n-1)/2 /sqrt(eps2) per set or in total, and
+     * (n-1) * 0.4/eps2 per force component).  The added error is at most
+     * half a unit per partial sum; it stays far below float32 rounding unless
+     * the sums are many orders of magnitude below their bound (terms much
+     * smaller than 1/sqrt(eps2)).  Accepted by pairs_energy_f32,
+     * pairs_energy_f64, pairs_force_f32 and pairs_energy_f32_batched; plans
+     * take it as PAIRS_PLAN_DETERMINISTIC in their kind. */
+    PAIRS_FLAG_DETERMINISTIC = 2u
 };
 
-/* Exact domain of the int32 collision count: every coordinate in
- * [-2^24, 2^24] and every radius in [0, 2^24].  Inside it the GPU evaluates
- * the predicate exactly (see pairs_count_i32). */
-#define PAIRS_I32_COORD_LIMIT (1 << 24)
-#define PAIRS_I32_RADIUS_LIMIT (1 << 24)
+/* Exact domain of the int32 collision counts (single set and batched):
+ * every coordinate in [PAIRS_I32_COORD_MIN, PAIRS_I32_COORD_MAX] =
+ * [-2^30, 2^30 - 1] and every radius in [0, PAIRS_I32_RADIUS_MAX] = [0, 2^30].
+ * Differences then fit in int32, and squared distances (below 3 * 2^62) and
+ * squared radius sums (at most 2^62) in uint64: inside it the GPU evaluates
+ * the predicate exactly, with no check needed (see pairs_count_i32). */
+#define PAIRS_I32_COORD_MIN (-(1 << 30))
+#define PAIRS_I32_COORD_MAX ((1 << 30) - 1)
+#define PAIRS_I32_RADIUS_MAX (1 << 30)
 
 /* Largest number of objects in one set of a single-set call: row and
  * partner indices are 32-bit inside the kernels. */
@@ -79,8 +97,16 @@ enum {
 enum {
     PAIRS_KIND_COUNT_I32 = 1, /* per-set exact int32 collision counts */
     PAIRS_KIND_COUNT_F32 = 2, /* per-set pinned-binary32 collision counts */
-    PAIRS_KIND_ENERGY_F32 = 3 /* per-set potential totals, optionally with counts */
+    PAIRS_KIND_ENERGY_F32 = 3, /* per-set potential totals, optionally with counts */
+    /* the two kinds below name single-set calls for pairs_debug_single_launch
+       only; plans and shape tables do not take them */
+    PAIRS_KIND_ENERGY_F64 = 4, /* pairs_energy_f64 */
+    PAIRS_KIND_FORCE_F32 = 5   /* pairs_force_f32 */
 };
+
+/* Or'ed into the kind of pairs_plan_create (PAIRS_KIND_ENERGY_F32 only): the
+ * plan's set energies are reduced as under PAIRS_FLAG_DETERMINISTIC. */
+#define PAIRS_PLAN_DETERMINISTIC 0x100
 
 typedef struct pairs_plan_s *pairs_plan_t;
 typedef struct pairs_graph_s *pairs_graph_t;
@@ -94,9 +120,13 @@ typedef struct pairs_graph_s *pairs_graph_t;
  *
  *   *d_count = #{ i < j : (x_i-x_j)^2 + (y_i-y_j)^2 + (z_i-z_j)^2 <= (r_i+r_j)^2 }
  *
- * The result is exact for inputs in the exact domain (PAIRS_I32_*_LIMIT);
- * outside it the result is undefined unless PAIRS_FLAG_VALIDATE is given, in
- * which case the call returns PAIRS_ERR_DOMAIN and writes nothing.
+ * The result is exact for every input in the exact domain (PAIRS_I32_COORD_MIN
+ * .. PAIRS_I32_COORD_MAX, radii 0 .. PAIRS_I32_RADIUS_MAX), with no flag and
+ * no host synchronisation: objects in a smaller box take a cheaper test, and
+ * a wave switches to the full-width test for a task or a group of 64
+ * partners that leaves it.  Outside the domain the result is undefined unless
+ * PAIRS_FLAG_VALIDATE is given, in which case the call returns
+ * PAIRS_ERR_DOMAIN and writes nothing.
  * d_count: one uint64 in device memory.  n >= 0, n <= PAIRS_MAX_SET_SIZE.
  */
 pairs_status_t pairs_count_i32(const int32_t *x, const int32_t *y, const int32_t *z,
@@ -187,6 +217,7 @@ pairs_status_t pairs_count_i32_batched(const int32_t *x, const int32_t *y, const
                                        int64_t n_sets, int64_t n_total, uint64_t *d_counts,
                                        void *d_ws, size_t ws_bytes, unsigned flags,
                                        pairs_stream_t stream);
+
 
 /* d_counts[s] = collision count of set s (the pairs_count_f32 predicate). */
 pairs_status_t pairs_count_f32_batched(const float *x, const float *y, const float *z,
@@ -279,7 +310,7 @@ pairs_status_t pairs_graph_destroy(pairs_graph_t graph);
  *   set, K = rows_per_lane per lane in lane-major order, and sweeps a chunk of
  *   at most `chunk` virtual partners u = row + s, each broadcast to every
  *   lane.  rows_per_lane is 1, 2, 4 or 8; chunk a multiple of 64 in
- *   [64, 2^24].
+ *   [64, 2^22].
  * PAIRS_FORM_STEPPING: the paper's own per-row form.  Each lane holds K =
  *   rows_per_lane (1 or 2) consecutive rows and steps through their partners
  *   (row + s) mod n, `chunk` steps per task.  chunk is a multiple of 16 in
@@ -422,6 +453,28 @@ pairs_status_t pairs_debug_task_ranges(int n, int rows_per_lane, int chunk, int3
  */
 pairs_status_t pairs_debug_step_ranges(int n, int rows_per_lane, int chunk, int32_t *out,
                                        int64_t capacity, int64_t *n_tasks);
+
+/*
+ * Host-only: tasks[k] (an index below the tiling's task count) of a single set
+ * of n <= PAIRS_MAX_SET_SIZE objects decoded as the single-set kernels decode
+ * it: out[3k] = first row, out[3k+1] = u0, out[3k+2] = u1.  rows_per_lane in
+ * {1, 2, 4, 8}; chunk a multiple of 64 in [64, 2^22].  For sets too large to
+ * list every task with pairs_debug_task_ranges.
+ */
+pairs_status_t pairs_debug_task_at(int64_t n, int rows_per_lane, int chunk,
+                                   const int64_t *tasks, int64_t count, int64_t *out);
+
+/*
+ * Host-only: the launch a single-set call of `kind` (PAIRS_KIND_COUNT_I32,
+ * _COUNT_F32, _ENERGY_F32, _ENERGY_F64 or _FORCE_F32) makes for n objects
+ * with the current tile shapes: *n_tasks wave tasks of the balanced
+ * assignment (Section 4) on *n_blocks blocks of *threads work-items.  Up to
+ * 2^22 blocks each wave runs one task; a larger tiling launches 2^22 blocks
+ * whose waves stride over the tasks, so no launch exceeds 2^32 work-items for
+ * any n <= PAIRS_MAX_SET_SIZE.  0 tasks and 0 blocks for n < 2.
+ */
+pairs_status_t pairs_debug_single_launch(int kind, int64_t n, int64_t *n_tasks,
+                                         int64_t *n_blocks, int32_t *threads);
 
 /* ---------------------------------------------------------------- errors -- */
 

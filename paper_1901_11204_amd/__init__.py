@@ -15,13 +15,14 @@ import ctypes
 import os
 
 __all__ = [
-    "PairsError", "lib", "lib_path", "FLAG_VALIDATE",
+    "PairsError", "lib", "lib_path", "FLAG_VALIDATE", "FLAG_DETERMINISTIC", "PLAN_DETERMINISTIC",
     "KIND_COUNT_I32", "KIND_COUNT_F32", "KIND_ENERGY_F32",
     "pairs_count_i32", "pairs_count_f32", "pairs_energy_f32", "pairs_energy_f64",
     "pairs_force_f32",
     "pairs_batched_workspace_size", "pairs_count_i32_batched", "pairs_count_f32_batched",
     "pairs_energy_f32_batched", "pairs_jitter_f32", "pairs_debug_task_ranges",
-    "pairs_debug_step_ranges", "FORM_BROADCAST", "FORM_STEPPING",
+    "pairs_debug_step_ranges", "pairs_debug_single_launch", "pairs_debug_task_at", "FORM_BROADCAST", "FORM_STEPPING",
+    "KIND_ENERGY_F64", "KIND_FORCE_F32",
     "Plan", "Graph", "ShapeTable", "pairs_get_shapes", "pairs_set_shapes",
     "count_i32", "count_f32", "energy_f32",
     "pairs_lattice_workspace_size", "pairs_lattice_count", "pairs_lattice_count_batched",
@@ -34,9 +35,12 @@ _LIB_PATH = os.path.join(_HERE, "libpairs.so")
 _lib = None
 
 FLAG_VALIDATE = 1
+FLAG_DETERMINISTIC = 2
+PLAN_DETERMINISTIC = 0x100  # or'ed into a plan's kind (KIND_ENERGY_F32)
 LATTICE_LDS_BEADS = 4096
 LATTICE_MAX_BEADS = (1 << 24) - 1
 KIND_COUNT_I32, KIND_COUNT_F32, KIND_ENERGY_F32 = 1, 2, 3
+KIND_ENERGY_F64, KIND_FORCE_F32 = 4, 5  # pairs_debug_single_launch only
 
 _STATUS = {
     0: "ok", -1: "invalid argument", -2: "input outside the exact domain",
@@ -107,6 +111,9 @@ def _declare(L):
         "pairs_graph_destroy": [_vp],
         "pairs_debug_task_ranges": [_int, _int, _int, _vp, _i64, ctypes.POINTER(_i64)],
         "pairs_debug_step_ranges": [_int, _int, _int, _vp, _i64, ctypes.POINTER(_i64)],
+        "pairs_debug_task_at": [_i64, _int, _int, _vp, _i64, _vp],
+        "pairs_debug_single_launch": [_int, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                      ctypes.POINTER(ctypes.c_int32)],
         "pairs_get_shapes": [_int, _int, ctypes.POINTER(ShapeTable)],
         "pairs_lattice_workspace_size": [_i64, _i64, _i64, ctypes.POINTER(_sz)],
         "pairs_binned_workspace_size": [_i64, ctypes.POINTER(_sz)],
@@ -134,6 +141,11 @@ def lib():
         if not os.path.exists(_LIB_PATH):
             raise RuntimeError(f"{_LIB_PATH} is not built; run "
                                "`python -m paper_1901_11204_amd.build` first")
+        # torch first: its HIP runtime is then the one libpairs.so binds to
+        # (same soname).  Loaded the other way round, the process would hold
+        # two HIP runtimes, and the library's would find no device once
+        # torch's has opened it.
+        import torch  # noqa: F401
         L = ctypes.CDLL(_LIB_PATH)
         _declare(L)
         _lib = L
@@ -425,6 +437,27 @@ def pairs_debug_step_ranges(n: int, rows_per_lane: int, chunk: int):
     return out
 
 
+def pairs_debug_task_at(n: int, rows_per_lane: int, chunk: int, tasks):
+    """Host-only: (first row, u0, u1) of the given task indices of a set of n
+    objects, decoded as the single-set kernels decode them."""
+    import numpy as np
+    t = np.ascontiguousarray(tasks, dtype=np.int64)
+    out = np.zeros((t.shape[0], 3), dtype=np.int64)
+    _check(lib().pairs_debug_task_at(n, rows_per_lane, chunk, t.ctypes.data_as(_vp),
+                                     int(t.shape[0]), out.ctypes.data_as(_vp)),
+           "pairs_debug_task_at")
+    return out
+
+
+def pairs_debug_single_launch(kind: int, n: int):
+    """Host-only: (tasks, blocks, threads per block) of the launch a single-set
+    call of `kind` makes for n objects."""
+    t, b, w = _i64(0), _i64(0), ctypes.c_int32(0)
+    _check(lib().pairs_debug_single_launch(kind, n, ctypes.byref(t), ctypes.byref(b),
+                                           ctypes.byref(w)), "pairs_debug_single_launch")
+    return int(t.value), int(b.value), int(w.value)
+
+
 def pairs_get_shapes(kind: int, batched: bool):
     """The tile-shape table as a list of (min_n, rows_per_lane, chunk, form)."""
     t = ShapeTable()
@@ -551,11 +584,14 @@ def count_f32(x, y, z, r, validate: bool = False) -> int:
     return int(out.item())
 
 
-def energy_f32(x, y, z, eps2: float = 1e-4, per_particle: bool = True):
-    """Returns (per-particle float64 tensor or None, total as a Python float)."""
+def energy_f32(x, y, z, eps2: float = 1e-4, per_particle: bool = True,
+               deterministic: bool = False):
+    """Returns (per-particle float64 tensor or None, total as a Python float);
+    deterministic selects the run-to-run reproducible fixed-point reduction."""
     import torch
     n = int(x.shape[0])
     total = torch.empty(1, dtype=torch.float64, device=x.device)
     energy = torch.empty(n, dtype=torch.float64, device=x.device) if per_particle else None
-    pairs_energy_f32(x, y, z, eps2, energy, total)
+    pairs_energy_f32(x, y, z, eps2, energy, total,
+                     FLAG_DETERMINISTIC if deterministic else 0)
     return energy, float(total.item())

@@ -77,15 +77,33 @@ def _entry(e):
     return e if len(e) == 4 else e + (FORM_BROADCAST,)
 
 
-def tune_batched(kind, offsets, inputs, outputs, eps2=1e-4, start=None, rounds=1, log=print):
+def boundary_candidates(table, c):
+    """Lower bounds the tuner tries for class c (c >= 0 and not the last
+    class): halving and doubling steps of the current bound that keep the
+    bounds strictly decreasing."""
+    lo = table[c][0]
+    upper = table[c - 1][0] if c > 0 else None
+    lower = table[c + 1][0] if c + 1 < len(table) else -1
+    out = []
+    for f in (0.25, 0.5, 2.0, 4.0):
+        v = int(lo * f)
+        if v > lower and (upper is None or v < upper) and v != lo and v > 0:
+            out.append(v)
+    return out
+
+
+def tune_batched(kind, offsets, inputs, outputs, eps2=1e-4, start=None, rounds=1, log=print,
+                 shapes=None, boundaries=True):
     """Coordinate descent over the (K, U, form) of each size class of a batch,
-    largest class first; the class boundaries of `start` stay fixed."""
+    largest class first, then over the class boundaries (min_n of every class
+    but the last).  shapes: the (K, U, form) candidates (default: all)."""
     table = [_entry(e) for e in (start or pairs_get_shapes(kind, True))]
     best = time_batched(kind, table, offsets, inputs, outputs, eps2)
     log(f"start {table}: {best:.3f} ms")
+    shapes = list(shapes) if shapes is not None else candidates(True)
     for _ in range(rounds):
         for c in range(len(table)):
-            for k, u, form in candidates(True):
+            for k, u, form in shapes:
                 if (k, u, form) == table[c][1:]:
                     continue
                 cand = list(table)
@@ -94,29 +112,40 @@ def tune_batched(kind, offsets, inputs, outputs, eps2=1e-4, start=None, rounds=1
                 if ms < best:
                     best, table = ms, cand
                     log(f"  class {c} -> K={k} U={u} form={form}: {ms:.3f} ms")
+        if boundaries:
+            for c in range(len(table) - 1):
+                for lo in boundary_candidates(table, c):
+                    cand = list(table)
+                    cand[c] = (lo,) + tuple(table[c][1:])
+                    ms = time_batched(kind, cand, offsets, inputs, outputs, eps2)
+                    if ms < best:
+                        best, table = ms, cand
+                        log(f"  class {c} -> min_n={lo}: {ms:.3f} ms")
     pairs_set_shapes(kind, True, table)
     return table, best
 
 
-def tune_single(kind, n_values, make_call, start=None, log=print):
+def tune_single(kind, n_values, make_call, start=None, log=print, rows=ROWS, chunks=CHUNKS):
     """For each size n (largest first) pick the (K, U) with the fastest
-    single-set call; make_call(n) returns a zero-argument callable."""
-    entries = []
-    for i, n in enumerate(sorted(n_values, reverse=True)):
+    single-set call; make_call(n) returns a zero-argument callable.  Returns
+    the table and the best time of each size."""
+    entries, times = [], []
+    ns = sorted(n_values, reverse=True)
+    for i, n in enumerate(ns):
         call = make_call(n)
         best = None
-        for k in ROWS:
-            for u in CHUNKS:
-                lo = (sorted(n_values, reverse=True)[i + 1] if i + 1 < len(n_values) else 0)
+        lo = ns[i + 1] if i + 1 < len(ns) else 0
+        for k in rows:
+            for u in chunks:
                 pairs_set_shapes(kind, False, entries + [(lo, k, u)])
                 ms = _time(call)
                 if best is None or ms < best[0]:
                     best = (ms, k, u)
-        lo = sorted(n_values, reverse=True)[i + 1] if i + 1 < len(n_values) else 0
         entries.append((lo, best[1], best[2]))
+        times.append(best[0])
         log(f"n={n}: K={best[1]} U={best[2]} {best[0]:.3f} ms")
     pairs_set_shapes(kind, False, entries)
-    return entries
+    return entries, times
 
 
 def load_cache(path=None, apply=True):
@@ -161,12 +190,35 @@ def main(argv=None):
     import workloads as w
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["binned-int32", "particles-f32"],
+    ap.add_argument("--workload", choices=["binned-int32", "particles-f32", "single-int32",
+                                           "single-energy"],
                     default="binned-int32")
     ap.add_argument("--out", default=DEFAULT_CACHE)
     ap.add_argument("--rounds", type=int, default=1)
+    ap.add_argument("--sizes", default="1048576,262144,65536,16384,4096",
+                    help="single-set workloads: the set sizes tuned, one per class")
     a = ap.parse_args(argv)
     dev = torch.device("cuda", 0)
+    if a.workload.startswith("single"):
+        from . import count_i32, energy_f32
+        ns = [int(v) for v in a.sizes.split(",")]
+        if a.workload == "single-int32":
+            kind, note = KIND_COUNT_I32, "single int32 sets, centres in [0,2^24)^3, radii [1,2^14]"
+
+            def make_call(n):
+                t = [torch.from_numpy(v).to(dev) for v in w.spheres_i32(n, 2, 2 ** 24,
+                                                                          2 ** 14).arrays()]
+                return lambda: count_i32(*t)
+        else:
+            kind, note = KIND_ENERGY_F32, "single float32 particle sets in the unit cube"
+
+            def make_call(n):
+                t = [torch.from_numpy(v).to(dev) for v in w.particles_f32(n, 4).arrays()]
+                return lambda: energy_f32(*t)
+        table, times = tune_single(kind, ns, make_call, log=lambda *m: print(*m, flush=True))
+        save_cache(a.out, kind, False, table, note + f"; sizes {ns}", times)
+        print(json.dumps({"kind": KIND_NAMES[kind], "table": table, "ms": times}), flush=True)
+        return 0
     if a.workload == "binned-int32":
         b = w.config4()
         ins = tuple(torch.from_numpy(v).to(dev) for v in b.objs.arrays())

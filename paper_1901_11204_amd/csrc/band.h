@@ -100,6 +100,13 @@ PAIRS_HD void task_range(const Band &b, const Tiling &t, int block, int c, int *
     *u1 = hi < uend ? hi : uend;
 }
 
+// Task `task` of the tiling, enumerated row block by chunk:
+// block = task / nchunks, chunk = task % nchunks.
+PAIRS_HD void task_at(const Band &b, const Tiling &t, int64_t task, int *ra, int *u0, int *u1) {
+    const int block = (int)(task / t.nchunks), c = (int)(task % t.nchunks);
+    task_range(b, t, block, c, ra, u0, u1);
+}
+
 // Row-stepping decomposition (the paper's own form: row i visits partners
 // (i + s) mod n for s = 1, 2, ...).  A stepping task holds K consecutive rows
 // per lane, rows [r0, r0 + 64K), and runs the steps [s0, s0 + T) for all its

@@ -24,21 +24,30 @@
 //      offsets;
 //   5. k_bin_hash_build: a hash table of 8-slot buckets from occupied cell
 //      keys to each cell's first object and size;
-//   6. k_bin_count: 16 lanes per occupied cell (cells of more than 64
-//      objects go to a list that k_bin_count_big counts, one wave per cell).
-//      Lanes 0..12 of a group look up the 13 forward neighbours in the
-//      table; the pairs inside the cell run on the balanced circular
+//   6. k_bin_count: 16 lanes per occupied cell.  Lanes 0..12 of a group
+//      look up the 13 forward neighbours in the table; the pairs inside a
+//      cell of at most kBigCell objects run on the balanced circular
 //      assignment (each lane takes rows and their steps s = 1 ..
 //      floor((n-1)/2), rows i < n/2 also s = n/2 when n is even); the pairs
-//      with each occupied neighbour run with the lanes taking the cell's
-//      objects against all of the neighbour's.  Wave sums go to the count
-//      with one atomic per wave.
+//      with each occupied neighbour of at most kBigCell objects run with the
+//      lanes taking the cell's objects against all of the neighbour's.  Wave
+//      sums go to the count with one atomic per wave.  Every pair of ranges
+//      with more than kBigCell objects on one side -- a big cell's own pairs,
+//      and the pairs between a cell and a neighbour when either is big -- is
+//      appended instead to a list of work items;
+//   7. k_bin_item_scan and k_bin_count_items: each item is tiled into wave
+//      tasks of at most 64 K rows against kItemChunk partners (the balanced
+//      assignment's row blocks and chunks for a cell's own pairs, a
+//      rectangle of rows and partners between two cells), and all waves
+//      share the tasks, so no wave's work grows with a cell's size.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "band.h"
 #include "device.h"
+#include "tasks.h"
 
 namespace pairs_binning {
 
@@ -204,17 +213,56 @@ __device__ __forceinline__ uint64_t neighbour_key(uint64_t key, int d, int fb) {
 // 0..12 of the group, the pairs inside the cell run on the balanced circular
 // assignment, and the pairs with each occupied neighbour with the lanes
 // taking the cell's objects against all of the neighbour's.
+// A work item: the pairs between objects [a0, a0 + na) and [b0, b0 + nb) of
+// the sorted records, or the pairs within [a0, a0 + na) when b0 == a0.
+struct Item {
+    uint32_t a0, na, b0, nb;
+};
+constexpr int64_t kBigCell = 64;
+
+// Capacity of the item list for n objects: at most n / (kBigCell + 1) cells
+// are big, and each takes part in at most 27 items (its own pairs and one
+// per neighbour in either direction).  Pushes beyond it (possible only for
+// inputs outside the domain, whose keys can wrap) are dropped, never
+// written.
+__host__ __device__ inline int64_t item_capacity(int64_t n) {
+    return 27 * (n / (kBigCell + 1)) + 1;
+}
+
+struct ItemList {
+    Item *items;
+    uint32_t *n;   // pushes so far (may pass cap)
+    uint32_t cap;
+};
+
+__device__ __forceinline__ void push_item(const ItemList &L, Item it) {
+    const uint32_t k = atomicAdd(L.n, 1u);
+    if (k < L.cap) L.items[k] = it;
+}
+
+__device__ __forceinline__ int64_t item_count(const ItemList &L) {
+    const uint32_t n = *L.n;
+    return n < L.cap ? n : L.cap;
+}
+
 template <int G>
 __device__ __forceinline__ uint64_t count_cell(int64_t a0, int64_t n, uint64_t key, int gl, int g0,
                                                const int4 *__restrict__ so,
                                                const uint64_t *__restrict__ htags,
                                                const uint64_t *__restrict__ hkeys,
                                                const uint2 *__restrict__ hvals, int blog,
-                                               int fb) {
+                                               int fb, const ItemList &items) {
     static_assert(G >= 13 && kWave % G == 0, "13 neighbour lookups per group");
     uint64_t cnt = 0;
     uint2 nb = make_uint2(0, 0);
     if (gl < 13) nb = find_cell(htags, hkeys, hvals, blog, neighbour_key(key, gl, fb));
+    const bool big = n > kBigCell;
+    // ranges with a big side go to the item list: the cell's own pairs, and
+    // those with each big (or, for a big cell, every) occupied neighbour
+    if (big && gl == 0) push_item(items, Item{(uint32_t)a0, (uint32_t)n, (uint32_t)a0, (uint32_t)n});
+    if (gl < 13 && nb.y != 0 && (big || nb.y > (uint32_t)kBigCell))
+        push_item(items, Item{(uint32_t)a0, (uint32_t)n, nb.x, nb.y});
+    if (big) return 0;
     const int64_t h = (n - 1) / 2;
     for (int64_t i = gl; n >= 2 && i < n; i += G) {
         const int4 oi = so[a0 + i];
@@ -225,18 +273,15 @@ __device__ __forceinline__ uint64_t count_cell(int64_t a0, int64_t n, uint64_t k
             cnt += touch(oi, so[a0 + j]);
         }
     }
-    // only the occupied neighbours, usually none in a sparse grid
-    uint32_t occ = (uint32_t)(__ballot(nb.y != 0) >> g0) & ((1u << 13) - 1);
+    // only the occupied neighbours of at most kBigCell objects, usually none
+    // in a sparse grid
+    uint32_t occ =
+        (uint32_t)(__ballot(nb.y != 0 && nb.y <= (uint32_t)kBigCell) >> g0) & ((1u << 13) - 1);
     while (occ) {
         const int d = __builtin_ctz(occ);
         occ &= occ - 1;
-        int nbn32 = __shfl((int)nb.y, g0 + d, kWave), b032 = __shfl((int)nb.x, g0 + d, kWave);
-        if constexpr (G == kWave) {
-            // one cell per wave: the neighbour's records are wave-uniform
-            // reads, which go through the scalar unit
-            nbn32 = __builtin_amdgcn_readfirstlane(nbn32);
-            b032 = __builtin_amdgcn_readfirstlane(b032);
-        }
+        const int nbn32 = __shfl((int)nb.y, g0 + d, kWave),
+                  b032 = __shfl((int)nb.x, g0 + d, kWave);
         const int64_t nbn = (uint32_t)nbn32, b0 = (uint32_t)b032;
         for (int64_t i = gl; i < n; i += G) {
             const int4 oi = so[a0 + i];
@@ -253,23 +298,20 @@ __device__ __forceinline__ void wave_count_to(uint64_t *count, uint64_t cnt) {
         atomicAdd((unsigned long long *)count, (unsigned long long)cnt);
 }
 
-// Small cells: 16 lanes per occupied cell, four cells per wave in flight,
-// which hides the latency of a cell's dependent loads.  Cells of more than
-// kBigCell objects are appended to `big` (their number in big_n) for
-// k_bin_count_big.  m_ptr: number of occupied cells (device); ukeys: their
-// keys; off: their first object in the sorted arrays, off[m] = n; htags,
-// hkeys, hvals, blog: the table from keys to cell ranges; fb: bits per axis
-// of a key; so: the object records in key order.
+// 16 lanes per occupied cell, four cells per wave in flight, which hides the
+// latency of a cell's dependent loads.  Ranges with a big side go to `items`
+// (their number in item_n).  m_ptr: number of occupied cells (device); ukeys:
+// their keys; off: their first object in the sorted arrays, off[m] = n;
+// htags, hkeys, hvals, blog: the table from keys to cell ranges; fb: bits per
+// axis of a key; so: the object records in key order.
 constexpr int kGroup = 16;
-constexpr int64_t kBigCell = 64;
 
 // Eight waves per SIMD: the loop waits on loads, so occupancy pays.
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_bin_count(
     const int4 *__restrict__ so, const uint64_t *__restrict__ ukeys,
     const uint32_t *__restrict__ off, const uint32_t *__restrict__ m_ptr,
     const uint64_t *__restrict__ htags, const uint64_t *__restrict__ hkeys,
-    const uint2 *__restrict__ hvals, int blog, int fb, uint32_t *big, uint32_t *big_n,
-    uint64_t *count) {
+    const uint2 *__restrict__ hvals, int blog, int fb, ItemList items, uint64_t *count) {
     const int lane = threadIdx.x & (kWave - 1);
     const int gl = lane % kGroup, g0 = lane - gl;
     const int64_t m = *m_ptr;
@@ -287,43 +329,155 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         uint64_t pk = 0;
         if (cn < m) p0 = off[cn], p1 = off[cn + 1], pk = ukeys[cn];
         const int64_t n = (int64_t)o1 - o0;
-        if (n > kBigCell) {
-            if (gl == 0) big[atomicAdd(big_n, 1u)] = (uint32_t)c;
-        } else {
-            cnt += count_cell<kGroup>(o0, n, key, gl, g0, so, htags, hkeys, hvals, blog, fb);
-        }
+        cnt += count_cell<kGroup>(o0, n, key, gl, g0, so, htags, hkeys, hvals, blog, fb, items);
         o0 = p0, o1 = p1, key = pk;
     }
     wave_count_to(count, cnt);
 }
 
-// Big cells: one wave per cell of the list.
-__global__ __launch_bounds__(kBlock) void k_bin_count_big(const int4 *__restrict__ so,
-                                                          const uint64_t *__restrict__ ukeys,
-                                                          const uint32_t *__restrict__ off,
-                                                          const uint64_t *__restrict__ htags,
-                                                          const uint64_t *__restrict__ hkeys,
-                                                          const uint2 *__restrict__ hvals,
-                                                          int blog, int fb, const uint32_t *big,
-                                                          const uint32_t *big_n,
-                                                          uint64_t *count) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t nbig = *big_n;
-    const int64_t waves = (int64_t)gridDim.x * (kBlock / kWave);
-    uint64_t cnt = 0;
-    for (int64_t q = (int64_t)blockIdx.x * (kBlock / kWave) + pairs_dev::wave_id(); q < nbig;
-         q += waves) {
-        const uint32_t c = big[q];
-        cnt += count_cell<kWave>(off[c], (int64_t)off[c + 1] - off[c], ukeys[c], lane, 0, so,
-                                 htags, hkeys, hvals, blog, fb);
+// ------------------------------------------------------------- work items --
+//
+// Tasks of an item: a cell's own pairs are the balanced assignment of its na
+// objects (band.h) tiled into row blocks of 64 kItemRows rows and chunks of
+// kItemChunk virtual partners; the pairs between two ranges are a rectangle
+// of row blocks of A against chunks of kItemChunk objects of B.
+constexpr int kItemRows = 4;
+constexpr int kItemChunk = 512;
+
+__device__ __forceinline__ int64_t item_tasks(const Item &it) {
+    if (it.a0 == it.b0) return Tiling::of(Band::of((int)it.na), kItemRows, kItemChunk).tasks();
+    return (int64_t)((it.na + 64 * kItemRows - 1) / (64 * kItemRows)) *
+           ((it.nb + kItemChunk - 1) / kItemChunk);
+}
+
+// One block: exclusive prefix of the items' task counts, pre[k] for
+// k = 0 .. items (pre[items] = all tasks).
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_bin_item_scan(ItemList L,
+                                                               int64_t *__restrict__ pre) {
+    __shared__ int64_t part[kScanThreads];
+    const int tid = threadIdx.x;
+    const Item *items = L.items;
+    const int64_t m = item_count(L);
+    const int64_t chunk = (m + kScanThreads - 1) / kScanThreads;
+    const int64_t k0 = min((int64_t)tid * chunk, m), k1 = min(k0 + chunk, m);
+    int64_t sum = 0;
+    for (int64_t k = k0; k < k1; ++k) sum += item_tasks(items[k]);
+    part[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t run = 0;
+        for (int k = 0; k < kScanThreads; ++k) {
+            const int64_t v = part[k];
+            part[k] = run;
+            run += v;
+        }
+        pre[m] = run;
     }
-    wave_count_to(count, cnt);
+    __syncthreads();
+    int64_t run = part[tid];
+    for (int64_t k = k0; k < k1; ++k) {
+        pre[k] = run;
+        run += item_tasks(items[k]);
+    }
+}
+
+// The tasks of all items, taken by the waves with a grid stride.  Rows are
+// held as in the pairs_count_i32 kernels (RowI32, kItemRows per lane); each
+// group of 64 partners is staged in LDS and read back as broadcasts.  The
+// binned domain (coordinates within 2^24) lies inside the box of the plain
+// 64-bit Gram test.  Padding rows (nq = -2^62) and padding partners
+// (q = INT64_MAX) never hit.
+__global__ __launch_bounds__(kBlock) void k_bin_count_items(const int4 *__restrict__ so,
+                                                            ItemList L,
+                                                            const int64_t *__restrict__ pre,
+                                                            uint64_t *count) {
+    using namespace pairs_dev;
+    constexpr int K = kItemRows;
+    __shared__ PartnerI32 wp_all[kBlock / kWave][kWave];
+    __shared__ int64_t wq_all[kBlock / kWave][kWave];
+    const int wave = wave_id(), lane = lane_id();
+    PartnerI32 *wp = wp_all[wave];
+    int64_t *wq = wq_all[wave];
+    const Item *items = L.items;
+    const int64_t m = item_count(L), total = pre[m];
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t t = (int64_t)blockIdx.x * (kBlock / kWave) + wave; t < total; t += stride) {
+        int64_t lo = 0, hi = m;  // pre[lo] <= t < pre[hi]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (pre[mid] <= t) lo = mid; else hi = mid;
+        }
+        const Item it = items[lo];
+        const int64_t local = t - pre[lo];
+        const bool self = it.a0 == it.b0;
+        const Band band = Band::of((int)it.na);
+        int ra, u0, u1;
+        if (self) {
+            task_at(band, Tiling::of(band, K, kItemChunk), local, &ra, &u0, &u1);
+        } else {
+            const int64_t nch = (it.nb + kItemChunk - 1) / kItemChunk;
+            ra = (int)(local / nch) * 64 * K;
+            u0 = (int)(local % nch) * kItemChunk;
+            u1 = min(u0 + kItemChunk, (int)it.nb);
+        }
+        RowI32 rows[K];
+        int row[K], nsteps[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = ra + kWave * k + lane;
+            row[k] = i;
+            nsteps[k] = 0;
+            rows[k].ax = rows[k].ay = rows[k].az = rows[k].ar = 0;
+            rows[k].nq = -((int64_t)1 << 62);
+            if (i < (int)it.na) {
+                const int4 o = so[it.a0 + i];
+                rows[k] = gram_row(o.x, o.y, o.z, o.w);
+                nsteps[k] = self ? band.steps(i) : 0;
+            }
+        }
+        uint32_t cnt = 0;
+        for (int g0 = u0; g0 < u1; g0 += kWave) {
+            const int u = g0 + lane;
+            if (u < u1) {
+                const uint32_t j = self ? it.a0 + (uint32_t)(u >= (int)it.na ? u - (int)it.na : u)
+                                        : it.b0 + (uint32_t)u;
+                const int4 o = so[j];
+                wp[lane] = PartnerI32{o.x, o.y, o.z, o.w};
+                wq[lane] = gram_q(o.x, o.y, o.z, o.w);
+            } else {
+                wp[lane] = PartnerI32{0, 0, 0, 0};
+                wq[lane] = INT64_MAX;
+            }
+            wave_sync();
+            const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
+            if (self) {
+                for (int q = 0; q < gn; ++q) {
+                    const PartnerI32 b = wp[q];
+                    const int64_t qb = wq[q];
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        cnt += count_bits_both(gram_hit(rows[k], b, qb),
+                                               owns(g0 + q, row[k], nsteps[k]));
+                }
+            } else {
+                for (int q = 0; q < gn; ++q) {
+                    const PartnerI32 b = wp[q];
+                    const int64_t qb = wq[q];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) cnt += count_bits(gram_hit(rows[k], b, qb));
+                }
+            }
+            wave_sync();
+        }
+        if (lane == 0 && cnt) atomicAdd((unsigned long long *)count, (unsigned long long)cnt);
+    }
 }
 
 // Ranges of 32-bit words that the pipeline needs zeroed, cleared by one
 // launch (blockIdx.y picks the range): the count, the cell sizes (the scan
 // runs over n + 1 sizes, zero past the m occupied cells, so that off[m] = n),
-// the table's tags and claim counts, and the number of big cells.
+// the table's tags and claim counts, and the number of work items.
 constexpr int kClearRanges = 5;
 struct ClearRanges {
     uint32_t *p[kClearRanges];

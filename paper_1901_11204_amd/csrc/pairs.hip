@@ -140,7 +140,8 @@ bool valid_table(const ClassTable &t, bool batched) {
             if (t.U[c] < 16 || t.U[c] % 16 != 0 || t.U[c] > step_max_chunk(t.K[c])) return false;
         } else if (t.form[c] == PAIRS_FORM_BROADCAST) {
             if (t.K[c] != 1 && t.K[c] != 2 && t.K[c] != 4 && t.K[c] != 8) return false;
-            if (t.U[c] < 64 || t.U[c] % 64 != 0 || t.U[c] > (1 << 24)) return false;
+            // a task's count (at most 64 K U pairs) stays below 2^32
+            if (t.U[c] < 64 || t.U[c] % 64 != 0 || t.U[c] > (1 << 22)) return false;
         } else {
             return false;
         }
@@ -172,13 +173,20 @@ __global__ void k_fill_f64(double *p, int64_t n, double v) {
     if (i < n) p[i] = v;
 }
 
+// Finishing passes of the fixed-point sums: the integer held in each 8-byte
+// word back to a double (one rounding; the scale is a power of two).
+__global__ void k_fixed_finish(double *p, int64_t n, double inv_scale) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (double)__double_as_longlong(p[i]) * inv_scale;
+}
+
 __global__ void k_validate_i32(const int32_t *x, const int32_t *y, const int32_t *z,
                                const int32_t *r, int64_t n, int *bad) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int32_t L = PAIRS_I32_COORD_LIMIT, RL = PAIRS_I32_RADIUS_LIMIT;
-    bool ok = x[i] >= -L && x[i] <= L && y[i] >= -L && y[i] <= L && z[i] >= -L && z[i] <= L &&
-              r[i] >= 0 && r[i] <= RL;
+    const int32_t lo = PAIRS_I32_COORD_MIN, hi = PAIRS_I32_COORD_MAX;
+    bool ok = x[i] >= lo && x[i] <= hi && y[i] >= lo && y[i] <= hi && z[i] >= lo && z[i] <= hi &&
+              r[i] >= 0 && r[i] <= PAIRS_I32_RADIUS_MAX;
     if (!ok) atomicOr(bad, 1);
 }
 
@@ -210,6 +218,28 @@ __global__ void k_validate_offsets(const int64_t *off, int64_t n_sets, int64_t n
 }
 
 // ------------------------------------------------------- single-set kernels --
+//
+// A single-set launch enumerates the tiling's tasks row block by chunk.  Up to
+// kMaxSingleBlocks blocks each wave runs one task; a larger tiling keeps that
+// grid and its waves take tasks with a grid stride over the 64-bit task
+// index, so every set size up to PAIRS_MAX_SET_SIZE launches within the
+// dispatch limit of 2^32 work-items.
+
+constexpr int64_t kMaxSingleBlocks = (int64_t)1 << 22;
+
+// Runs f(ra, u0, u1) for every non-empty task of the tiling owned by the
+// calling wave.
+template <typename F>
+__device__ __forceinline__ void for_each_task(const Band &band, const Tiling &til, F &&f) {
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t ntasks = til.tasks();
+    for (int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); task < ntasks;
+         task += stride) {
+        int ra, u0, u1;
+        task_at(band, til, task, &ra, &u0, &u1);
+        if (u0 < u1) f(ra, u0, u1);
+    }
+}
 
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_count_i32(const int32_t *__restrict__ x,
@@ -221,17 +251,13 @@ __global__ __launch_bounds__(kBlock) void k_count_i32(const int32_t *__restrict_
     const int wave = wave_id();
     const Band band = Band::of(n);
     const Tiling til = Tiling::of(band, K, U);
-    const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    if (task >= til.tasks()) return;
-    const int blk = (int)(task / til.nchunks), c = (int)(task % til.nchunks);
-    int ra, u0, u1;
-    task_range(band, til, blk, c, &ra, &u0, &u1);
-    if (u0 >= u1) return;
-    TaskInputs<int32_t, K> in;
-    load_task_inputs<int32_t, K, K, true>(x, y, z, r, 0, band, ra, u0, u1, in);
-    uint32_t cnt = count_i32_task<K, K>(x, y, z, r, 0, band, ra, u0, u1, lds + wave * kCountI32Lds,
-                                        in);
-    if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)out, (unsigned long long)cnt);
+    for_each_task(band, til, [&](int ra, int u0, int u1) {
+        TaskInputs<int32_t, K> in;
+        load_task_inputs<int32_t, K, K, true>(x, y, z, r, 0, band, ra, u0, u1, in);
+        uint32_t cnt = count_i32_task<K, K>(x, y, z, r, 0, band, ra, u0, u1,
+                                            lds + wave * kCountI32Lds, in);
+        if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)out, (unsigned long long)cnt);
+    });
 }
 
 template <int K>
@@ -244,39 +270,31 @@ __global__ __launch_bounds__(kBlock) void k_count_f32(const float *__restrict__ 
     const int wave = wave_id();
     const Band band = Band::of(n);
     const Tiling til = Tiling::of(band, K, U);
-    const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    if (task >= til.tasks()) return;
-    const int blk = (int)(task / til.nchunks), c = (int)(task % til.nchunks);
-    int ra, u0, u1;
-    task_range(band, til, blk, c, &ra, &u0, &u1);
-    if (u0 >= u1) return;
-    TaskInputs<float, K> in;
-    load_task_inputs<float, K, K, true>(x, y, z, r, 0, band, ra, u0, u1, in);
-    uint32_t cnt = count_f32_task<K, K>(x, y, z, r, 0, band, ra, u0, u1, lds + wave * kCountF32Lds,
-                                        in);
-    if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)out, (unsigned long long)cnt);
+    for_each_task(band, til, [&](int ra, int u0, int u1) {
+        TaskInputs<float, K> in;
+        load_task_inputs<float, K, K, true>(x, y, z, r, 0, band, ra, u0, u1, in);
+        uint32_t cnt = count_f32_task<K, K>(x, y, z, r, 0, band, ra, u0, u1,
+                                            lds + wave * kCountF32Lds, in);
+        if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)out, (unsigned long long)cnt);
+    });
 }
 
 template <int K, bool PerObject>
 __global__ __launch_bounds__(kBlock) void k_energy(const float *__restrict__ x,
                                                    const float *__restrict__ y,
                                                    const float *__restrict__ z, int n, int U,
-                                                   float eps2, double *E, double *total) {
+                                                   float eps2, SumSink E, SumSink total) {
     __shared__ float lds[kWavesPerBlock * kEnergyLds];
     const int wave = wave_id();
     const Band band = Band::of(n);
     const Tiling til = Tiling::of(band, K, U);
-    const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    if (task >= til.tasks()) return;
-    const int blk = (int)(task / til.nchunks), c = (int)(task % til.nchunks);
-    int ra, u0, u1;
-    task_range(band, til, blk, c, &ra, &u0, &u1);
-    if (u0 >= u1) return;
-    TaskInputs<float, K> in;
-    load_task_inputs<float, K, K, false>(x, y, z, nullptr, 0, band, ra, u0, u1, in);
-    EnergyResult res = energy_task<K, K, PerObject, false>(x, y, z, nullptr, 0, band, ra, u0, u1,
-                                                           eps2, lds + wave * kEnergyLds, E, in);
-    if (lane_id() == 0) atomicAdd(total, res.energy);
+    for_each_task(band, til, [&](int ra, int u0, int u1) {
+        TaskInputs<float, K> in;
+        load_task_inputs<float, K, K, false>(x, y, z, nullptr, 0, band, ra, u0, u1, in);
+        EnergyResult res = energy_task<K, K, PerObject, false>(
+            x, y, z, nullptr, 0, band, ra, u0, u1, eps2, lds + wave * kEnergyLds, E, in);
+        if (lane_id() == 0) total.add(0, res.energy);
+    });
 }
 
 // The softened potential in double precision (energy64_task).
@@ -284,22 +302,18 @@ template <int K, bool PerObject>
 __global__ __launch_bounds__(kBlock) void k_energy64(const double *__restrict__ x,
                                                      const double *__restrict__ y,
                                                      const double *__restrict__ z, int n, int U,
-                                                     double eps2, double *E, double *total) {
+                                                     double eps2, SumSink E, SumSink total) {
     __shared__ double lds[kWavesPerBlock * kEnergy64Lds];
     const int wave = wave_id();
     const Band band = Band::of(n);
     const Tiling til = Tiling::of(band, K, U);
-    const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    if (task >= til.tasks()) return;
-    const int blk = (int)(task / til.nchunks), c = (int)(task % til.nchunks);
-    int ra, u0, u1;
-    task_range(band, til, blk, c, &ra, &u0, &u1);
-    if (u0 >= u1) return;
-    TaskInputs<double, K> in;
-    load_task_inputs<double, K, K, false>(x, y, z, nullptr, 0, band, ra, u0, u1, in);
-    const double e = energy64_task<K, PerObject>(x, y, z, 0, band, ra, u0, u1, eps2,
-                                                 lds + wave * kEnergy64Lds, E, in);
-    if (lane_id() == 0) atomicAdd(total, e);
+    for_each_task(band, til, [&](int ra, int u0, int u1) {
+        TaskInputs<double, K> in;
+        load_task_inputs<double, K, K, false>(x, y, z, nullptr, 0, band, ra, u0, u1, in);
+        const double e = energy64_task<K, PerObject>(x, y, z, 0, band, ra, u0, u1, eps2,
+                                                     lds + wave * kEnergy64Lds, E, in);
+        if (lane_id() == 0) total.add(0, e);
+    });
 }
 
 // Forces of the softened potential on every object (force_task).
@@ -307,20 +321,17 @@ template <int K>
 __global__ __launch_bounds__(kBlock) void k_force(const float *__restrict__ x,
                                                   const float *__restrict__ y,
                                                   const float *__restrict__ z, int n, int U,
-                                                  float eps2, double *Fx, double *Fy, double *Fz) {
+                                                  float eps2, SumSink Fx, SumSink Fy, SumSink Fz) {
     __shared__ float lds[kWavesPerBlock * kForceLds];
     const int wave = wave_id();
     const Band band = Band::of(n);
     const Tiling til = Tiling::of(band, K, U);
-    const int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    if (task >= til.tasks()) return;
-    const int blk = (int)(task / til.nchunks), c = (int)(task % til.nchunks);
-    int ra, u0, u1;
-    task_range(band, til, blk, c, &ra, &u0, &u1);
-    if (u0 >= u1) return;
-    TaskInputs<float, K> in;
-    load_task_inputs<float, K, K, false>(x, y, z, nullptr, 0, band, ra, u0, u1, in);
-    force_task<K>(x, y, z, 0, band, ra, u0, u1, eps2, lds + wave * kForceLds, Fx, Fy, Fz, in);
+    for_each_task(band, til, [&](int ra, int u0, int u1) {
+        TaskInputs<float, K> in;
+        load_task_inputs<float, K, K, false>(x, y, z, nullptr, 0, band, ra, u0, u1, in);
+        force_task<K>(x, y, z, 0, band, ra, u0, u1, eps2, lds + wave * kForceLds, Fx, Fy, Fz,
+                      in);
+    });
 }
 
 // ---------------------------------------------------------- batched kernels --
@@ -346,82 +357,233 @@ struct TaskDesc {
 };
 static_assert(sizeof(TaskDesc) == 32, "one 32-byte scalar load per task");
 
-// Task source of an unplanned call: per-class exclusive prefix sums of the
-// per-set task counts (coff[c][s], s = 0..n_sets) and the class bases.
-struct ScanSource {
-    const int64_t *bases;  // [kMaxClasses + 1]
-    const int64_t *coff;   // [kMaxClasses][n_sets + 1]
-    int64_t n_sets;
-    int classes;
-    __device__ int64_t total() const { return bases[classes]; }
-    __device__ void decode(int64_t t, int64_t *set, int *local) const {
-        int c = 0;
-        while (c + 1 < classes && t >= bases[c + 1]) ++c;
-        const int64_t tl = t - bases[c];
-        const int64_t *o = coff + (int64_t)c * (n_sets + 1);
-        // last s with o[s] <= tl; sets of other classes have empty ranges
-        int64_t lo = 0, hi = n_sets;  // o[lo] <= tl < o[hi]
-        while (hi - lo > 1) {
-            int64_t mid = (lo + hi) >> 1;
-            if (o[mid] <= tl) lo = mid; else hi = mid;
-        }
-        *set = lo;
-        *local = (int)(tl - o[lo]);
-    }
+// ------------------------------------------------------ unplanned schedule --
+//
+// An unplanned call schedules on the device.  It lists the sets that have
+// pairs class by class (the largest sets first, set order within a class),
+// with pre[j] the global index of the first task of listed set j, so the
+// tasks of all sets form one range [0, T).  A bucket table maps every B-th
+// task to its listed set (B = ceil(T / listed), so the table has at most
+// `listed` + 1 entries and each bucket spans at most B + 1 listed sets): a
+// wave finds the set of task t by one table lookup and a binary search over
+// at most B + 1 entries of pre.
+//
+// The list is built by four kernels over blocks of kSchedBlock sets: class
+// and task counts per block, a scan of the block counts (one block), the
+// list and pre with block-local scans, and the bucket table.
+
+constexpr int kSchedBlock = 1024;
+
+// Workspace layout of an unplanned call of n_sets sets.
+struct SchedLayout {
+    size_t hdr, list, pre, tab, blk, total;
+    int64_t nb;  // blocks of kSchedBlock sets
 };
 
-// The single-block scheduler of unplanned calls.
-constexpr int kSchedThreads = 1024;
+constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-__global__ __launch_bounds__(kSchedThreads) void k_batch_schedule(
-    const int64_t *__restrict__ off, int64_t n_sets, int64_t n_total, ClassTable ct,
-    int64_t *__restrict__ coff, int64_t *__restrict__ bases) {
-    __shared__ int64_t part[kMaxClasses][kSchedThreads];
-    __shared__ int64_t class_total[kMaxClasses];
-    const int tid = threadIdx.x;
-    const int64_t chunk = (n_sets + kSchedThreads - 1) / kSchedThreads;
-    const int64_t s0 = min((int64_t)tid * chunk, n_sets), s1 = min(s0 + chunk, n_sets);
-    int64_t sum[kMaxClasses] = {0, 0, 0, 0};
-    for (int64_t s = s0; s < s1; ++s) {
-        int64_t b;
-        int n;
-        set_range(off, s, n_total, &b, &n);
-        int c = ct.class_of(n);
-        sum[c] += ct.tasks(n, c);
-    }
-    for (int c = 0; c < kMaxClasses; ++c) part[c][tid] = sum[c];
+constexpr SchedLayout sched_layout(int64_t n_sets) {
+    SchedLayout L{};
+    const int64_t nb = (n_sets + kSchedBlock - 1) / kSchedBlock;
+    size_t p = 0;
+    L.hdr = p;
+    p += 256;
+    L.list = p;
+    p += align256(4 * (size_t)n_sets);
+    L.pre = p;
+    p += align256(8 * (size_t)(n_sets + 1));
+    L.tab = p;
+    p += align256(4 * (size_t)(n_sets + 2));
+    L.blk = p;
+    p += align256(8 * 2 * kMaxClasses * (size_t)nb);
+    L.nb = nb;
+    L.total = p;
+    return L;
+}
+
+// The header: class bases in the list and in the task range, and the totals.
+struct SchedHeader {
+    int64_t cbase[kMaxClasses + 1];  // first list index of each class
+    int64_t tbase[kMaxClasses + 1];  // first task of each class
+    int64_t T;                       // tasks in all
+    int64_t listed;                  // sets with at least one task
+    int64_t B;                       // tasks per bucket
+    int64_t nbuckets;                // ceil(T / B)
+};
+static_assert(sizeof(SchedHeader) <= 256, "the header fits its slot");
+
+// Class (or -1: no pairs) and task count of set s.
+__device__ __forceinline__ int set_work(const int64_t *off, int64_t s, int64_t n_sets,
+                                        int64_t n_total, const ClassTable &ct, int64_t *tasks) {
+    *tasks = 0;
+    if (s >= n_sets) return -1;
+    int64_t b;
+    int n;
+    set_range(off, s, n_total, &b, &n);
+    if (n < 2) return -1;
+    const int c = ct.class_of(n);
+    *tasks = ct.tasks(n, c);
+    return *tasks > 0 ? c : -1;
+}
+
+// Per block: sets and tasks of each class (blk[b][c] and blk[b][kMaxClasses + c]).
+__global__ __launch_bounds__(kSchedBlock) void k_sched_count(const int64_t *__restrict__ off,
+                                                             int64_t n_sets, int64_t n_total,
+                                                             ClassTable ct, int64_t *blk) {
+    __shared__ unsigned long long acc[2 * kMaxClasses];
+    if (threadIdx.x < 2 * kMaxClasses) acc[threadIdx.x] = 0;
     __syncthreads();
-    if (tid < ct.count) {  // exclusive scan of class tid over the threads
-        int64_t run = 0;
-        for (int k = 0; k < kSchedThreads; ++k) {
-            int64_t v = part[tid][k];
-            part[tid][k] = run;
+    int64_t t;
+    const int c = set_work(off, (int64_t)blockIdx.x * kSchedBlock + threadIdx.x, n_sets, n_total,
+                           ct, &t);
+    if (c >= 0) {
+        atomicAdd(&acc[c], 1ull);
+        atomicAdd(&acc[kMaxClasses + c], (unsigned long long)t);
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kMaxClasses)
+        blk[(int64_t)blockIdx.x * 2 * kMaxClasses + threadIdx.x] = (int64_t)acc[threadIdx.x];
+}
+
+// One block: exclusive scans of the block counts per class (in place), the
+// class bases and the totals.
+__global__ __launch_bounds__(kSchedBlock) void k_sched_scan(int64_t *blk, int64_t nb,
+                                                            SchedHeader *hdr) {
+    __shared__ int64_t part[kSchedBlock];
+    __shared__ int64_t total[2 * kMaxClasses];
+    const int tid = threadIdx.x;
+    const int64_t chunk = (nb + kSchedBlock - 1) / kSchedBlock;
+    const int64_t b0 = min((int64_t)tid * chunk, nb), b1 = min(b0 + chunk, nb);
+    for (int q = 0; q < 2 * kMaxClasses; ++q) {
+        int64_t sum = 0;
+        for (int64_t b = b0; b < b1; ++b) sum += blk[b * 2 * kMaxClasses + q];
+        part[tid] = sum;
+        __syncthreads();
+        if (tid == 0) {  // exclusive scan of the thread sums
+            int64_t run = 0;
+            for (int k = 0; k < kSchedBlock; ++k) {
+                const int64_t v = part[k];
+                part[k] = run;
+                run += v;
+            }
+            total[q] = run;
+        }
+        __syncthreads();
+        int64_t run = part[tid];
+        for (int64_t b = b0; b < b1; ++b) {
+            const int64_t v = blk[b * 2 * kMaxClasses + q];
+            blk[b * 2 * kMaxClasses + q] = run;
             run += v;
         }
-        class_total[tid] = run;
-        coff[(int64_t)tid * (n_sets + 1) + n_sets] = run;
+        __syncthreads();
     }
-    __syncthreads();
     if (tid == 0) {
-        int64_t acc = 0;
-        for (int c = 0; c < ct.count; ++c) {
-            bases[c] = acc;
-            acc += class_total[c];
+        int64_t ls = 0, ts = 0;
+        for (int c = 0; c < kMaxClasses; ++c) {
+            hdr->cbase[c] = ls;
+            hdr->tbase[c] = ts;
+            ls += total[c];
+            ts += total[kMaxClasses + c];
         }
-        bases[ct.count] = acc;
-    }
-    int64_t run[kMaxClasses];
-    for (int c = 0; c < kMaxClasses; ++c) run[c] = part[c][tid];
-    for (int64_t s = s0; s < s1; ++s) {
-        int64_t b;
-        int n;
-        set_range(off, s, n_total, &b, &n);
-        int cs = ct.class_of(n);
-        for (int c = 0; c < ct.count; ++c)
-            coff[(int64_t)c * (n_sets + 1) + s] = run[c];
-        run[cs] += ct.tasks(n, cs);
+        hdr->cbase[kMaxClasses] = ls;
+        hdr->tbase[kMaxClasses] = ts;
+        hdr->T = ts;
+        hdr->listed = ls;
+        const int64_t B = ls > 0 ? max((int64_t)1, (ts + ls - 1) / ls) : 1;
+        hdr->B = B;
+        hdr->nbuckets = (ts + B - 1) / B;
     }
 }
+
+// Exclusive scan of v over the block (kSchedBlock threads); *sum gets the total.
+__device__ __forceinline__ int64_t block_scan(int64_t v, int64_t *wave_tot, int64_t *sum) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    int64_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) wave_tot[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int w = 0; w < kSchedBlock / kWave; ++w) {
+            const int64_t t = wave_tot[w];
+            wave_tot[w] = run;
+            run += t;
+        }
+        wave_tot[kSchedBlock / kWave] = run;
+    }
+    __syncthreads();
+    const int64_t r = wave_tot[wave] + x - v;
+    *sum = wave_tot[kSchedBlock / kWave];
+    __syncthreads();  // wave_tot is reused by the next scan
+    return r;
+}
+
+// The list and the task prefixes.
+__global__ __launch_bounds__(kSchedBlock) void k_sched_list(
+    const int64_t *__restrict__ off, int64_t n_sets, int64_t n_total, ClassTable ct,
+    const int64_t *__restrict__ blk, const SchedHeader *__restrict__ hdr,
+    int32_t *__restrict__ list, int64_t *__restrict__ pre) {
+    __shared__ int64_t wave_tot[kSchedBlock / kWave + 1];
+    const int64_t s = (int64_t)blockIdx.x * kSchedBlock + threadIdx.x;
+    int64_t t;
+    const int c = set_work(off, s, n_sets, n_total, ct, &t);
+    const int64_t *bb = blk + (int64_t)blockIdx.x * 2 * kMaxClasses;
+    for (int q = 0; q < kMaxClasses; ++q) {
+        int64_t sum;
+        const int64_t rank = block_scan(c == q ? 1 : 0, wave_tot, &sum);
+        const int64_t tpre = block_scan(c == q ? t : 0, wave_tot, &sum);
+        if (c == q) {
+            const int64_t j = hdr->cbase[q] + bb[q] + rank;
+            list[j] = (int32_t)s;
+            pre[j] = hdr->tbase[q] + bb[kMaxClasses + q] + tpre;
+        }
+    }
+    if (s == 0) pre[hdr->listed] = hdr->T;
+}
+
+// The bucket table: tab[k] = the listed set holding task k B; a sentinel
+// tab[nbuckets] = listed - 1.
+__global__ void k_sched_tab(const int64_t *__restrict__ pre, const SchedHeader *__restrict__ hdr,
+                            int32_t *__restrict__ tab) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nbk = hdr->nbuckets, listed = hdr->listed;
+    if (k > nbk) return;
+    if (k == nbk) {
+        tab[k] = (int32_t)max((int64_t)0, listed - 1);
+        return;
+    }
+    const int64_t t = k * hdr->B;
+    int64_t lo = 0, hi = listed;  // pre[lo] <= t < pre[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= t) lo = mid; else hi = mid;
+    }
+    tab[k] = (int32_t)lo;
+}
+
+// Task source of an unplanned call, read by the scan kernels.
+struct ScanSource {
+    const SchedHeader *hdr;
+    const int32_t *list;
+    const int64_t *pre;
+    const int32_t *tab;
+
+    // Set (listed index j) and local task of global task t.
+    __device__ __forceinline__ void decode(int64_t t, int64_t B, int64_t *set, int *local) const {
+        const int64_t b = t / B;
+        int64_t lo = tab[b], hi = (int64_t)tab[b + 1] + 1;  // pre[lo] <= t < pre[hi]
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (pre[mid] <= t) lo = mid; else hi = mid;
+        }
+        *set = list[lo];
+        *local = (int)(t - pre[lo]);
+    }
+};
 
 enum Kind { kCountI32 = 1, kCountF32 = 2, kEnergyF32 = 3 };
 
@@ -447,7 +609,27 @@ struct BatchIO {
     float eps2;
     const int64_t *pack_base;  // plans: first object of each packed set
     const int32_t *pack_set;   // plans: id of each packed set
+    double emax;               // > 0: fixed-point set energies (bound on one term)
 };
+
+// The sets' fixed-point energies back to doubles, each with its set's scale.
+__global__ void k_finish_sets(double *E, const int64_t *off, int64_t n_sets, int64_t n_total,
+                              double emax) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_sets) return;
+    int64_t b;
+    int n;
+    set_range(off, s, n_total, &b, &n);
+    E[s] = (double)__double_as_longlong(E[s]) / fixed_scale(0.5 * n * (n - 1.0) * emax);
+}
+
+// Adds e to the energy of set `set` of n objects: a double atomic, or with
+// io.emax > 0 a fixed-point one whose scale follows from the bound
+// n (n - 1) / 2 * emax on the set's sum (k_finish_sets uses the same).
+__device__ __forceinline__ void add_set_energy(const BatchIO &io, int64_t set, int n, double e) {
+    const double scale = io.emax > 0.0 ? fixed_scale(0.5 * n * (n - 1.0) * io.emax) : 0.0;
+    SumSink{io.energy, scale}.add(set, e);
+}
 
 // Object type of a kind.
 template <int KindV>
@@ -492,14 +674,14 @@ __device__ __forceinline__ void batched_task(const BatchIO &io, int64_t base, co
             res = energy_task<K, KM, false, true>((const float *)io.x, (const float *)io.y,
                                                   (const float *)io.z, (const float *)io.r, base,
                                                   band, ra, u0, u1, io.eps2, (float *)win,
-                                                  nullptr, in);
+                                                  SumSink{nullptr, 0.0}, in);
         else
             res = energy_task<K, KM, false, false>((const float *)io.x, (const float *)io.y,
                                                    (const float *)io.z, nullptr, base, band, ra,
-                                                   u0, u1, io.eps2, (float *)win, nullptr,
-                                                   in);
+                                                   u0, u1, io.eps2, (float *)win,
+                                                   SumSink{nullptr, 0.0}, in);
         if (lane_id() == 0) {
-            atomicAdd(&io.energy[set], res.energy);
+            add_set_energy(io, set, band.n, res.energy);
             if (io.r && res.count)
                 atomicAdd((unsigned long long *)&io.counts[set], (unsigned long long)res.count);
         }
@@ -602,7 +784,7 @@ __device__ __forceinline__ void step_run(const BatchIO &io, const StepGeom &g, c
                                    ? segment_sum(r.lane, g, win)
                                    : 0u;
             if (lane < g.m) {
-                atomicAdd(&io.energy[ss.out_set], e);
+                add_set_energy(io, ss.out_set, g.n, e);
                 if (c)
                     atomicAdd((unsigned long long *)&io.counts[ss.out_set],
                               (unsigned long long)c);
@@ -610,7 +792,7 @@ __device__ __forceinline__ void step_run(const BatchIO &io, const StepGeom &g, c
         } else {
             const double e = wave_sum(r.lane_energy);
             if (lane == 0) {
-                atomicAdd(&io.energy[ss.out_set], e);
+                add_set_energy(io, ss.out_set, g.n, e);
                 if (io.r && r.wave)
                     atomicAdd((unsigned long long *)&io.counts[ss.out_set],
                               (unsigned long long)r.wave);
@@ -710,11 +892,11 @@ __global__ __launch_bounds__(kBlock, (batched_min_waves<KindV, KMAX>())) void k_
     const int wave = wave_id();
     void *win = lds + wave * kLdsBytes;
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
-    const int64_t ntasks = src.total();
+    const int64_t ntasks = src.hdr->T, B = src.hdr->B;
     for (int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave; t < ntasks; t += stride) {
         int64_t set;
         int local;
-        src.decode(t, &set, &local);
+        src.decode(t, B, &set, &local);
         int64_t base;
         int n;
         set_range(io.off, set, io.n_total, &base, &n);
@@ -820,7 +1002,13 @@ pairs_status_t hip_fail(hipError_t e) {
         if (s_ != PAIRS_OK) return s_; \
     } while (0)
 
-// Per-device state: a device word for validation results and the CU count.
+// Status words of the validation passes and the lattice kernels, in the
+// library's own device memory: each device holds its copy from the time the
+// library's code is loaded on it, so no call allocates for them.  Word 0
+// takes the answer of a validation pass; word 16 takes bits nobody reads.
+__device__ __align__(256) int g_status_words[64];
+
+// Per-device state: the address of that device's status words and its CU count.
 struct DeviceState {
     int *d_flag = nullptr;
     int n_cu = 0;
@@ -842,26 +1030,21 @@ pairs_status_t current_device(int *dev) {
     return PAIRS_OK;
 }
 
+// Looks the state up on first use on a device (with that device current):
+// the symbol's device address and an attribute query, neither of which
+// allocates.
 pairs_status_t device_state(DeviceState **st) {
     int dev;
     PAIRS_TRY(current_device(&dev));
     std::lock_guard<std::mutex> lock(g_dev_mutex);
     DeviceState &d = g_dev[dev];
     if (!d.d_flag) {
-        void *p = nullptr;
-        hipError_t e = hipMalloc(&p, 256);
-        if (e != hipSuccess) {
-            g_last_hip_error = e;
-            return PAIRS_ERR_NO_MEMORY;
-        }
+        void *flag = nullptr;
+        PAIRS_HIP_CHECK(hipGetSymbolAddress(&flag, HIP_SYMBOL(g_status_words)));
         int ncu = 0;
-        e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) {
-            (void)hipFree(p);
-            return hip_fail(e);
-        }
+        PAIRS_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         d.n_cu = ncu;
-        d.d_flag = (int *)p;
+        d.d_flag = (int *)flag;
     }
     *st = &d;
     return PAIRS_OK;
@@ -926,59 +1109,98 @@ struct Shape {
     int U;
 };
 
+// The double-precision energy and the forces run the float32 energy's shapes
+// with at most 4 rows per lane: their rows and partner sums take twice the
+// registers.
 Shape single_set_shape(int kind, int64_t n) {
-    const ClassTable t = shapes(kind, false);
+    const bool wide = kind == PAIRS_KIND_ENERGY_F64 || kind == PAIRS_KIND_FORCE_F32;
+    const ClassTable t = shapes(wide ? PAIRS_KIND_ENERGY_F32 : kind, false);
     const int c = t.class_of((int)n);
-    return {t.K[c], t.U[c]};
+    return {wide ? std::min(t.K[c], 4) : t.K[c], t.U[c]};
 }
 
-int64_t single_blocks(int n, int K, int U) {
+// Blocks of a single-set launch: one wave per task, at most kMaxSingleBlocks
+// (the waves then stride over the remaining tasks).
+unsigned single_blocks(int n, int K, int U) {
     Tiling t = Tiling::of(Band::of(n), K, U);
-    return (t.tasks() + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int64_t need = (t.tasks() + kWavesPerBlock - 1) / kWavesPerBlock;
+    return (unsigned)std::min<int64_t>(need, kMaxSingleBlocks);
 }
 
 template <int K>
 void launch_count_i32(const int32_t *x, const int32_t *y, const int32_t *z, const int32_t *r,
                       int n, int U, uint64_t *out, hipStream_t s) {
-    int64_t blocks = single_blocks(n, K, U);
-    if (blocks > 0) k_count_i32<K><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, r, n, U, out);
+    const unsigned blocks = single_blocks(n, K, U);
+    if (blocks > 0) k_count_i32<K><<<blocks, kBlock, 0, s>>>(x, y, z, r, n, U, out);
 }
 
 template <int K>
 void launch_count_f32(const float *x, const float *y, const float *z, const float *r, int n,
                       int U, uint64_t *out, hipStream_t s) {
-    int64_t blocks = single_blocks(n, K, U);
-    if (blocks > 0) k_count_f32<K><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, r, n, U, out);
+    const unsigned blocks = single_blocks(n, K, U);
+    if (blocks > 0) k_count_f32<K><<<blocks, kBlock, 0, s>>>(x, y, z, r, n, U, out);
 }
 
 template <int K>
 void launch_energy(const float *x, const float *y, const float *z, int n, int U, float eps2,
-                   double *E, double *total, hipStream_t s) {
-    int64_t blocks = single_blocks(n, K, U);
-    if (blocks <= 0) return;
-    if (E)
-        k_energy<K, true><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
+                   SumSink E, SumSink total, hipStream_t s) {
+    const unsigned blocks = single_blocks(n, K, U);
+    if (blocks == 0) return;
+    if (E.p)
+        k_energy<K, true><<<blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
     else
-        k_energy<K, false><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
+        k_energy<K, false><<<blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
 }
 
 template <int K>
 void launch_energy64(const double *x, const double *y, const double *z, int n, int U, double eps2,
-                     double *E, double *total, hipStream_t s) {
-    int64_t blocks = single_blocks(n, K, U);
-    if (blocks <= 0) return;
-    if (E)
-        k_energy64<K, true><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
+                     SumSink E, SumSink total, hipStream_t s) {
+    const unsigned blocks = single_blocks(n, K, U);
+    if (blocks == 0) return;
+    if (E.p)
+        k_energy64<K, true><<<blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
     else
-        k_energy64<K, false><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
+        k_energy64<K, false><<<blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, E, total);
 }
 
 template <int K>
 void launch_force(const float *x, const float *y, const float *z, int n, int U, float eps2,
-                  double *Fx, double *Fy, double *Fz, hipStream_t s) {
-    int64_t blocks = single_blocks(n, K, U);
-    if (blocks <= 0) return;
-    k_force<K><<<(unsigned)blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, Fx, Fy, Fz);
+                  SumSink Fx, SumSink Fy, SumSink Fz, hipStream_t s) {
+    const unsigned blocks = single_blocks(n, K, U);
+    if (blocks == 0) return;
+    k_force<K><<<blocks, kBlock, 0, s>>>(x, y, z, n, U, eps2, Fx, Fy, Fz);
+}
+
+// Bounds on one term of the potential, 1/sqrt(d2 + eps2) <= 1/sqrt(eps2), and
+// of one force component, |d| / (d2 + eps2)^(3/2) <= 2 / (3 sqrt(3) eps2),
+// with a margin for the float32 evaluation and partial sums.
+double energy_term_bound(double eps2) { return 1.01 / sqrt(eps2); }
+double force_term_bound(double eps2) { return 0.4 / eps2; }
+
+constexpr unsigned kSumFlags = PAIRS_FLAG_VALIDATE | PAIRS_FLAG_DETERMINISTIC;
+
+// Sinks of a single-set sum: double atomics, or under PAIRS_FLAG_DETERMINISTIC
+// fixed point scaled for `bound`, the largest magnitude any partial sum of
+// the output can reach.
+SumSink sink(double *p, bool det, double bound) {
+    return SumSink{p, det ? fixed_scale(bound) : 0.0};
+}
+
+// Converts fixed-point set energies back to doubles (no-op without the flag).
+pairs_status_t finish_sets(const BatchIO &io, int64_t n_sets, hipStream_t s) {
+    if (io.emax <= 0.0 || n_sets <= 0) return PAIRS_OK;
+    k_finish_sets<<<blocks_for(n_sets, 256), 256, 0, s>>>(io.energy, io.off, n_sets, io.n_total,
+                                                          io.emax);
+    PAIRS_HIP_CHECK(hipGetLastError());
+    return PAIRS_OK;
+}
+
+// Converts a fixed-point output back to doubles (no-op without the flag).
+pairs_status_t finish(const SumSink &k, int64_t n, hipStream_t s) {
+    if (k.scale <= 0.0 || !k.p || n <= 0) return PAIRS_OK;
+    k_fixed_finish<<<blocks_for(n, 256), 256, 0, s>>>(k.p, n, 1.0 / k.scale);
+    PAIRS_HIP_CHECK(hipGetLastError());
+    return PAIRS_OK;
 }
 
 int max_rows(const ClassTable &ct) {
@@ -1046,44 +1268,65 @@ pairs_status_t launch_scan(int kind, const BatchIO &io, const ScanSource &src,
     // tasks, and blocks that start as others finish even out the tail
     with_scan_kernel(kind, max_rows(ct), [&](auto kern) {
         const int64_t blocks = resident_blocks(st, kern) * kScanBlockFactor;
-        kern<<<(unsigned)blocks, kBlock, 0, s>>>(io, src, ct);
+        kern<<<blocks, kBlock, 0, s>>>(io, src, ct);
     });
     PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;
 }
 
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-size_t batched_ws_bytes(int64_t n_sets) {
-    return align256(sizeof(int64_t) * (kMaxClasses + 1)) +
-           align256(sizeof(int64_t) * (size_t)kMaxClasses * (size_t)(n_sets + 1));
-}
+constexpr size_t batched_ws_bytes(int64_t n_sets) { return sched_layout(n_sets).total; }
 
 pairs_status_t batched_common(int kind, const BatchIO &io, int64_t n_sets, void *ws,
                               size_t ws_bytes, hipStream_t s) {
     if (!ws || ws_bytes < batched_ws_bytes(n_sets)) return PAIRS_ERR_WORKSPACE;
+    const SchedLayout L = sched_layout(n_sets);
     unsigned char *p = (unsigned char *)ws;
-    int64_t *bases = (int64_t *)p;
-    p += align256(sizeof(int64_t) * (kMaxClasses + 1));
-    int64_t *coff = (int64_t *)p;
+    SchedHeader *hdr = (SchedHeader *)(p + L.hdr);
+    int32_t *list = (int32_t *)(p + L.list);
+    int64_t *pre = (int64_t *)(p + L.pre);
+    int32_t *tab = (int32_t *)(p + L.tab);
+    int64_t *blk = (int64_t *)(p + L.blk);
     const ClassTable ct = shapes(kind == kCountI32   ? PAIRS_KIND_COUNT_I32
                                  : kind == kCountF32 ? PAIRS_KIND_COUNT_F32
                                                      : PAIRS_KIND_ENERGY_F32,
                                  true);
-    k_batch_schedule<<<1, kSchedThreads, 0, s>>>(io.off, n_sets, io.n_total, ct, coff, bases);
+    const unsigned nb = (unsigned)L.nb;
+    k_sched_count<<<nb, kSchedBlock, 0, s>>>(io.off, n_sets, io.n_total, ct, blk);
+    k_sched_scan<<<1, kSchedBlock, 0, s>>>(blk, L.nb, hdr);
+    k_sched_list<<<nb, kSchedBlock, 0, s>>>(io.off, n_sets, io.n_total, ct, blk, hdr, list, pre);
+    // at most n_sets + 1 buckets and the sentinel
+    k_sched_tab<<<blocks_for(n_sets + 2, 256), 256, 0, s>>>(pre, hdr, tab);
     PAIRS_HIP_CHECK(hipGetLastError());
-    ScanSource src{bases, coff, n_sets, ct.count};
+    ScanSource src{hdr, list, pre, tab};
     return launch_scan(kind, io, src, ct, s);
 }
 
 pairs_status_t batched_args(const void *x, const void *y, const void *z,
                             const int64_t *d_offsets, int64_t n_sets, int64_t n_total,
-                            unsigned flags) {
-    if (n_sets < 0 || n_total < 0 || !d_offsets || (flags & ~PAIRS_FLAG_VALIDATE))
+                            unsigned flags, unsigned allowed = PAIRS_FLAG_VALIDATE) {
+    if (n_sets < 0 || n_total < 0 || !d_offsets || (flags & ~allowed))
         return PAIRS_ERR_INVALID_ARG;
     if (n_sets >= INT32_MAX) return PAIRS_ERR_INVALID_ARG;
     if (n_total > 0 && (!x || !y || !z)) return PAIRS_ERR_INVALID_ARG;
     return PAIRS_OK;
+}
+
+// The unplanned batched count into a workspace of ws_bytes at ws; arguments
+// already checked.  The schedule kernel
+// writes every workspace word the scan kernel reads, so nothing needs
+// clearing between calls.
+pairs_status_t count_i32_batched(const int32_t *x, const int32_t *y, const int32_t *z,
+                                 const int32_t *r, const int64_t *d_offsets, int64_t n_sets,
+                                 int64_t n_total, uint64_t *d_counts, void *ws, size_t ws_bytes,
+                                 unsigned flags, hipStream_t s) {
+    if (flags & PAIRS_FLAG_VALIDATE) {
+        PAIRS_TRY(validate_offsets(d_offsets, n_sets, n_total, s));
+        PAIRS_TRY(validate_i32(x, y, z, r, n_total, s));
+    }
+    PAIRS_TRY(fill_u64(d_counts, n_sets, 0, s));
+    if (n_sets == 0) return PAIRS_OK;
+    BatchIO io{x, y, z, r, d_offsets, n_total, d_counts, nullptr, 0.0f};
+    return batched_common(kCountI32, io, n_sets, ws, ws_bytes, s);
 }
 
 // ----------------------------------------------------------- binned count --
@@ -1093,7 +1336,7 @@ namespace bin = pairs_binning;
 // Workspace layout of a binned count of n objects.
 struct BinnedLayout {
     size_t keys_in, keys_out, idx_in, idx_out, so, ukeys, sizes, off, runs, temp;
-    size_t htags, hkeys, hvals, hcnt, big, big_n;
+    size_t htags, hkeys, hvals, hcnt, items, item_pre, item_n;
     size_t temp_bytes, total;
     int blog;  // cell table of 2^blog buckets of 8 slots, at least 2n slots
 };
@@ -1163,8 +1406,10 @@ pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
     L->hkeys = take(8 * slots);
     L->hvals = take(8 * slots);
     L->hcnt = take(4 * (size_t(1) << L->blog));
-    L->big = take(4 * un);
-    L->big_n = take(8);
+    const size_t cap = (size_t)bin::item_capacity(n);
+    L->items = take(sizeof(bin::Item) * cap);
+    L->item_pre = take(8 * (cap + 1));
+    L->item_n = take(8);
     L->temp_bytes = std::max(t1, std::max(t2, t3));
     L->temp = take(L->temp_bytes);
     L->total = p;
@@ -1302,6 +1547,7 @@ pairs_status_t lattice_args(const int32_t *x, const int32_t *y, const int32_t *z
 
 struct pairs_plan_s {
     int kind;
+    bool det;  // fixed-point set energies (PAIRS_PLAN_DETERMINISTIC)
     int device;
     int64_t n_sets;
     int64_t n_total;
@@ -1376,7 +1622,7 @@ pairs_status_t pairs_count_f32(const float *x, const float *y, const float *z, c
 pairs_status_t pairs_energy_f32(const float *x, const float *y, const float *z, int64_t n,
                                 float eps2, double *d_energy, double *d_total, unsigned flags,
                                 pairs_stream_t stream) {
-    if (!d_total || n < 0 || n > PAIRS_MAX_SET_SIZE || (flags & ~PAIRS_FLAG_VALIDATE))
+    if (!d_total || n < 0 || n > PAIRS_MAX_SET_SIZE || (flags & ~kSumFlags))
         return PAIRS_ERR_INVALID_ARG;
     if (!(eps2 > 0.0f) || !isfinite(eps2)) return PAIRS_ERR_INVALID_ARG;
     if (n > 0 && (!x || !y || !z)) return PAIRS_ERR_INVALID_ARG;
@@ -1387,21 +1633,26 @@ pairs_status_t pairs_energy_f32(const float *x, const float *y, const float *z, 
     PAIRS_TRY(fill_f64(d_total, 1, 0.0, s));
     PAIRS_TRY(fill_f64(d_energy, n, 0.0, s));
     if (n < 2) return PAIRS_OK;
+    const bool det = flags & PAIRS_FLAG_DETERMINISTIC;
+    const double emax = energy_term_bound(eps2), dn = (double)n;
+    const SumSink E = sink(d_energy, det, (dn - 1.0) * emax);
+    const SumSink T = sink(d_total, det, 0.5 * dn * (dn - 1.0) * emax);
     Shape sh = single_set_shape(PAIRS_KIND_ENERGY_F32, n);
     switch (sh.K) {
-        case 1: launch_energy<1>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
-        case 2: launch_energy<2>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
-        case 4: launch_energy<4>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
-        default: launch_energy<8>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
+        case 1: launch_energy<1>(x, y, z, (int)n, sh.U, eps2, E, T, s); break;
+        case 2: launch_energy<2>(x, y, z, (int)n, sh.U, eps2, E, T, s); break;
+        case 4: launch_energy<4>(x, y, z, (int)n, sh.U, eps2, E, T, s); break;
+        default: launch_energy<8>(x, y, z, (int)n, sh.U, eps2, E, T, s); break;
     }
     PAIRS_HIP_CHECK(hipGetLastError());
-    return PAIRS_OK;
+    PAIRS_TRY(finish(E, n, s));
+    return finish(T, 1, s);
 }
 
 pairs_status_t pairs_energy_f64(const double *x, const double *y, const double *z, int64_t n,
                                 double eps2, double *d_energy, double *d_total, unsigned flags,
                                 pairs_stream_t stream) {
-    if (!d_total || n < 0 || n > PAIRS_MAX_SET_SIZE || (flags & ~PAIRS_FLAG_VALIDATE))
+    if (!d_total || n < 0 || n > PAIRS_MAX_SET_SIZE || (flags & ~kSumFlags))
         return PAIRS_ERR_INVALID_ARG;
     if (!(eps2 > 0.0) || !isfinite(eps2)) return PAIRS_ERR_INVALID_ARG;
     if (n > 0 && (!x || !y || !z)) return PAIRS_ERR_INVALID_ARG;
@@ -1415,22 +1666,25 @@ pairs_status_t pairs_energy_f64(const double *x, const double *y, const double *
     PAIRS_TRY(fill_f64(d_total, 1, 0.0, s));
     PAIRS_TRY(fill_f64(d_energy, n, 0.0, s));
     if (n < 2) return PAIRS_OK;
-    // the float32 energy kernel's tile shapes, at most 4 rows per lane:
-    // double rows and partner sums take twice the registers
-    const Shape sh = single_set_shape(PAIRS_KIND_ENERGY_F32, n);
-    switch (std::min(sh.K, 4)) {
-        case 1: launch_energy64<1>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
-        case 2: launch_energy64<2>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
-        default: launch_energy64<4>(x, y, z, (int)n, sh.U, eps2, d_energy, d_total, s); break;
+    const bool det = flags & PAIRS_FLAG_DETERMINISTIC;
+    const double emax = energy_term_bound(eps2), dn = (double)n;
+    const SumSink E = sink(d_energy, det, (dn - 1.0) * emax);
+    const SumSink T = sink(d_total, det, 0.5 * dn * (dn - 1.0) * emax);
+    const Shape sh = single_set_shape(PAIRS_KIND_ENERGY_F64, n);
+    switch (sh.K) {
+        case 1: launch_energy64<1>(x, y, z, (int)n, sh.U, eps2, E, T, s); break;
+        case 2: launch_energy64<2>(x, y, z, (int)n, sh.U, eps2, E, T, s); break;
+        default: launch_energy64<4>(x, y, z, (int)n, sh.U, eps2, E, T, s); break;
     }
     PAIRS_HIP_CHECK(hipGetLastError());
-    return PAIRS_OK;
+    PAIRS_TRY(finish(E, n, s));
+    return finish(T, 1, s);
 }
 
 pairs_status_t pairs_force_f32(const float *x, const float *y, const float *z, int64_t n,
                                float eps2, double *d_fx, double *d_fy, double *d_fz,
                                unsigned flags, pairs_stream_t stream) {
-    if (n < 0 || n > PAIRS_MAX_SET_SIZE || (flags & ~PAIRS_FLAG_VALIDATE))
+    if (n < 0 || n > PAIRS_MAX_SET_SIZE || (flags & ~kSumFlags))
         return PAIRS_ERR_INVALID_ARG;
     if (!(eps2 > 0.0f) || !isfinite(eps2)) return PAIRS_ERR_INVALID_ARG;
     if (n > 0 && (!x || !y || !z || !d_fx || !d_fy || !d_fz)) return PAIRS_ERR_INVALID_ARG;
@@ -1442,16 +1696,21 @@ pairs_status_t pairs_force_f32(const float *x, const float *y, const float *z, i
     PAIRS_TRY(fill_f64(d_fy, n, 0.0, s));
     PAIRS_TRY(fill_f64(d_fz, n, 0.0, s));
     if (n < 2) return PAIRS_OK;
-    // the energy kernel's tile shapes, at most 4 rows per lane: three
-    // components per row and per partner sum need the registers of two
-    const Shape sh = single_set_shape(PAIRS_KIND_ENERGY_F32, n);
-    switch (std::min(sh.K, 4)) {
-        case 1: launch_force<1>(x, y, z, (int)n, sh.U, eps2, d_fx, d_fy, d_fz, s); break;
-        case 2: launch_force<2>(x, y, z, (int)n, sh.U, eps2, d_fx, d_fy, d_fz, s); break;
-        default: launch_force<4>(x, y, z, (int)n, sh.U, eps2, d_fx, d_fy, d_fz, s); break;
+    const bool det = flags & PAIRS_FLAG_DETERMINISTIC;
+    // partial sums of a component never exceed the sum of |f| over n - 1 pairs
+    const double bound = ((double)n - 1.0) * force_term_bound(eps2);
+    const SumSink Fx = sink(d_fx, det, bound), Fy = sink(d_fy, det, bound),
+                  Fz = sink(d_fz, det, bound);
+    const Shape sh = single_set_shape(PAIRS_KIND_FORCE_F32, n);
+    switch (sh.K) {
+        case 1: launch_force<1>(x, y, z, (int)n, sh.U, eps2, Fx, Fy, Fz, s); break;
+        case 2: launch_force<2>(x, y, z, (int)n, sh.U, eps2, Fx, Fy, Fz, s); break;
+        default: launch_force<4>(x, y, z, (int)n, sh.U, eps2, Fx, Fy, Fz, s); break;
     }
     PAIRS_HIP_CHECK(hipGetLastError());
-    return PAIRS_OK;
+    PAIRS_TRY(finish(Fx, n, s));
+    PAIRS_TRY(finish(Fy, n, s));
+    return finish(Fz, n, s);
 }
 
 pairs_status_t pairs_batched_workspace_size(int64_t n_sets, int64_t n_total, size_t *bytes) {
@@ -1469,15 +1728,8 @@ pairs_status_t pairs_count_i32_batched(const int32_t *x, const int32_t *y, const
     if (!d_ws || ws_bytes < batched_ws_bytes(n_sets)) return PAIRS_ERR_WORKSPACE;
     int dev;
     PAIRS_TRY(current_device(&dev));
-    hipStream_t s = (hipStream_t)stream;
-    if (flags & PAIRS_FLAG_VALIDATE) {
-        PAIRS_TRY(validate_offsets(d_offsets, n_sets, n_total, s));
-        PAIRS_TRY(validate_i32(x, y, z, r, n_total, s));
-    }
-    PAIRS_TRY(fill_u64(d_counts, n_sets, 0, s));
-    if (n_sets == 0) return PAIRS_OK;
-    BatchIO io{x, y, z, r, d_offsets, n_total, d_counts, nullptr, 0.0f};
-    return batched_common(kCountI32, io, n_sets, d_ws, ws_bytes, s);
+    return count_i32_batched(x, y, z, r, d_offsets, n_sets, n_total, d_counts, d_ws, ws_bytes,
+                             flags, (hipStream_t)stream);
 }
 
 pairs_status_t pairs_count_f32_batched(const float *x, const float *y, const float *z,
@@ -1505,7 +1757,7 @@ pairs_status_t pairs_energy_f32_batched(const float *x, const float *y, const fl
                                         int64_t n_total, float eps2, double *d_set_energy,
                                         uint64_t *d_set_counts, void *d_ws, size_t ws_bytes,
                                         unsigned flags, pairs_stream_t stream) {
-    PAIRS_TRY(batched_args(x, y, z, d_offsets, n_sets, n_total, flags));
+    PAIRS_TRY(batched_args(x, y, z, d_offsets, n_sets, n_total, flags, kSumFlags));
     if (!(eps2 > 0.0f) || !isfinite(eps2)) return PAIRS_ERR_INVALID_ARG;
     if (n_sets > 0 && !d_set_energy) return PAIRS_ERR_INVALID_ARG;
     if ((r == nullptr) != (d_set_counts == nullptr)) return PAIRS_ERR_INVALID_ARG;
@@ -1521,16 +1773,21 @@ pairs_status_t pairs_energy_f32_batched(const float *x, const float *y, const fl
     PAIRS_TRY(fill_u64(d_set_counts, n_sets, 0, s));
     if (n_sets == 0) return PAIRS_OK;
     BatchIO io{x, y, z, r, d_offsets, n_total, d_set_counts, d_set_energy, eps2};
-    return batched_common(kEnergyF32, io, n_sets, d_ws, ws_bytes, s);
+    if (flags & PAIRS_FLAG_DETERMINISTIC) io.emax = energy_term_bound(eps2);
+    PAIRS_TRY(batched_common(kEnergyF32, io, n_sets, d_ws, ws_bytes, s));
+    return finish_sets(io, n_sets, s);
 }
 
 pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_sets,
                                  pairs_plan_t *out) {
     if (!out) return PAIRS_ERR_INVALID_ARG;
     *out = nullptr;
+    const bool det = (kind & PAIRS_PLAN_DETERMINISTIC) != 0;
+    kind &= ~PAIRS_PLAN_DETERMINISTIC;
     if (kind != PAIRS_KIND_COUNT_I32 && kind != PAIRS_KIND_COUNT_F32 &&
         kind != PAIRS_KIND_ENERGY_F32)
         return PAIRS_ERR_INVALID_ARG;
+    if (det && kind != PAIRS_KIND_ENERGY_F32) return PAIRS_ERR_INVALID_ARG;
     if (n_sets < 0 || n_sets >= INT32_MAX || !h_offsets) return PAIRS_ERR_INVALID_ARG;
     if (h_offsets[0] != 0) return PAIRS_ERR_INVALID_ARG;
     for (int64_t s = 0; s < n_sets; ++s) {
@@ -1716,6 +1973,7 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
     pairs_plan_s *p = new (std::nothrow) pairs_plan_s();
     if (!p) return PAIRS_ERR_NO_MEMORY;
     p->kind = kind;
+    p->det = det;
     p->device = dev;
     p->n_sets = n_sets;
     p->n_total = h_offsets[n_sets];
@@ -1798,6 +2056,7 @@ pairs_status_t pairs_plan_execute(pairs_plan_t plan, const void *const *in, void
         io.energy = (double *)out[0];
         io.counts = (uint64_t *)out[1];
         io.eps2 = eps2;
+        if (plan->det) io.emax = energy_term_bound(eps2);
         if (plan->n_sets > 0 && !io.energy) return PAIRS_ERR_INVALID_ARG;
         if ((io.r == nullptr) != (io.counts == nullptr)) return PAIRS_ERR_INVALID_ARG;
         PAIRS_TRY(fill_f64(io.energy, plan->n_sets, 0.0, s));
@@ -1814,11 +2073,11 @@ pairs_status_t pairs_plan_execute(pairs_plan_t plan, const void *const *in, void
                                                           : kEnergyF32;
     const int64_t blocks = (plan->n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
     with_plan_kernel(kind, plan->kmax, [&](auto kern) {
-        kern<<<(unsigned)blocks, kBlock, 0, s>>>(io, plan->d_descs, plan->d_wave_start,
+        kern<<<blocks, kBlock, 0, s>>>(io, plan->d_descs, plan->d_wave_start,
                                                   plan->n_waves);
     });
     PAIRS_HIP_CHECK(hipGetLastError());
-    return PAIRS_OK;
+    return finish_sets(io, plan->n_sets, s);
 }
 
 pairs_status_t pairs_plan_destroy(pairs_plan_t plan) {
@@ -1976,6 +2235,41 @@ pairs_status_t pairs_debug_task_ranges(int n, int rows_per_lane, int chunk, int3
     return PAIRS_OK;
 }
 
+pairs_status_t pairs_debug_task_at(int64_t n, int rows_per_lane, int chunk,
+                                   const int64_t *tasks, int64_t count, int64_t *out) {
+    if (n < 0 || n > PAIRS_MAX_SET_SIZE || count < 0 || (count > 0 && (!tasks || !out)) ||
+        (rows_per_lane != 1 && rows_per_lane != 2 && rows_per_lane != 4 && rows_per_lane != 8) ||
+        chunk < 64 || chunk % 64 != 0 || chunk > (1 << 22))
+        return PAIRS_ERR_INVALID_ARG;
+    const Band band = Band::of((int)n);
+    const Tiling til = Tiling::of(band, rows_per_lane, chunk);
+    for (int64_t k = 0; k < count; ++k)
+        if (tasks[k] < 0 || tasks[k] >= til.tasks()) return PAIRS_ERR_INVALID_ARG;
+    for (int64_t k = 0; k < count; ++k) {
+        int ra, u0, u1;
+        task_at(band, til, tasks[k], &ra, &u0, &u1);
+        out[3 * k] = ra;
+        out[3 * k + 1] = u0;
+        out[3 * k + 2] = u1;
+    }
+    return PAIRS_OK;
+}
+
+pairs_status_t pairs_debug_single_launch(int kind, int64_t n, int64_t *n_tasks,
+                                         int64_t *n_blocks, int32_t *threads) {
+    if (kind < PAIRS_KIND_COUNT_I32 || kind > PAIRS_KIND_FORCE_F32 || n < 0 ||
+        n > PAIRS_MAX_SET_SIZE || !n_tasks || !n_blocks || !threads)
+        return PAIRS_ERR_INVALID_ARG;
+    *n_tasks = 0;
+    *n_blocks = 0;
+    *threads = kBlock;
+    if (n < 2) return PAIRS_OK;
+    const Shape sh = single_set_shape(kind, n);
+    *n_tasks = Tiling::of(Band::of((int)n), sh.K, sh.U).tasks();
+    *n_blocks = single_blocks((int)n, sh.K, sh.U);
+    return PAIRS_OK;
+}
+
 pairs_status_t pairs_binned_workspace_size(int64_t n, size_t *bytes) {
     if (!bytes || n < 0 || n > PAIRS_BINNED_MAX_SET_SIZE) return PAIRS_ERR_INVALID_ARG;
     if (n > 0) {
@@ -2027,9 +2321,12 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
     uint2 *hvals = (uint2 *)(w + L.hvals);
     uint32_t *hcnt = (uint32_t *)(w + L.hcnt);
     uint8_t *htags = (uint8_t *)(w + L.htags);
-    uint32_t *big = (uint32_t *)(w + L.big), *big_n = (uint32_t *)(w + L.big_n);
+    uint32_t *item_n = (uint32_t *)(w + L.item_n);
+    const bin::ItemList items{(bin::Item *)(w + L.items), item_n,
+                              (uint32_t)bin::item_capacity(n)};
+    int64_t *item_pre = (int64_t *)(w + L.item_pre);
     const int64_t buckets = int64_t(1) << L.blog;
-    bin::ClearRanges cr = {{(uint32_t *)d_count, sizes, (uint32_t *)htags, hcnt, big_n},
+    bin::ClearRanges cr = {{(uint32_t *)d_count, sizes, (uint32_t *)htags, hcnt, item_n},
                            {2, n + 1, buckets * bin::kSlots / 4, buckets, 1}};
     bin::k_bin_clear<<<dim3((unsigned)std::min<int64_t>(blocks_for(n + 1, 256), 2048),
                             bin::kClearRanges),
@@ -2046,16 +2343,16 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
     PAIRS_HIP_CHECK(rocprim::exclusive_scan(temp, tb, sizes, off, 0u, (size_t)n + 1,
                                             rocprim::plus<uint32_t>(), s));
     bin::k_bin_hash_build<<<nb, 256, 0, s>>>(ukeys, off, runs, htags, hkeys, hvals, hcnt, L.blog);
-    // 16 lanes per small cell, one wave per big one, at most a few waves per
-    // SIMD of the device
+    // 16 lanes per occupied cell, at most a few waves per SIMD of the device;
+    // then the work items' tasks, shared by every wave
     const int64_t blocks = std::min<int64_t>((n + 15) / 16, (int64_t)st->n_cu * 16);
     bin::k_bin_count<<<(unsigned)blocks, bin::kBlock, 0, s>>>(
-        so, ukeys, off, runs, (const uint64_t *)htags, hkeys, hvals, L.blog, fb, big, big_n,
-        d_count);
-    const int64_t big_blocks = std::min<int64_t>((n / bin::kBigCell + 3) / 4 + 1,
-                                                 (int64_t)st->n_cu * 16);
-    bin::k_bin_count_big<<<(unsigned)big_blocks, bin::kBlock, 0, s>>>(
-        so, ukeys, off, (const uint64_t *)htags, hkeys, hvals, L.blog, fb, big, big_n, d_count);
+        so, ukeys, off, runs, (const uint64_t *)htags, hkeys, hvals, L.blog, fb, items, d_count);
+    bin::k_bin_item_scan<<<1, bin::kScanThreads, 0, s>>>(items, item_pre);
+    const int64_t item_blocks = std::min<int64_t>(n / (4 * bin::kBigCell) + 1,
+                                                  (int64_t)st->n_cu * 8);
+    bin::k_bin_count_items<<<(unsigned)item_blocks, bin::kBlock, 0, s>>>(so, items, item_pre,
+                                                                       d_count);
     PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;
 }

@@ -341,18 +341,15 @@ __device__ __forceinline__ StepCountResult step_count_i32(const StepRaw<int32_t>
     const StepLane p = step_lane<Pack>(g);
     RowI32 rows[K];
     bool extra[K];
+    bool in = true;  // rows and staged entries of this lane inside the plain test's box
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int r = g.r0 + K * p.l + k;
         extra[k] = r < g.half;
         if (p.live && r < g.n) {
             const int4 v = k == 0 ? raw.row0 : raw.row1;  // k is a constant here
-            const int32_t x = v.x, y = v.y, z = v.z, rr = v.w;
-            rows[k].ax = 2 * x;
-            rows[k].ay = 2 * y;
-            rows[k].az = 2 * z;
-            rows[k].ar = 2 * rr;
-            rows[k].nq = -gram_q(x, y, z, rr);
+            rows[k] = gram_row(v.x, v.y, v.z, v.w);
+            in = in && in_box<kBoxBitsI64>(v.x, v.y, v.z, v.w);
         } else {
             rows[k].ax = rows[k].ay = rows[k].az = rows[k].ar = 0;
             rows[k].nq = -((int64_t)1 << 62);  // never hits
@@ -361,6 +358,7 @@ __device__ __forceinline__ StepCountResult step_count_i32(const StepRaw<int32_t>
     step_stage<int32_t, K, Pack>(g, p, raw, [&](int e, bool valid, const int4 &v) PAIRS_INLINE {
         wa[e] = valid ? v : make_int4(0, 0, 0, 0);
         wq[e] = valid ? gram_q(v.x, v.y, v.z, v.w) : INT64_MAX;  // sentinel: never reached
+        in = in && (!valid || in_box<kBoxBitsI64>(v.x, v.y, v.z, v.w));
     });
     hook();
     const int e0 = (p.j * K) * g.S + p.l;
@@ -371,6 +369,29 @@ __device__ __forceinline__ StepCountResult step_count_i32(const StepRaw<int32_t>
         else
             res.wave += count_bits(hit);
     };
+    if (!wave_all(in)) {
+        // a row or window object outside the plain test's box: the wide test
+        // for the whole task (sentinel entries, q = INT64_MAX, are read only
+        // by padding rows, whose results are not counted)
+        auto wide = [&](int e, int k, bool masked) PAIRS_INLINE {
+            const int4 v = wa[e];
+            bool hit = gram_hit_wide(rows[k], PartnerI32{v.x, v.y, v.z, v.w}, wq[e]);
+            if (masked) hit = hit && extra[k];
+            tally(hit && (p.live && g.r0 + K * p.l + k < g.n));
+        };
+        step_sweep<K>(
+            g, e0, wide,
+            [&](int ea, int eb) PAIRS_INLINE {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    wide(ea, k, false);
+                    wide(eb, k, false);
+                }
+            },
+            []() PAIRS_INLINE {});
+        wave_sync();
+        return res;
+    }
     step_sweep<K>(
         g, e0,
         [&](int e, int k, bool masked) PAIRS_INLINE {

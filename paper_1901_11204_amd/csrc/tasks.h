@@ -27,12 +27,20 @@ namespace pairs_dev {
 //   |p_i - p_j|^2 <= (r_i + r_j)^2  <=>  q_i + q_j <= 2 (p_i.p_j + r_i r_j),
 // which is evaluated as v = -q_i + sum over the four coordinates of
 // (2 c_i) c_j with 32x32->64-bit multiply-adds, and the test v >= q_j.
-// For |coordinate|, r <= 2^29 every 2 c_i fits in 32 bits, every product is
-// at most 2^59 in magnitude and every partial sum stays below 2^62, so nothing
-// overflows and the test is exact; the library's domain (2^24) is inside.
+// For coordinates in [-2^29, 2^29) and radii in [0, 2^30) every 2 c_i fits
+// in 32 bits, every product is below 2^61 in magnitude and every partial sum
+// below 2^62, so nothing overflows and the test is exact.
+//
+// The library's domain is wider: coordinates in [-2^30, 2^30), radii in
+// [0, 2^30].  There the same sum, taken modulo 2^64, still identifies the
+// exact value T = v - q_j = (r_i + r_j)^2 - |p_i - p_j|^2, because T lies in
+// (-3 * 2^62, 2^62], an interval of length 2^64: T >= 0 exactly when
+// (v - q_j) mod 2^64 <= 2^62.  That "wide" test costs two more operations per
+// pair, so a wave takes it only for a task whose rows, or a partner group
+// whose objects, leave the box of the plain test (a wave-uniform ballot).
 
 struct RowI32 {
-    int32_t ax, ay, az, ar;  // 2x, 2y, 2z, 2r
+    int32_t ax, ay, az, ar;  // 2x, 2y, 2z, 2r (2r as the low 32 bits: 2^31 at r = 2^30)
     int64_t nq;              // -q
 };
 
@@ -41,11 +49,23 @@ struct PartnerI32 {
 };
 
 __device__ __forceinline__ int64_t gram_q(int32_t x, int32_t y, int32_t z, int32_t r) {
-    int64_t q = (int64_t)x * x;
-    q += (int64_t)y * y;
-    q += (int64_t)z * z;
-    q -= (int64_t)r * r;
-    return q;
+    uint64_t q = (uint64_t)((int64_t)x * x);
+    q += (uint64_t)((int64_t)y * y);
+    q += (uint64_t)((int64_t)z * z);
+    q -= (uint64_t)((int64_t)r * r);
+    return (int64_t)q;  // in [-2^60, 3 * 2^60] inside the domain
+}
+
+__device__ __forceinline__ int32_t twice(int32_t v) { return (int32_t)((uint32_t)v << 1); }
+
+__device__ __forceinline__ RowI32 gram_row(int32_t x, int32_t y, int32_t z, int32_t r) {
+    RowI32 a;
+    a.ax = twice(x);
+    a.ay = twice(y);
+    a.az = twice(z);
+    a.ar = twice(r);
+    a.nq = (int64_t)(0 - (uint64_t)gram_q(x, y, z, r));
+    return a;
 }
 
 __device__ __forceinline__ bool gram_hit(const RowI32 &a, const PartnerI32 &b, int64_t qb) {
@@ -55,6 +75,30 @@ __device__ __forceinline__ bool gram_hit(const RowI32 &a, const PartnerI32 &b, i
     v += (int64_t)a.ar * b.r;
     return v >= qb;
 }
+
+// The wide test, exact on the whole domain (modulo-2^64 sum; the radius
+// product unsigned, as 2r may be 2^31).
+__device__ __forceinline__ bool gram_hit_wide(const RowI32 &a, const PartnerI32 &b, int64_t qb) {
+    uint64_t v = (uint64_t)a.nq;
+    v += (uint64_t)((int64_t)a.ax * b.x);
+    v += (uint64_t)((int64_t)a.ay * b.y);
+    v += (uint64_t)((int64_t)a.az * b.z);
+    v += (uint64_t)(uint32_t)a.ar * (uint32_t)b.r;
+    return v - (uint64_t)qb <= ((uint64_t)1 << 62);
+}
+
+// Whether an object lies in the box [-B, B)^3 x [0, 2B) of a plain test,
+// B = 2^bits: one unsigned comparison of the or of the shifted values.
+template <int bits>
+__device__ __forceinline__ bool in_box(int32_t x, int32_t y, int32_t z, int32_t r) {
+    constexpr uint32_t B = 1u << bits;
+    return (((uint32_t)x + B) | ((uint32_t)y + B) | ((uint32_t)z + B) | (uint32_t)r) < 2 * B;
+}
+constexpr int kBoxBitsI64 = 29;  // plain 64-bit integer Gram test
+constexpr int kBoxBitsF64 = 24;  // double-precision Gram test
+
+// True on every lane when no lane's flag is false.
+__device__ __forceinline__ bool wave_all(bool v) { return __builtin_amdgcn_ballot_w64(!v) == 0; }
 
 // LDS window of one wave, in 8-byte words: large enough for both forms (the
 // integer form uses 64 partner records of 16 bytes and 64 q values, the
@@ -124,17 +168,15 @@ __device__ __forceinline__ uint32_t count_i32_task_i64(const int32_t *__restrict
     const int lane = lane_id();
     RowI32 rows[K];
     int row[K], nsteps[K];  // row index and its step count (0 for padding rows)
+    bool rows_in = true;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         int i = ra + kWave * k + lane;
         row[k] = i;
         if (i < band.n) {
             const int32_t x = in.x[k], y = in.y[k], z = in.z[k], r = in.r[k];
-            rows[k].ax = 2 * x;
-            rows[k].ay = 2 * y;
-            rows[k].az = 2 * z;
-            rows[k].ar = 2 * r;
-            rows[k].nq = -gram_q(x, y, z, r);
+            rows[k] = gram_row(x, y, z, r);
+            rows_in = rows_in && in_box<kBoxBitsI64>(x, y, z, r);
             nsteps[k] = band.steps(i);
         } else {
             rows[k].ax = rows[k].ay = rows[k].az = rows[k].ar = 0;
@@ -142,6 +184,7 @@ __device__ __forceinline__ uint32_t count_i32_task_i64(const int32_t *__restrict
             nsteps[k] = 0;
         }
     }
+    const bool rows_plain = wave_all(rows_in);
     const int rlast = min(ra + kWave * K, band.n) - 1;
     const int core_lo = rlast + 1;            // every row has u - 1 >= row
     const int core_hi = ra + band.steps(ra);  // every row has u <= row + steps(row)
@@ -149,12 +192,15 @@ __device__ __forceinline__ uint32_t count_i32_task_i64(const int32_t *__restrict
     uint32_t cnt = 0;
     int32_t qx = in.px, qy = in.py, qz = in.pz, qr = in.pr;  // this group's partner values
     for (int g0 = u0; g0 < u1; g0 += kWave) {
+        bool plain;
         {
             PartnerI32 p;
             p.x = qx; p.y = qy; p.z = qz; p.r = qr;
             wp[lane] = p;
+            const bool pad = g0 + lane >= u1;
             // padding partner: q above any reachable v, never hits
-            wq[lane] = (g0 + lane >= u1) ? INT64_MAX : gram_q(qx, qy, qz, qr);
+            wq[lane] = pad ? INT64_MAX : gram_q(qx, qy, qz, qr);
+            plain = rows_plain && wave_all(pad || in_box<kBoxBitsI64>(qx, qy, qz, qr));
         }
         {
             int u = g0 + kWave + lane;
@@ -165,7 +211,7 @@ __device__ __forceinline__ uint32_t count_i32_task_i64(const int32_t *__restrict
         }
         wave_sync();
         const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
-        if (g0 >= core_lo && g0 + gn - 1 <= core_hi) {
+        if (plain && g0 >= core_lo && g0 + gn - 1 <= core_hi) {
 #pragma unroll 2
             for (int t = 0; t < kWave; ++t) {
                 const PartnerI32 b = wp[t];
@@ -173,7 +219,7 @@ __device__ __forceinline__ uint32_t count_i32_task_i64(const int32_t *__restrict
 #pragma unroll
                 for (int k = 0; k < K; ++k) cnt += count_bits(gram_hit(rows[k], b, qb));
             }
-        } else {
+        } else if (plain) {
             for (int t = 0; t < gn; ++t) {
                 const int u = g0 + t;
                 const PartnerI32 b = wp[t];
@@ -182,6 +228,16 @@ __device__ __forceinline__ uint32_t count_i32_task_i64(const int32_t *__restrict
                 for (int k = 0; k < K; ++k)
                     cnt += count_bits_both(gram_hit(rows[k], b, qb), owns(u, row[k], nsteps[k]));
             }
+        } else {
+            for (int t = 0; t < gn; ++t) {
+                const int u = g0 + t;
+                const PartnerI32 b = wp[t];
+                const int64_t qb = wq[t];
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    cnt += count_bits_both(gram_hit_wide(rows[k], b, qb),
+                                           owns(u, row[k], nsteps[k]));
+            }
         }
         wave_sync();
     }
@@ -189,10 +245,12 @@ __device__ __forceinline__ uint32_t count_i32_task_i64(const int32_t *__restrict
 }
 
 // The same predicate in double precision, for tall row blocks.  With
-// h = q/2 = (|p|^2 - r^2)/2 it reads p_i.p_j + r_i r_j - h_i >= h_j; inside
-// |coordinate|, r <= 2^24 every product is an integer of magnitude at most 2^48
-// and every partial sum a multiple of 1/2 below 2^51, so each fused
-// multiply-add and the comparison are exact.  Its partner records are 40
+// h = q/2 = (|p|^2 - r^2)/2 it reads p_i.p_j + r_i r_j - h_i >= h_j; for
+// coordinates in [-2^24, 2^24) and radii in [0, 2^25) every product is an
+// integer below 2^50 in magnitude and every partial sum a multiple of 1/2
+// below 2^52, so each fused multiply-add and the comparison are exact.
+// Outside that box a group takes the wide test from the same double records
+// (wide_hit_f64).  Its partner records are 40
 // bytes instead of 24, but gfx950 issues its FP64 fused multiply-adds and
 // compares slightly faster than the 64-bit integer ones, so it wins where
 // one partner feeds many rows (K >= 4) and LDS traffic is no limit.
@@ -211,6 +269,21 @@ __device__ __forceinline__ void gram_features(int32_t xi, int32_t yi, int32_t zi
     H = 0.5 * a;
 }
 
+// The difference-and-square test, exact on the library's whole domain, from
+// doubles that hold int32 values exactly: each difference is exact in double
+// and below 2^31 in magnitude, so it converts to int32; the squares and their
+// sum (below 3 * 2^62) are exact in unsigned 64-bit integers, as is
+// (r_i + r_j)^2 <= 2^62.
+__device__ __forceinline__ bool wide_hit_f64(double xi, double yi, double zi, double ri,
+                                             double xj, double yj, double zj, double rj) {
+    const int32_t dx = __double2int_rz(xi - xj), dy = __double2int_rz(yi - yj),
+                  dz = __double2int_rz(zi - zj);
+    const uint32_t R = __double2uint_rz(ri + rj);
+    uint64_t d2 = (uint64_t)((int64_t)dx * dx);
+    d2 += (uint64_t)((int64_t)dy * dy);
+    d2 += (uint64_t)((int64_t)dz * dz);
+    return d2 <= (uint64_t)R * R;
+}
 
 template <int K, int KM, typename BandT = Band>
 __device__ __forceinline__ uint32_t count_i32_task_f64(const int32_t *__restrict__ px, const int32_t *__restrict__ py,
@@ -221,6 +294,7 @@ __device__ __forceinline__ uint32_t count_i32_task_f64(const int32_t *__restrict
     const int lane = lane_id();
     double xr[K], yr[K], zr[K], rr[K], nh[K];
     int row[K], nsteps[K];  // row index and its step count (0 for padding rows)
+    bool rows_in = true;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         int i = ra + kWave * k + lane;
@@ -228,6 +302,7 @@ __device__ __forceinline__ uint32_t count_i32_task_f64(const int32_t *__restrict
         if (i < band.n) {
             double h;
             gram_features(in.x[k], in.y[k], in.z[k], in.r[k], xr[k], yr[k], zr[k], rr[k], h);
+            rows_in = rows_in && in_box<kBoxBitsF64>(in.x[k], in.y[k], in.z[k], in.r[k]);
             nh[k] = -h;
             nsteps[k] = band.steps(i);
         } else {
@@ -236,6 +311,7 @@ __device__ __forceinline__ uint32_t count_i32_task_f64(const int32_t *__restrict
             nsteps[k] = 0;
         }
     }
+    const bool rows_plain = wave_all(rows_in);
     const int rlast = min(ra + kWave * K, band.n) - 1;
     const int core_lo = rlast + 1;            // every row has u - 1 >= row
     const int core_hi = ra + band.steps(ra);  // every row has u <= row + steps(row)
@@ -243,10 +319,13 @@ __device__ __forceinline__ uint32_t count_i32_task_f64(const int32_t *__restrict
     uint32_t cnt = 0;
     int32_t qx = in.px, qy = in.py, qz = in.pz, qr = in.pr;  // this group's raw partner values
     for (int g0 = u0; g0 < u1; g0 += kWave) {
+        bool plain;
         {
             double X, Y, Z, R, H;
             gram_features(qx, qy, qz, qr, X, Y, Z, R, H);
-            if (g0 + lane >= u1) H = INFINITY;  // padding partner: never hits
+            const bool pad = g0 + lane >= u1;
+            plain = rows_plain && wave_all(pad || in_box<kBoxBitsF64>(qx, qy, qz, qr));
+            if (pad) H = INFINITY;  // padding partner: never hits
             win[0 * kWave + lane] = X;
             win[1 * kWave + lane] = Y;
             win[2 * kWave + lane] = Z;
@@ -262,7 +341,7 @@ __device__ __forceinline__ uint32_t count_i32_task_f64(const int32_t *__restrict
         }
         wave_sync();
         const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
-        if (g0 >= core_lo && g0 + gn - 1 <= core_hi) {
+        if (plain && g0 >= core_lo && g0 + gn - 1 <= core_hi) {
 #pragma unroll 2
             for (int t = 0; t < kWave; ++t) {
                 const double jx = win[t], jy = win[kWave + t], jz = win[2 * kWave + t],
@@ -275,6 +354,16 @@ __device__ __forceinline__ uint32_t count_i32_task_f64(const int32_t *__restrict
                     v = __builtin_fma(rr[k], jr, v);
                     cnt += count_bits(v >= jh);
                 }
+            }
+        } else if (!plain) {
+            for (int t = 0; t < gn; ++t) {
+                const int u = g0 + t;
+                const double jx = win[t], jy = win[kWave + t], jz = win[2 * kWave + t],
+                             jr = win[3 * kWave + t];
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    cnt += count_bits_both(wide_hit_f64(xr[k], yr[k], zr[k], rr[k], jx, jy, jz, jr),
+                                           owns(u, row[k], nsteps[k]));
             }
         } else {
             for (int t = 0; t < gn; ++t) {
@@ -400,6 +489,39 @@ __device__ __forceinline__ uint32_t count_f32_task(const float *__restrict__ px,
     return cnt;
 }
 
+// ------------------------------------------------------ sums of doubles --
+//
+// The kernels add partial sums of each output (a per-object or per-set sum,
+// a total) with atomics.  By default these are double atomics, whose order
+// varies from run to run and with it the last bits of a result.  With a
+// positive scale 2^S (PAIRS_FLAG_DETERMINISTIC) each partial is rounded once
+// to a multiple of 2^-S and added as a 64-bit integer into the same 8 bytes;
+// integer additions are exact and commute, so the result is the same in
+// every run, and a finishing pass turns the integer back into a double.
+// fixed_scale() chooses 2^S from a bound on every partial sum's magnitude:
+// the largest power of two with bound * 2^S < 2^61, which leaves room for
+// the rounding of each added value.  The absolute error is at most half a
+// unit per added value.
+
+PAIRS_HD double fixed_scale(double bound) {
+    int e;
+    frexp(bound, &e);  // bound < 2^e
+    return ldexp(1.0, 61 - e);
+}
+
+struct SumSink {
+    double *p;
+    double scale;  // 0: double atomics; else fixed point in units of 1/scale
+
+    __device__ __forceinline__ void add(int64_t i, double v) const {
+        if (scale > 0.0)
+            atomicAdd((unsigned long long *)(p + i),
+                      (unsigned long long)__double2ll_rn(v * scale));
+        else
+            atomicAdd(p + i, v);
+    }
+};
+
 // ---------------------------------------------------------------- energy --
 //
 // e = 1/sqrt(d2 + eps2) in float32 with the hardware reciprocal square root.
@@ -481,7 +603,7 @@ template <int K, int KM, bool PerObject, bool WithCount>
 __device__ __forceinline__ EnergyResult energy_task(const float *__restrict__ px, const float *__restrict__ py,
                                     const float *__restrict__ pz, const float *__restrict__ pr,
                                     int64_t base, const Band band, int ra, int u0, int u1,
-                                    float eps2, float *__restrict__ win, double *__restrict__ E,
+                                    float eps2, float *__restrict__ win, const SumSink E,
                                     const TaskInputs<float, KM> &in) {
     const int lane = lane_id();
     float xr[K], yr[K], zr[K], rr[K], part[K];
@@ -533,7 +655,7 @@ __device__ __forceinline__ EnergyResult energy_task(const float *__restrict__ px
         if (PerObject) {
             wave_sync();
             if (lane < gn)
-                atomicAdd(&E[partner_index(base, band, g0 + lane)], (double)win[4 * kWave + lane]);
+                E.add(partner_index(base, band, g0 + lane), (double)win[4 * kWave + lane]);
         }
         wave_sync();
     }
@@ -542,7 +664,7 @@ __device__ __forceinline__ EnergyResult energy_task(const float *__restrict__ px
     for (int k = 0; k < K; ++k) {
         int i = ra + kWave * k + lane;
         if (i < band.n) {
-            if (PerObject) atomicAdd(&E[base + i], acc[k]);
+            if (PerObject) E.add(base + i, acc[k]);
             tot += acc[k];
         }
     }
@@ -628,8 +750,8 @@ template <int K>
 __device__ __forceinline__ void force_task(const float *__restrict__ px, const float *__restrict__ py,
                                            const float *__restrict__ pz, int64_t base,
                                            const Band band, int ra, int u0, int u1, float eps2,
-                                           float *__restrict__ win, double *__restrict__ Fx,
-                                           double *__restrict__ Fy, double *__restrict__ Fz,
+                                           float *__restrict__ win, const SumSink Fx,
+                                           const SumSink Fy, const SumSink Fz,
                                            const TaskInputs<float, K> &in) {
     const int lane = lane_id();
     float xr[K], yr[K], zr[K], part[3][K];
@@ -678,9 +800,9 @@ __device__ __forceinline__ void force_task(const float *__restrict__ px, const f
         wave_sync();
         if (lane < gn) {
             const int64_t g = partner_index(base, band, g0 + lane);
-            atomicAdd(&Fx[g], -(double)win[3 * kWave + lane]);
-            atomicAdd(&Fy[g], -(double)win[4 * kWave + lane]);
-            atomicAdd(&Fz[g], -(double)win[5 * kWave + lane]);
+            Fx.add(g, -(double)win[3 * kWave + lane]);
+            Fy.add(g, -(double)win[4 * kWave + lane]);
+            Fz.add(g, -(double)win[5 * kWave + lane]);
         }
         wave_sync();
     }
@@ -688,9 +810,9 @@ __device__ __forceinline__ void force_task(const float *__restrict__ px, const f
     for (int k = 0; k < K; ++k) {
         int i = ra + kWave * k + lane;
         if (i < band.n) {
-            atomicAdd(&Fx[base + i], acc[0][k]);
-            atomicAdd(&Fy[base + i], acc[1][k]);
-            atomicAdd(&Fz[base + i], acc[2][k]);
+            Fx.add(base + i, acc[0][k]);
+            Fy.add(base + i, acc[1][k]);
+            Fz.add(base + i, acc[2][k]);
         }
     }
 }
@@ -759,7 +881,7 @@ __device__ __forceinline__ double energy64_task(const double *__restrict__ px,
                                                 const double *__restrict__ pz, int64_t base,
                                                 const Band band, int ra, int u0, int u1,
                                                 double eps2, double *__restrict__ win,
-                                                double *__restrict__ E,
+                                                const SumSink E,
                                                 const TaskInputs<double, K> &in) {
     const int lane = lane_id();
     double xr[K], yr[K], zr[K], acc[K];
@@ -804,7 +926,7 @@ __device__ __forceinline__ double energy64_task(const double *__restrict__ px,
                                                slot);
         if (PerObject) {
             wave_sync();
-            if (lane < gn) atomicAdd(&E[partner_index(base, band, g0 + lane)], win[3 * kWave + lane]);
+            if (lane < gn) E.add(partner_index(base, band, g0 + lane), win[3 * kWave + lane]);
         }
         wave_sync();
     }
@@ -813,7 +935,7 @@ __device__ __forceinline__ double energy64_task(const double *__restrict__ px,
     for (int k = 0; k < K; ++k) {
         int i = ra + kWave * k + lane;
         if (i < band.n) {
-            if (PerObject) atomicAdd(&E[base + i], acc[k]);
+            if (PerObject) E.add(base + i, acc[k]);
             tot += acc[k];
         }
     }

@@ -63,6 +63,35 @@ def test_batched_count_i32_lognormal(planned):
     np.testing.assert_array_equal(got, want)
 
 
+@pytest.mark.parametrize("planned", [False, True])
+def test_batched_count_i32_full_domain(planned):
+    """Sets of every form (packs of small sets, stepping row blocks) whose
+    objects span the whole exact domain, some sets entirely inside the plain
+    test's box: each wave takes the plain or the wide test per task."""
+    lo, hi, rmax = -(2 ** 30), 2 ** 30 - 1, 2 ** 30
+    sizes = np.array(EDGE_SIZES + [3, 5, 17, 40, 300, 2000], np.int64)
+    off = w.offsets_from_sizes(sizes)
+    n = int(off[-1])
+    rng = np.random.default_rng(23)
+    x, y, z = (rng.integers(lo, hi, n, endpoint=True).astype(np.int32) for _ in range(3))
+    r = rng.integers(0, rmax, n, endpoint=True).astype(np.int32)
+    # every third set stays dense inside the box (collisions among small values)
+    dense = w.spheres_i32(n, 24, 64, 5, radius_lo=0)
+    for k in range(0, len(sizes), 3):
+        a, b = off[k], off[k + 1]
+        x[a:b], y[a:b], z[a:b], r[a:b] = (v[a:b] for v in dense.arrays())
+    # touching pairs across the span at the start of every set of two or more
+    for k in range(1, len(sizes), 3):
+        a = off[k]
+        if sizes[k] >= 2:
+            x[a], x[a + 1], y[a], y[a + 1], z[a], z[a + 1] = lo, hi, 0, 0, 0, 0
+            r[a], r[a + 1] = rmax, rmax - 1
+    announce("batched count_i32 full domain", planned)
+    got = run_count_i32(x, y, z, r, off, planned)
+    want = oracle.count_i32_batched(x, y, z, r, off)
+    np.testing.assert_array_equal(got, want)
+
+
 def test_batched_permuted_sets_permute_outputs():
     rng = np.random.default_rng(8)
     sizes = rng.integers(0, 700, 60).astype(np.int64)
@@ -141,7 +170,7 @@ def test_batched_validation():
     P.pairs_count_i32_batched(*dev(*s.arrays()), *dev(bad), counts)
     T.cuda.synchronize()
     x = s.x.copy()
-    x[0] = -(2 ** 24) - 1
+    x[0] = -(2 ** 30) - 1
     with pytest.raises(P.PairsError) as e:
         P.pairs_count_i32_batched(*dev(x, s.y, s.z, s.r), *dev(off), counts,
                                   flags=P.FLAG_VALIDATE)

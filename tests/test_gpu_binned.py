@@ -129,3 +129,33 @@ def test_config2_full_size(golden_dir):
     s = w.config2(2 ** 20)
     announce("binned config 2")
     assert binned(s.arrays(), 1 << 15) == want
+
+
+def test_one_cell_above_2p16():
+    """70 000 objects in one cell (more than 2^16): the cell's pairs are tiled
+    into bounded tasks shared by every wave, where one wave per cell would do
+    2.4e9 pair tests alone."""
+    a = spheres(70_000, 81, 0, 4000, 8)
+    announce("binned one cell of 70000 objects")
+    assert binned(a, 1 << 14) == oracle.count_i32(*a)
+
+
+def test_big_cells_next_to_small_and_big():
+    """Big cells (more than 64 objects) next to small cells and next to each
+    other along every forward direction, with isolated small cells between:
+    every pair of ranges with a big side goes through the work items."""
+    cell = 1024
+    rng = np.random.default_rng(82)
+    parts = []
+    for cx, cy, cz, m in [(0, 0, 0, 300), (1, 0, 0, 5), (0, 1, 1, 200), (1, 1, 1, 90),
+                          (5, 5, 5, 2), (5, 5, 6, 150), (6, 6, 6, 40), (9, 0, 0, 65),
+                          (9, 1, 0, 64), (9, 0, 1, 66)]:
+        xyz = rng.integers(0, cell, (m, 3)) + np.array([cx, cy, cz]) * cell
+        parts.append(xyz)
+    xyz = np.concatenate(parts)
+    perm = rng.permutation(len(xyz))
+    xyz = xyz[perm]
+    x, y, z = (np.ascontiguousarray(xyz[:, k].astype(np.int32)) for k in range(3))
+    r = rng.integers(0, cell // 2, len(x), endpoint=True).astype(np.int32)
+    announce("binned big cells next to small and big", len(x))
+    assert binned([x, y, z, r], cell) == oracle.count_i32(x, y, z, r)

@@ -70,42 +70,115 @@ def test_count_i32_every_shape(forced_shape, K, U):
         assert P.count_i32(*dev(*s.arrays())) == oracle.count_i32(*s.arrays()), (K, U, n)
 
 
+LO, HI, RMAX = -(2 ** 30), 2 ** 30 - 1, 2 ** 30   # the exact domain
+
+
+def domain_set(n, seed, lo, hi, rmax):
+    rng = np.random.default_rng(seed)
+    x, y, z = (rng.integers(lo, hi, n, endpoint=True).astype(np.int32) for _ in range(3))
+    r = rng.integers(0, rmax, n, endpoint=True).astype(np.int32)
+    return x, y, z, r
+
+
 @pytest.mark.parametrize("K", [1, 2, 4, 8])
-@pytest.mark.parametrize("L", [2 ** 22, 2 ** 24])
+@pytest.mark.parametrize("L", [2 ** 22, 2 ** 24, 2 ** 29, 2 ** 30])
 def test_count_i32_domain_edges(forced_shape, K, L):
+    """Coordinates in [-L, L) and radii in [0, L] up to the domain's edges,
+    with no flag: the plain Gram tests hold up to 2^24 (double form, K >= 4)
+    and 2^29 (integer form, K <= 2); beyond, waves switch to the wide test."""
     forced_shape(P.KIND_COUNT_I32, K, 256)
-    rng = np.random.default_rng(5)
     n = 3001
-    x, y, z = (rng.integers(-L, L, n, endpoint=True).astype(np.int32) for _ in range(3))
-    r = rng.integers(0, L, n, endpoint=True).astype(np.int32)
+    x, y, z, r = domain_set(n, 5 + K, -L, L - 1, L)
     # pin a few objects to the extreme corners
-    x[:4] = [-L, L, -L, L]
-    y[:4] = [-L, L, L, -L]
-    z[:4] = [L, -L, -L, L]
+    x[:4] = [-L, L - 1, -L, L - 1]
+    y[:4] = [-L, L - 1, L - 1, -L]
+    z[:4] = [L - 1, -L, -L, L - 1]
     r[:4] = [L, L, 0, L]
-    announce("count_i32 domain edges", n)
+    announce("count_i32 domain edges", K, L, n)
+    assert P.count_i32(*dev(x, y, z, r)) == oracle.count_i32(x, y, z, r)
     assert P.count_i32(*dev(x, y, z, r), validate=True) == oracle.count_i32(x, y, z, r)
-    # touching and one-apart pairs at full span
+    # touching and one-apart pairs across the full span
     for gap, expect in ((0, 1), (1, 0)):
-        a = np.array([-L, L], np.int32)
+        a = np.array([-L, L - 1], np.int32)
         zero = np.zeros(2, np.int32)
-        rr = np.array([L, L - gap], np.int32)
-        assert P.count_i32(*dev(a, zero, zero, rr)) == expect
+        rr = np.array([L, L - 1 - gap], np.int32)
+        assert P.count_i32(*dev(a, zero, zero, rr)) == expect, (gap, L)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+def test_count_i32_extreme_pairs(forced_shape, K):
+    """Pairs at the largest distances and radii of the domain, decided at exact
+    equality: the squared distance 3 (2^31 - 1)^2 and the squared radius sum
+    2^62 sit at the edges of the wide test's modulo-2^64 window."""
+    forced_shape(P.KIND_COUNT_I32, K, 64)
+    pts = []
+    # opposite corners: d^2 = 3 (2^31 - 1)^2 > (2^31)^2, never touching
+    pts.append(((LO, LO, LO, RMAX), (HI, HI, HI, RMAX)))
+    # along one axis: d = 2^31 - 1 against R = 2^31 (hit), 2^31 - 1 (hit), 2^31 - 2 (miss)
+    pts.append(((LO, 0, 0, RMAX), (HI, 0, 0, RMAX)))
+    pts.append(((LO, 0, 0, RMAX - 1), (HI, 0, 0, RMAX)))
+    pts.append(((LO, 0, 0, RMAX - 1), (HI, 0, 0, RMAX - 1)))
+    # two axes: d^2 = 2 (2^31 - 1)^2 against (2^31)^2 (miss)
+    pts.append(((LO, LO, 0, RMAX), (HI, HI, 0, RMAX)))
+    # a Pythagorean triple scaled to the span: (3k, 4k) at distance 5k
+    k = (2 ** 31 - 1) // 5
+    pts.append(((-(2 ** 30), -(2 ** 30), 7, (5 * k) // 2), (-(2 ** 30) + 3 * k, -(2 ** 30) + 4 * k,
+                                                          7, 5 * k - (5 * k) // 2)))
+    pts.append(((-(2 ** 30), -(2 ** 30), 7, (5 * k) // 2), (-(2 ** 30) + 3 * k, -(2 ** 30) + 4 * k,
+                                                          7, 5 * k - (5 * k) // 2 - 1)))
+    for a, b in pts:
+        x, y, z, r = (np.array([a[c], b[c]], np.int32) for c in range(4))
+        want = oracle.count_i32(x, y, z, r)
+        announce("count_i32 extreme pair", K, a, b, want)
+        assert P.count_i32(*dev(x, y, z, r)) == want, (a, b)
+    # all of them in one set, shuffled among ordinary objects
+    rng = np.random.default_rng(K)
+    obj = [c for ab in pts for c in ab]
+    x, y, z, r = domain_set(2000, 40 + K, LO, HI, RMAX)
+    for i, o in enumerate(obj):
+        x[i], y[i], z[i], r[i] = o
+    perm = rng.permutation(2000)
+    x, y, z, r = x[perm], y[perm], z[perm], r[perm]
+    assert P.count_i32(*dev(x, y, z, r)) == oracle.count_i32(x, y, z, r)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+def test_count_i32_mixed_boxes(forced_shape, K):
+    """Dense objects inside the plain tests' boxes with a few far outside:
+    tasks and partner groups take the plain and the wide test side by side."""
+    forced_shape(P.KIND_COUNT_I32, K, 128)
+    n = 5000
+    s = dense_i32(n, 90 + K)
+    x, y, z, r = [a.copy() for a in s.arrays()]
+    rng = np.random.default_rng(K)
+    far = rng.choice(n, 9, replace=False)
+    x[far[:3]] = [HI, LO, HI]
+    y[far[3:6]] = [LO, HI, LO]
+    r[far[6:]] = [RMAX, 2 ** 29, 2 ** 24 + 1]     # huge spheres reach everything nearby
+    announce("count_i32 mixed boxes", K, n)
+    assert P.count_i32(*dev(x, y, z, r)) == oracle.count_i32(x, y, z, r)
 
 
 def test_count_i32_validate_rejects_out_of_domain():
     import torch
     s = sparse_i32(100, 3)
+    for axis, v in ((0, 2 ** 30), (1, -(2 ** 30) - 1), (2, 2 ** 31 - 1)):
+        a = [c.copy() for c in (s.x, s.y, s.z)]
+        a[axis][17] = v
+        with pytest.raises(P.PairsError) as e:
+            P.count_i32(*dev(*a, s.r), validate=True)
+        assert e.value.status == -2
+    for bad_r in (-1, 2 ** 30 + 1):
+        r = s.r.copy()
+        r[3] = bad_r
+        with pytest.raises(P.PairsError):
+            P.count_i32(*dev(s.x, s.y, s.z, r), validate=True)
+    # the domain's own edges pass validation
     x = s.x.copy()
-    x[17] = 2 ** 24 + 1
-    t = dev(x, s.y, s.z, s.r)
-    with pytest.raises(P.PairsError) as e:
-        P.count_i32(*t, validate=True)
-    assert e.value.status == -2
+    x[5], x[6] = -(2 ** 30), 2 ** 30 - 1
     r = s.r.copy()
-    r[3] = -1
-    with pytest.raises(P.PairsError):
-        P.count_i32(*dev(s.x, s.y, s.z, r), validate=True)
+    r[7] = 2 ** 30
+    assert P.count_i32(*dev(x, s.y, s.z, r), validate=True) == oracle.count_i32(x, s.y, s.z, r)
     torch.cuda.synchronize()
 
 

@@ -1,0 +1,203 @@
+"""The reproducible reduction (PAIRS_FLAG_DETERMINISTIC, PAIRS_PLAN_DETERMINISTIC):
+energies and forces reduced as 64-bit fixed-point integers are bit-identical
+from call to call and between a graph replay and an eager call, and stay
+within the stated tolerances of the FP64 oracle (totals and per-set sums
+1e-6, per-object sums 1e-5, forces 1e-5 of each object's norm sum)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1901_11204_amd as P
+import workloads as w
+from gpu_util import announce, dev
+
+pytestmark = pytest.mark.gpu
+
+EPS2 = np.float32(1e-4)
+DET = P.FLAG_DETERMINISTIC
+
+
+def T():
+    import torch
+    return torch
+
+
+def bits(t):
+    return t.cpu().numpy().view(np.uint64).copy()
+
+
+def energy(arrays, flags, per_object=True):
+    torch = T()
+    n = int(arrays[0].shape[0])
+    t = dev(*arrays)
+    E = torch.full((n,), 3.0, dtype=torch.float64, device="cuda") if per_object else None
+    tot = torch.full((1,), 5.0, dtype=torch.float64, device="cuda")
+    P.pairs_energy_f32(*t, float(EPS2), E, tot, flags)
+    torch.cuda.synchronize()
+    return E, tot
+
+
+@pytest.mark.parametrize("n", [2, 3, 65, 1000, 4097, 30001])
+def test_energy_f32_reproducible_and_accurate(n):
+    p = w.particles_f32(n, 500 + n)
+    a = p.arrays()
+    announce("deterministic energy_f32", n)
+    E0, t0 = energy(a, DET)
+    for _ in range(2):
+        E1, t1 = energy(a, DET)
+        np.testing.assert_array_equal(bits(E1), bits(E0))
+        np.testing.assert_array_equal(bits(t1), bits(t0))
+    _, t2 = energy(a, DET, per_object=False)
+    np.testing.assert_array_equal(bits(t2), bits(t0))
+    want_t = oracle.energy_total(*a, EPS2)
+    assert abs(float(t0) - want_t) <= 1e-6 * want_t
+    want_E = oracle.energy_rows(*a, EPS2)
+    assert np.max(np.abs(E0.cpu().numpy() - want_E) / want_E) <= 1e-5
+    # the double-atomic path agrees to well within the tolerance
+    Ed, td = energy(a, 0)
+    assert abs(float(td) - float(t0)) <= 1e-9 * want_t
+    assert np.max(np.abs(Ed.cpu().numpy() - E0.cpu().numpy()) / want_E) <= 1e-9
+
+
+@pytest.mark.parametrize("K,U", [(1, 64), (8, 1024)])
+def test_energy_f32_reproducible_every_shape(K, U):
+    P.pairs_set_shapes(P.KIND_ENERGY_F32, False, [(0, K, U)])
+    try:
+        p = w.particles_f32(20011, 77)
+        a = p.arrays()
+        announce("deterministic energy_f32 shape", K, U)
+        E0, t0 = energy(a, DET)
+        E1, t1 = energy(a, DET)
+        np.testing.assert_array_equal(bits(E1), bits(E0))
+        np.testing.assert_array_equal(bits(t1), bits(t0))
+        want_t = oracle.energy_total(*a, EPS2)
+        assert abs(float(t0) - want_t) <= 1e-6 * want_t
+    finally:
+        P.pairs_set_shapes(P.KIND_ENERGY_F32, False, None)
+
+
+def test_energy_f32_clustered_and_spread():
+    # terms near their bound (coincident clusters) and far below it (a
+    # spread-out set: e ~ 1e-4 of 1/sqrt(eps2))
+    rng = np.random.default_rng(3)
+    c = np.repeat(rng.random((40, 3), dtype=np.float32), 50, axis=0)
+    far = (rng.random((2000, 3)) * 1e4).astype(np.float32)
+    for pts in (c, far):
+        a = [np.ascontiguousarray(pts[:, k]) for k in range(3)]
+        E0, t0 = energy(a, DET)
+        E1, t1 = energy(a, DET)
+        np.testing.assert_array_equal(bits(E1), bits(E0))
+        want_t = oracle.energy_total(*a, EPS2)
+        assert abs(float(t0) - want_t) <= 1e-6 * want_t
+        want_E = oracle.energy_rows(*a, EPS2)
+        assert np.max(np.abs(E0.cpu().numpy() - want_E) / want_E) <= 1e-5
+
+
+def test_energy_f64_and_forces_reproducible():
+    torch = T()
+    p = w.particles_f32(9001, 9)
+    a32 = p.arrays()
+    a64 = [v.astype(np.float64) for v in a32]
+    n = 9001
+    runs = []
+    for _ in range(3):
+        E = torch.empty(n, dtype=torch.float64, device="cuda")
+        tot = torch.empty(1, dtype=torch.float64, device="cuda")
+        P.pairs_energy_f64(*dev(*a64), 1e-4, E, tot, DET)
+        F = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        P.pairs_force_f32(*dev(*a32), float(EPS2), *F, DET)
+        torch.cuda.synchronize()
+        runs.append((bits(E), bits(tot), [bits(f) for f in F], E.cpu().numpy(), float(tot),
+                     np.stack([f.cpu().numpy() for f in F], axis=1)))
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r[0], runs[0][0])
+        np.testing.assert_array_equal(r[1], runs[0][1])
+        for c in range(3):
+            np.testing.assert_array_equal(r[2][c], runs[0][2][c])
+    E, tot, Fg = runs[0][3], runs[0][4], runs[0][5]
+    want_t = oracle.energy_f64_total(*a64, 1e-4)
+    assert abs(tot - want_t) <= 1e-12 * want_t
+    assert np.max(np.abs(E - oracle.energy_f64_rows(*a64, 1e-4)) /
+                  oracle.energy_f64_rows(*a64, 1e-4)) <= 1e-12
+    Fw, S = oracle.force_rows(*a32, EPS2)
+    assert np.all(np.abs(Fg - Fw).max(axis=1) <= 1e-5 * S)
+
+
+def batched_energy(arrays, off, flags, planned, counts=True):
+    torch = T()
+    n_sets = len(off) - 1
+    t = dev(*arrays)
+    E = torch.full((n_sets,), 9.0, dtype=torch.float64, device="cuda")
+    C = torch.empty(n_sets, dtype=torch.int64, device="cuda") if counts else None
+    r = t[3] if counts else None
+    if planned:
+        kind = P.KIND_ENERGY_F32 | (P.PLAN_DETERMINISTIC if flags else 0)
+        plan = P.Plan(kind, off)
+        plan.execute((t[0], t[1], t[2], r), (E, C), eps2=float(EPS2))
+        torch.cuda.synchronize()
+        plan.close()
+    else:
+        P.pairs_energy_f32_batched(t[0], t[1], t[2], r, *dev(off), float(EPS2), E, C,
+                                   flags=flags)
+        torch.cuda.synchronize()
+    return E, C
+
+
+@pytest.mark.parametrize("planned", [False, True])
+def test_batched_energy_reproducible(planned):
+    b = w.config5(n_sets=3000, seed=41, size_hi=3000)
+    a = b.objs.arrays()
+    announce("deterministic batched energy", planned)
+    E0, C0 = batched_energy(a, b.offsets, DET, planned)
+    for _ in range(2):
+        E1, C1 = batched_energy(a, b.offsets, DET, planned)
+        np.testing.assert_array_equal(bits(E1), bits(E0))
+        np.testing.assert_array_equal(C1.cpu().numpy(), C0.cpu().numpy())
+    want_e, want_c = oracle.energy_count_f32_batched(*a, b.offsets, EPS2)
+    got = E0.cpu().numpy()
+    nz = want_e > 0
+    assert np.all(got[~nz] == 0)
+    assert np.max(np.abs(got[nz] - want_e[nz]) / want_e[nz]) <= 1e-6
+    np.testing.assert_array_equal(C0.cpu().numpy().astype(np.uint64), want_c)
+    Ed, _ = batched_energy(a, b.offsets, 0, planned)
+    assert np.max(np.abs(Ed.cpu().numpy()[nz] - got[nz]) / want_e[nz]) <= 1e-9
+
+
+def test_graph_replay_equals_eager_deterministic():
+    """A deterministic plan's 3-step graph, replayed twice with eager work in
+    between, against eager jitter + execute on a copy of the positions: every
+    step's set energies are bit-identical."""
+    torch = T()
+    b = w.config5(n_sets=500, seed=43, size_hi=1500)
+    x, y, z, r = b.objs.arrays()
+    steps = 3
+    kind = P.KIND_ENERGY_F32 | P.PLAN_DETERMINISTIC
+    plan = P.Plan(kind, b.offsets)
+    tg = dev(x, y, z, r)
+    te = dev(x, y, z, r)
+    E = torch.zeros(steps * b.n_sets, dtype=torch.float64, device="cuda")
+    C = torch.zeros(steps * b.n_sets, dtype=torch.int64, device="cuda")
+    g = plan.capture_steps(tg[0], tg[1], tg[2], tg[3], seed=6, sigma=1e-3, first_step=0,
+                           n_steps=steps, eps2=float(EPS2), energy=E, counts=C)
+    announce("deterministic graph replay vs eager")
+    for rep in range(2):
+        g.launch()
+        torch.cuda.synchronize()
+        got = bits(E).reshape(steps, b.n_sets)
+        for k in range(steps):
+            P.pairs_jitter_f32(te[0], te[1], te[2], 6, k, 1e-3)
+            Ek = torch.empty(b.n_sets, dtype=torch.float64, device="cuda")
+            Ck = torch.empty(b.n_sets, dtype=torch.int64, device="cuda")
+            plan.execute(te, (Ek, Ck), eps2=float(EPS2))
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(got[k], bits(Ek))
+        # eager work between replays
+        P.count_f32(*[v[:200].contiguous() for v in te])
+    g.close()
+    plan.close()
+
+
+def test_plan_flag_only_for_energies():
+    off = np.array([0, 3, 7], np.int64)
+    with pytest.raises(P.PairsError):
+        P.Plan(P.KIND_COUNT_I32 | P.PLAN_DETERMINISTIC, off)

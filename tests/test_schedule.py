@@ -221,3 +221,68 @@ def test_step_window_emulation_packs(K):
         for j in range(m):
             got = sorted(tuple(sorted((r, o))) for (jj, r, o) in pairs if jj == j)
             assert got == [(a, b) for a in range(n) for b in range(a + 1, n)], (n, Kp, j)
+
+
+# ------------------------------------------------------ launch geometry --
+#
+# A single-set call launches one wave per task up to 2^22 blocks and strides
+# over the rest, so every n up to PAIRS_MAX_SET_SIZE = 2^30 launches within
+# the 2^32 work-item limit of one dispatch.
+
+KINDS = [P.KIND_COUNT_I32, P.KIND_COUNT_F32, P.KIND_ENERGY_F32, P.KIND_ENERGY_F64,
+         P.KIND_FORCE_F32]
+LARGE = [2, 3, 4095, 4096, 2 ** 20, 2 ** 22, 2 ** 22 + 1, 2 ** 23, 204 ** 3, 2 ** 27 - 1,
+         2 ** 27, 2 ** 29 + 7, 2 ** 30 - 1, 2 ** 30]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_single_launch_fits_one_dispatch(kind):
+    assert P.pairs_debug_single_launch(kind, 0) == (0, 0, 256)
+    assert P.pairs_debug_single_launch(kind, 1) == (0, 0, 256)
+    for n in LARGE:
+        tasks, blocks, threads = P.pairs_debug_single_launch(kind, n)
+        assert tasks >= 1 and 1 <= blocks <= 2 ** 22, (kind, n)
+        assert blocks * threads < 2 ** 32, (kind, n)
+        waves = blocks * threads // 64
+        if tasks <= 4 * 2 ** 22:
+            assert blocks == -(-tasks // 4)           # one wave per task
+        else:
+            assert waves == 2 ** 24 and tasks > waves  # grid stride
+
+
+def test_single_launch_rejects_bad_kind_and_size():
+    with pytest.raises(P.PairsError):
+        P.pairs_debug_single_launch(0, 10)
+    with pytest.raises(P.PairsError):
+        P.pairs_debug_single_launch(6, 10)
+    with pytest.raises(P.PairsError):
+        P.pairs_debug_single_launch(P.KIND_COUNT_I32, 2 ** 30 + 1)
+
+
+@pytest.mark.parametrize("n", [2 ** 27, 2 ** 27 + 1, 2 ** 30 - 1, 2 ** 30])
+@pytest.mark.parametrize("K,U", [(8, 1024), (1, 64)])
+def test_task_decode_at_the_size_limit(n, K, U):
+    """Row blocks at both ends and around the wrap of a set too large to list:
+    the chunks of each block tile its virtual partners [ra+1, rlast +
+    steps(rlast)] exactly, in 32-bit indices."""
+    rows = 64 * K
+    nblocks = -(-n // rows)
+    span = min(rows, n) - 1 + steps(n, 0)
+    nchunks = -(-span // U)
+    picks = sorted(set([0, 1, nblocks // 2 - 1, nblocks // 2, nblocks // 2 + 1, nblocks - 2,
+                        nblocks - 1]))
+    for b in picks:
+        if K == 1 and b not in (0, nblocks - 1):
+            continue   # 2^23 chunks per block at K = 1: the two ends suffice
+        t = P.pairs_debug_task_at(n, K, U, np.arange(b * nchunks, (b + 1) * nchunks))
+        ra = b * rows
+        rlast = min(ra + rows, n) - 1
+        uend = rlast + steps(n, rlast) + 1
+        assert np.all(t[:, 0] == ra)
+        live = t[t[:, 1] < t[:, 2]]
+        assert live[0, 1] == ra + 1 and live[-1, 2] == uend, (n, b)
+        assert np.all(live[1:, 1] == live[:-1, 2])         # contiguous, disjoint
+        assert np.all(live[:, 2] - live[:, 1] <= U)
+        assert int(t[:, 1:].max()) < 2 ** 31 and uend <= 2 * n
+    with pytest.raises(P.PairsError):
+        P.pairs_debug_task_at(n, K, U, [nblocks * nchunks])
