@@ -218,6 +218,26 @@ pairs_status_t pairs_count_i32_batched(const int32_t *x, const int32_t *y, const
                                        void *d_ws, size_t ws_bytes, unsigned flags,
                                        pairs_stream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * unplanned batched count above with no workspace argument.  Its workspace is
+ * a scratch array of 8 MiB in the library's own device memory, one per
+ * device, held until the process ends; the call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine), and nothing it uses
+ * needs clearing between calls.  Batches of more than PAIRS_NOALLOC_MAX_SETS
+ * sets return PAIRS_ERR_WORKSPACE with nothing enqueued.  Every call on a
+ * device shares that device's scratch: calls that overlap on one device (on
+ * different streams, or from different threads) race and give undefined
+ * counts; calls ordered on one stream are safe.  Arguments, flags and results
+ * are those of pairs_count_i32_batched.
+ */
+#define PAIRS_NOALLOC_MAX_SETS ((int64_t)250000)
+pairs_status_t pairs_count_i32_batched_noalloc(const int32_t *x, const int32_t *y,
+                                               const int32_t *z, const int32_t *r,
+                                               const int64_t *d_offsets, int64_t n_sets,
+                                               int64_t n_total, uint64_t *d_counts,
+                                               unsigned flags, pairs_stream_t stream);
 
 /* d_counts[s] = collision count of set s (the pairs_count_f32 predicate). */
 pairs_status_t pairs_count_f32_batched(const float *x, const float *y, const float *z,

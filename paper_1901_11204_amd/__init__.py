@@ -20,7 +20,8 @@ __all__ = [
     "pairs_count_i32", "pairs_count_f32", "pairs_energy_f32", "pairs_energy_f64",
     "pairs_force_f32",
     "pairs_batched_workspace_size", "pairs_count_i32_batched", "pairs_count_f32_batched",
-    "pairs_energy_f32_batched", "pairs_jitter_f32", "pairs_debug_task_ranges",
+    "pairs_energy_f32_batched", "pairs_count_i32_batched_noalloc", "NOALLOC_MAX_SETS",
+    "pairs_jitter_f32", "pairs_debug_task_ranges",
     "pairs_debug_step_ranges", "pairs_debug_single_launch", "pairs_debug_task_at", "FORM_BROADCAST", "FORM_STEPPING",
     "KIND_ENERGY_F64", "KIND_FORCE_F32",
     "Plan", "Graph", "ShapeTable", "pairs_get_shapes", "pairs_set_shapes",
@@ -41,6 +42,7 @@ LATTICE_LDS_BEADS = 4096
 LATTICE_MAX_BEADS = (1 << 24) - 1
 KIND_COUNT_I32, KIND_COUNT_F32, KIND_ENERGY_F32 = 1, 2, 3
 KIND_ENERGY_F64, KIND_FORCE_F32 = 4, 5  # pairs_debug_single_launch only
+NOALLOC_MAX_SETS = 250000
 
 _STATUS = {
     0: "ok", -1: "invalid argument", -2: "input outside the exact domain",
@@ -97,6 +99,7 @@ def _declare(L):
                                     _vp],
         "pairs_count_f32_batched": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _sz, _u32,
                                     _vp],
+        "pairs_count_i32_batched_noalloc": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _u32, _vp],
         "pairs_energy_f32_batched": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f32, _vp, _vp, _vp,
                                      _sz, _u32, _vp],
         "pairs_plan_create": [_int, _vp, _i64, ctypes.POINTER(_vp)],
@@ -294,6 +297,21 @@ def pairs_count_i32_batched(x, y, z, r, offsets, counts, ws=None, flags: int = 0
     _check(lib().pairs_count_i32_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(r), _ptr(offsets),
                                          n_sets, n_total, _ptr(counts), _ptr(ws), nbytes, flags,
                                          _stream(stream)), "pairs_count_i32_batched")
+
+
+def pairs_count_i32_batched_noalloc(x, y, z, r, offsets, counts, flags: int = 0,
+                                    stream=None) -> None:
+    """pairs_count_i32_batched with the library's static scratch as workspace:
+    allocates nothing (at most NOALLOC_MAX_SETS sets; calls overlapping on one
+    device race)."""
+    import torch
+    n_total, n_sets = _batch_checks(x, (x, y, z, r), torch.int32, offsets,
+                                    "pairs_count_i32_batched_noalloc")
+    _require((counts,), torch.int64, n_sets, "pairs_count_i32_batched_noalloc counts")
+    _check(lib().pairs_count_i32_batched_noalloc(_ptr(x), _ptr(y), _ptr(z), _ptr(r),
+                                                 _ptr(offsets), n_sets, n_total, _ptr(counts),
+                                                 flags, _stream(stream)),
+           "pairs_count_i32_batched_noalloc")
 
 
 def pairs_count_f32_batched(x, y, z, r, offsets, counts, ws=None, flags: int = 0,

@@ -1008,9 +1008,20 @@ pairs_status_t hip_fail(hipError_t e) {
 // takes the answer of a validation pass; word 16 takes bits nobody reads.
 __device__ __align__(256) int g_status_words[64];
 
-// Per-device state: the address of that device's status words and its CU count.
+// Scratch of pairs_count_i32_batched_noalloc: the workspace of an unplanned
+// batched call, in the library's own device memory (each device holds its
+// copy until the process ends).  Host code never passes the array's name to
+// a kernel or a copy: in host code it is a stand-in, not a device address.
+// The device address is looked up once per device (device_state) and used
+// instead.
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Per-device state: the addresses of that device's status words and scratch,
+// and its CU count.
 struct DeviceState {
     int *d_flag = nullptr;
+    void *d_scratch = nullptr;
     int n_cu = 0;
 };
 
@@ -1031,7 +1042,7 @@ pairs_status_t current_device(int *dev) {
 }
 
 // Looks the state up on first use on a device (with that device current):
-// the symbol's device address and an attribute query, neither of which
+// the symbols' device addresses and an attribute query, none of which
 // allocates.
 pairs_status_t device_state(DeviceState **st) {
     int dev;
@@ -1039,11 +1050,13 @@ pairs_status_t device_state(DeviceState **st) {
     std::lock_guard<std::mutex> lock(g_dev_mutex);
     DeviceState &d = g_dev[dev];
     if (!d.d_flag) {
-        void *flag = nullptr;
+        void *flag = nullptr, *scr = nullptr;
         PAIRS_HIP_CHECK(hipGetSymbolAddress(&flag, HIP_SYMBOL(g_status_words)));
+        PAIRS_HIP_CHECK(hipGetSymbolAddress(&scr, HIP_SYMBOL(scratch)));
         int ncu = 0;
         PAIRS_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         d.n_cu = ncu;
+        d.d_scratch = scr;
         d.d_flag = (int *)flag;
     }
     *st = &d;
@@ -1276,6 +1289,9 @@ pairs_status_t launch_scan(int kind, const BatchIO &io, const ScanSource &src,
 
 constexpr size_t batched_ws_bytes(int64_t n_sets) { return sched_layout(n_sets).total; }
 
+static_assert(batched_ws_bytes(PAIRS_NOALLOC_MAX_SETS) <= kScratchBytes,
+              "the no-allocation count's largest batch fits its scratch");
+
 pairs_status_t batched_common(int kind, const BatchIO &io, int64_t n_sets, void *ws,
                               size_t ws_bytes, hipStream_t s) {
     if (!ws || ws_bytes < batched_ws_bytes(n_sets)) return PAIRS_ERR_WORKSPACE;
@@ -1311,9 +1327,9 @@ pairs_status_t batched_args(const void *x, const void *y, const void *z,
     return PAIRS_OK;
 }
 
-// The unplanned batched count into a workspace of ws_bytes at ws; arguments
-// already checked.  The schedule kernel
-// writes every workspace word the scan kernel reads, so nothing needs
+// The unplanned batched count into a workspace of ws_bytes at ws (a caller's
+// or the library's scratch); arguments already checked.  The schedule
+// kernels write every workspace word the scan kernel reads, so nothing needs
 // clearing between calls.
 pairs_status_t count_i32_batched(const int32_t *x, const int32_t *y, const int32_t *z,
                                  const int32_t *r, const int64_t *d_offsets, int64_t n_sets,
@@ -1730,6 +1746,20 @@ pairs_status_t pairs_count_i32_batched(const int32_t *x, const int32_t *y, const
     PAIRS_TRY(current_device(&dev));
     return count_i32_batched(x, y, z, r, d_offsets, n_sets, n_total, d_counts, d_ws, ws_bytes,
                              flags, (hipStream_t)stream);
+}
+
+pairs_status_t pairs_count_i32_batched_noalloc(const int32_t *x, const int32_t *y,
+                                               const int32_t *z, const int32_t *r,
+                                               const int64_t *d_offsets, int64_t n_sets,
+                                               int64_t n_total, uint64_t *d_counts,
+                                               unsigned flags, pairs_stream_t stream) {
+    PAIRS_TRY(batched_args(x, y, z, d_offsets, n_sets, n_total, flags));
+    if ((n_sets > 0 && !d_counts) || (n_total > 0 && !r)) return PAIRS_ERR_INVALID_ARG;
+    if (n_sets > PAIRS_NOALLOC_MAX_SETS) return PAIRS_ERR_WORKSPACE;
+    DeviceState *st;
+    PAIRS_TRY(device_state(&st));  // the scratch's address on this device
+    return count_i32_batched(x, y, z, r, d_offsets, n_sets, n_total, d_counts, st->d_scratch,
+                             kScratchBytes, flags, (hipStream_t)stream);
 }
 
 pairs_status_t pairs_count_f32_batched(const float *x, const float *y, const float *z,

@@ -82,6 +82,17 @@ def test_batched_argument_errors_on_the_host():
     assert L.pairs_count_i32_batched(x, y, z, r, None, 10, 100, out, ws, need, 0,
                                      None) == INVALID
     assert L.pairs_count_i32_batched(x, y, z, r, off, -1, 100, out, ws, need, 0, None) == INVALID
+    # the no-allocation variant: its static scratch holds at most
+    # NOALLOC_MAX_SETS sets; more is refused on the host
+    lim = P.NOALLOC_MAX_SETS
+    assert L.pairs_count_i32_batched_noalloc(x, y, z, r, off, lim + 1, 100, out, 0,
+                                             None) == WORKSPACE
+    assert L.pairs_count_i32_batched_noalloc(x, y, z, r, None, 10, 100, out, 0,
+                                             None) == INVALID
+    assert L.pairs_count_i32_batched_noalloc(x, y, z, None, off, 10, 100, out, 0,
+                                             None) == INVALID
+    assert L.pairs_count_i32_batched_noalloc(x, y, z, r, off, 10, 100, None, 0,
+                                             None) == INVALID
     # energies: r and counts must be both given or both absent
     assert L.pairs_energy_f32_batched(x, y, z, r, off, 10, 100, 1e-4, out, None, ws, need, 0,
                                       None) == INVALID
