@@ -93,7 +93,7 @@ def boundary_candidates(table, c):
 
 
 def tune_batched(kind, offsets, inputs, outputs, eps2=1e-4, start=None, rounds=1, log=print,
-                 shapes=None, boundaries=True):
+                 shapes=None, boundaries=True, trace=None):
     """Coordinate descent over the (K, U, form) of each size class of a batch,
     largest class first, then over the class boundaries (min_n of every class
     but the last).  shapes: the (K, U, form) candidates (default: all)."""
@@ -109,6 +109,8 @@ def tune_batched(kind, offsets, inputs, outputs, eps2=1e-4, start=None, rounds=1
                 cand = list(table)
                 cand[c] = (table[c][0], k, u, form)
                 ms = time_batched(kind, cand, offsets, inputs, outputs, eps2)
+                if trace:
+                    trace(f"    class {c} K={k} U={u} form={form}: {ms:.3f} ms")
                 if ms < best:
                     best, table = ms, cand
                     log(f"  class {c} -> K={k} U={u} form={form}: {ms:.3f} ms")
@@ -118,6 +120,8 @@ def tune_batched(kind, offsets, inputs, outputs, eps2=1e-4, start=None, rounds=1
                     cand = list(table)
                     cand[c] = (lo,) + tuple(table[c][1:])
                     ms = time_batched(kind, cand, offsets, inputs, outputs, eps2)
+                    if trace:
+                        trace(f"    class {c} min_n={lo}: {ms:.3f} ms")
                     if ms < best:
                         best, table = ms, cand
                         log(f"  class {c} -> min_n={lo}: {ms:.3f} ms")
@@ -125,12 +129,15 @@ def tune_batched(kind, offsets, inputs, outputs, eps2=1e-4, start=None, rounds=1
     return table, best
 
 
-def tune_single(kind, n_values, make_call, start=None, log=print, rows=ROWS, chunks=CHUNKS):
+def tune_single(kind, n_values, make_call, start=None, log=print, rows=ROWS, chunks=CHUNKS,
+                trace=None):
     """For each size n (largest first) pick the (K, U) with the fastest
     single-set call; make_call(n) returns a zero-argument callable.  Returns
     the table and the best time of each size."""
     entries, times = [], []
     ns = sorted(n_values, reverse=True)
+    if not 1 <= len(ns) <= 4:
+        raise ValueError("tune_single takes 1 to 4 sizes, one per size class")
     for i, n in enumerate(ns):
         call = make_call(n)
         best = None
@@ -139,6 +146,8 @@ def tune_single(kind, n_values, make_call, start=None, log=print, rows=ROWS, chu
             for u in chunks:
                 pairs_set_shapes(kind, False, entries + [(lo, k, u)])
                 ms = _time(call)
+                if trace:
+                    trace(f"    n={n} K={k} U={u}: {ms:.3f} ms")
                 if best is None or ms < best[0]:
                     best = (ms, k, u)
         entries.append((lo, best[1], best[2]))
@@ -195,9 +204,12 @@ def main(argv=None):
                     default="binned-int32")
     ap.add_argument("--out", default=DEFAULT_CACHE)
     ap.add_argument("--rounds", type=int, default=1)
-    ap.add_argument("--sizes", default="1048576,262144,65536,16384,4096",
-                    help="single-set workloads: the set sizes tuned, one per class")
+    ap.add_argument("--sizes", default="1048576,262144,16384,4096",
+                    help="single-set workloads: the set sizes tuned, one per class (at most 4)")
+    ap.add_argument("--verbose", action="store_true", help="print every candidate's time")
     a = ap.parse_args(argv)
+    say = lambda *m: print(*m, flush=True)
+    trace = say if a.verbose else None
     dev = torch.device("cuda", 0)
     if a.workload.startswith("single"):
         from . import count_i32, energy_f32
@@ -215,7 +227,7 @@ def main(argv=None):
             def make_call(n):
                 t = [torch.from_numpy(v).to(dev) for v in w.particles_f32(n, 4).arrays()]
                 return lambda: energy_f32(*t)
-        table, times = tune_single(kind, ns, make_call, log=lambda *m: print(*m, flush=True))
+        table, times = tune_single(kind, ns, make_call, log=say, trace=trace)
         save_cache(a.out, kind, False, table, note + f"; sizes {ns}", times)
         print(json.dumps({"kind": KIND_NAMES[kind], "table": table, "ms": times}), flush=True)
         return 0
@@ -230,8 +242,7 @@ def main(argv=None):
         outs = (torch.empty(b.n_sets, dtype=torch.float64, device=dev),
                 torch.empty(b.n_sets, dtype=torch.int64, device=dev))
         kind, note = KIND_ENERGY_F32, "50000 float32 sets, lognormal(5,1) sizes, seed 6, r=0.01"
-    table, ms = tune_batched(kind, b.offsets, ins, outs, rounds=a.rounds,
-                             log=lambda *m: print(*m, flush=True))
+    table, ms = tune_batched(kind, b.offsets, ins, outs, rounds=a.rounds, log=say, trace=trace)
     save_cache(a.out, kind, True, table, note, ms)
     print(json.dumps({"kind": KIND_NAMES[kind], "table": table, "ms": ms}), flush=True)
     return 0

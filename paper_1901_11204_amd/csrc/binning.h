@@ -338,23 +338,37 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 // ------------------------------------------------------------- work items --
 //
 // Tasks of an item: a cell's own pairs are the balanced assignment of its na
-// objects (band.h) tiled into row blocks of 64 kItemRows rows and chunks of
+// objects (band.h) tiled into row blocks of 64 K rows and chunks of
 // kItemChunk virtual partners; the pairs between two ranges are a rectangle
-// of row blocks of A against chunks of kItemChunk objects of B.
-constexpr int kItemRows = 4;
+// of row blocks of A against chunks of kItemChunk objects of B.  K (rows per
+// lane, 1, 2 or 4) follows the item's na, so that a row block of a
+// 100-object cell does not leave half of 256 lanes' rows empty.
 constexpr int kItemChunk = 512;
 
+__host__ __device__ inline int item_rows(uint32_t na) { return na <= 64 ? 1 : na <= 128 ? 2 : 4; }
+
 __device__ __forceinline__ int64_t item_tasks(const Item &it) {
-    if (it.a0 == it.b0) return Tiling::of(Band::of((int)it.na), kItemRows, kItemChunk).tasks();
-    return (int64_t)((it.na + 64 * kItemRows - 1) / (64 * kItemRows)) *
-           ((it.nb + kItemChunk - 1) / kItemChunk);
+    const int K = item_rows(it.na);
+    if (it.a0 == it.b0) return Tiling::of(Band::of((int)it.na), K, kItemChunk).tasks();
+    return (int64_t)((it.na + 64 * K - 1) / (64 * K)) * ((it.nb + kItemChunk - 1) / kItemChunk);
 }
 
-// One block: exclusive prefix of the items' task counts, pre[k] for
-// k = 0 .. items (pre[items] = all tasks).
+// The items' task range, as the unplanned batched schedule lays out sets: pre[k]
+// is the first task of item k (pre[m] = T), and a bucket table tab[q] names
+// the item holding task q B, with B = ceil(T / m), so a wave finds a task's
+// item with one table read and a search over at most B + 1 entries of pre.
+struct ItemSched {
+    int64_t m;         // items
+    int64_t T;         // tasks in all
+    int64_t B;         // tasks per bucket
+    int64_t nbuckets;  // ceil(T / B)
+};
+
+// One block: the exclusive prefix of the items' task counts and the header.
 constexpr int kScanThreads = 1024;
 __global__ __launch_bounds__(kScanThreads) void k_bin_item_scan(ItemList L,
-                                                               int64_t *__restrict__ pre) {
+                                                               int64_t *__restrict__ pre,
+                                                               ItemSched *__restrict__ hdr) {
     __shared__ int64_t part[kScanThreads];
     const int tid = threadIdx.x;
     const Item *items = L.items;
@@ -373,6 +387,11 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_item_scan(ItemList L,
             run += v;
         }
         pre[m] = run;
+        const int64_t B = m > 0 ? max((int64_t)1, (run + m - 1) / m) : 1;
+        hdr->m = m;
+        hdr->T = run;
+        hdr->B = B;
+        hdr->nbuckets = (run + B - 1) / B;
     }
     __syncthreads();
     int64_t run = part[tid];
@@ -382,96 +401,134 @@ __global__ __launch_bounds__(kScanThreads) void k_bin_item_scan(ItemList L,
     }
 }
 
-// The tasks of all items, taken by the waves with a grid stride.  Rows are
-// held as in the pairs_count_i32 kernels (RowI32, kItemRows per lane); each
-// group of 64 partners is staged in LDS and read back as broadcasts.  The
-// binned domain (coordinates within 2^24) lies inside the box of the plain
-// 64-bit Gram test.  Padding rows (nq = -2^62) and padding partners
-// (q = INT64_MAX) never hit.
+// The bucket table: tab[q] = the item holding task q B; tab[nbuckets] = m - 1.
+__global__ void k_bin_item_tab(const int64_t *__restrict__ pre,
+                               const ItemSched *__restrict__ hdr, int32_t *__restrict__ tab) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nbk = hdr->nbuckets, m = hdr->m;
+    if (q > nbk) return;
+    if (q == nbk) {
+        tab[q] = (int32_t)max((int64_t)0, m - 1);
+        return;
+    }
+    const int64_t t = q * hdr->B;
+    int64_t lo = 0, hi = m;  // pre[lo] <= t < pre[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= t) lo = mid; else hi = mid;
+    }
+    tab[q] = (int32_t)lo;
+}
+
+// One task of an item with K rows per lane: rows [ra, ra + 64 K) of A held as
+// in the pairs_count_i32 kernels (RowI32), partners u in [u0, u1) staged 64
+// at a time in LDS and read back as broadcasts.  The binned domain
+// (coordinates within 2^24) lies inside the box of the plain 64-bit Gram
+// test.  Padding rows (nq = -2^62) and padding partners (q = INT64_MAX) never
+// hit.
+template <int K>
+__device__ __forceinline__ uint32_t item_task(const int4 *__restrict__ so, const Item &it,
+                                              int64_t local, pairs_dev::PartnerI32 *wp,
+                                              int64_t *wq) {
+    using namespace pairs_dev;
+    const int lane = lane_id();
+    const bool self = it.a0 == it.b0;
+    const Band band = Band::of((int)it.na);
+    int ra, u0, u1;
+    if (self) {
+        task_at(band, Tiling::of(band, K, kItemChunk), local, &ra, &u0, &u1);
+    } else {
+        const int64_t nch = (it.nb + kItemChunk - 1) / kItemChunk;
+        ra = (int)(local / nch) * 64 * K;
+        u0 = (int)(local % nch) * kItemChunk;
+        u1 = min(u0 + kItemChunk, (int)it.nb);
+    }
+    RowI32 rows[K];
+    int row[K], nsteps[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = ra + kWave * k + lane;
+        row[k] = i;
+        nsteps[k] = 0;
+        rows[k].ax = rows[k].ay = rows[k].az = rows[k].ar = 0;
+        rows[k].nq = -((int64_t)1 << 62);
+        if (i < (int)it.na) {
+            const int4 o = so[it.a0 + i];
+            rows[k] = gram_row(o.x, o.y, o.z, o.w);
+            nsteps[k] = self ? band.steps(i) : 0;
+        }
+    }
+    uint32_t cnt = 0;
+    for (int g0 = u0; g0 < u1; g0 += kWave) {
+        const int u = g0 + lane;
+        if (u < u1) {
+            const uint32_t j = self ? it.a0 + (uint32_t)(u >= (int)it.na ? u - (int)it.na : u)
+                                    : it.b0 + (uint32_t)u;
+            const int4 o = so[j];
+            wp[lane] = PartnerI32{o.x, o.y, o.z, o.w};
+            wq[lane] = gram_q(o.x, o.y, o.z, o.w);
+        } else {
+            wp[lane] = PartnerI32{0, 0, 0, 0};
+            wq[lane] = INT64_MAX;
+        }
+        wave_sync();
+        const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
+        if (self) {
+            for (int q = 0; q < gn; ++q) {
+                const PartnerI32 b = wp[q];
+                const int64_t qb = wq[q];
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    cnt += count_bits_both(gram_hit(rows[k], b, qb),
+                                           owns(g0 + q, row[k], nsteps[k]));
+            }
+        } else {
+            for (int q = 0; q < gn; ++q) {
+                const PartnerI32 b = wp[q];
+                const int64_t qb = wq[q];
+#pragma unroll
+                for (int k = 0; k < K; ++k) cnt += count_bits(gram_hit(rows[k], b, qb));
+            }
+        }
+        wave_sync();
+    }
+    return cnt;
+}
+
+// The tasks of all items, taken by the waves with a grid stride.
 __global__ __launch_bounds__(kBlock) void k_bin_count_items(const int4 *__restrict__ so,
                                                             ItemList L,
                                                             const int64_t *__restrict__ pre,
+                                                            const int32_t *__restrict__ tab,
+                                                            const ItemSched *__restrict__ hdr,
                                                             uint64_t *count) {
     using namespace pairs_dev;
-    constexpr int K = kItemRows;
     __shared__ PartnerI32 wp_all[kBlock / kWave][kWave];
     __shared__ int64_t wq_all[kBlock / kWave][kWave];
-    const int wave = wave_id(), lane = lane_id();
+    const int wave = wave_id();
     PartnerI32 *wp = wp_all[wave];
     int64_t *wq = wq_all[wave];
-    const Item *items = L.items;
-    const int64_t m = item_count(L), total = pre[m];
+    const int64_t total = hdr->T, B = hdr->B;
     const int64_t stride = (int64_t)gridDim.x * (kBlock / kWave);
+    uint64_t cnt = 0;
     for (int64_t t = (int64_t)blockIdx.x * (kBlock / kWave) + wave; t < total; t += stride) {
-        int64_t lo = 0, hi = m;  // pre[lo] <= t < pre[hi]
+        const int64_t b = t / B;
+        int64_t lo = tab[b], hi = (int64_t)tab[b + 1] + 1;  // pre[lo] <= t < pre[hi]
         while (hi - lo > 1) {
             const int64_t mid = (lo + hi) >> 1;
             if (pre[mid] <= t) lo = mid; else hi = mid;
         }
-        const Item it = items[lo];
+        const Item it = L.items[lo];
         const int64_t local = t - pre[lo];
-        const bool self = it.a0 == it.b0;
-        const Band band = Band::of((int)it.na);
-        int ra, u0, u1;
-        if (self) {
-            task_at(band, Tiling::of(band, K, kItemChunk), local, &ra, &u0, &u1);
-        } else {
-            const int64_t nch = (it.nb + kItemChunk - 1) / kItemChunk;
-            ra = (int)(local / nch) * 64 * K;
-            u0 = (int)(local % nch) * kItemChunk;
-            u1 = min(u0 + kItemChunk, (int)it.nb);
-        }
-        RowI32 rows[K];
-        int row[K], nsteps[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = ra + kWave * k + lane;
-            row[k] = i;
-            nsteps[k] = 0;
-            rows[k].ax = rows[k].ay = rows[k].az = rows[k].ar = 0;
-            rows[k].nq = -((int64_t)1 << 62);
-            if (i < (int)it.na) {
-                const int4 o = so[it.a0 + i];
-                rows[k] = gram_row(o.x, o.y, o.z, o.w);
-                nsteps[k] = self ? band.steps(i) : 0;
-            }
-        }
-        uint32_t cnt = 0;
-        for (int g0 = u0; g0 < u1; g0 += kWave) {
-            const int u = g0 + lane;
-            if (u < u1) {
-                const uint32_t j = self ? it.a0 + (uint32_t)(u >= (int)it.na ? u - (int)it.na : u)
-                                        : it.b0 + (uint32_t)u;
-                const int4 o = so[j];
-                wp[lane] = PartnerI32{o.x, o.y, o.z, o.w};
-                wq[lane] = gram_q(o.x, o.y, o.z, o.w);
-            } else {
-                wp[lane] = PartnerI32{0, 0, 0, 0};
-                wq[lane] = INT64_MAX;
-            }
-            wave_sync();
-            const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
-            if (self) {
-                for (int q = 0; q < gn; ++q) {
-                    const PartnerI32 b = wp[q];
-                    const int64_t qb = wq[q];
-#pragma unroll
-                    for (int k = 0; k < K; ++k)
-                        cnt += count_bits_both(gram_hit(rows[k], b, qb),
-                                               owns(g0 + q, row[k], nsteps[k]));
-                }
-            } else {
-                for (int q = 0; q < gn; ++q) {
-                    const PartnerI32 b = wp[q];
-                    const int64_t qb = wq[q];
-#pragma unroll
-                    for (int k = 0; k < K; ++k) cnt += count_bits(gram_hit(rows[k], b, qb));
-                }
-            }
-            wave_sync();
-        }
-        if (lane == 0 && cnt) atomicAdd((unsigned long long *)count, (unsigned long long)cnt);
+        const int K = item_rows(it.na);
+        if (K == 1)
+            cnt += item_task<1>(so, it, local, wp, wq);
+        else if (K == 2)
+            cnt += item_task<2>(so, it, local, wp, wq);
+        else
+            cnt += item_task<4>(so, it, local, wp, wq);
     }
+    if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)count, (unsigned long long)cnt);
 }
 
 // Ranges of 32-bit words that the pipeline needs zeroed, cleared by one

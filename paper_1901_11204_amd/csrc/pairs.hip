@@ -1352,7 +1352,7 @@ namespace bin = pairs_binning;
 // Workspace layout of a binned count of n objects.
 struct BinnedLayout {
     size_t keys_in, keys_out, idx_in, idx_out, so, ukeys, sizes, off, runs, temp;
-    size_t htags, hkeys, hvals, hcnt, items, item_pre, item_n;
+    size_t htags, hkeys, hvals, hcnt, items, item_pre, item_tab, item_hdr, item_n;
     size_t temp_bytes, total;
     int blog;  // cell table of 2^blog buckets of 8 slots, at least 2n slots
 };
@@ -1425,6 +1425,8 @@ pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
     const size_t cap = (size_t)bin::item_capacity(n);
     L->items = take(sizeof(bin::Item) * cap);
     L->item_pre = take(8 * (cap + 1));
+    L->item_tab = take(4 * (cap + 2));
+    L->item_hdr = take(sizeof(bin::ItemSched));
     L->item_n = take(8);
     L->temp_bytes = std::max(t1, std::max(t2, t3));
     L->temp = take(L->temp_bytes);
@@ -2355,6 +2357,8 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
     const bin::ItemList items{(bin::Item *)(w + L.items), item_n,
                               (uint32_t)bin::item_capacity(n)};
     int64_t *item_pre = (int64_t *)(w + L.item_pre);
+    int32_t *item_tab = (int32_t *)(w + L.item_tab);
+    bin::ItemSched *item_hdr = (bin::ItemSched *)(w + L.item_hdr);
     const int64_t buckets = int64_t(1) << L.blog;
     bin::ClearRanges cr = {{(uint32_t *)d_count, sizes, (uint32_t *)htags, hcnt, item_n},
                            {2, n + 1, buckets * bin::kSlots / 4, buckets, 1}};
@@ -2378,11 +2382,14 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
     const int64_t blocks = std::min<int64_t>((n + 15) / 16, (int64_t)st->n_cu * 16);
     bin::k_bin_count<<<(unsigned)blocks, bin::kBlock, 0, s>>>(
         so, ukeys, off, runs, (const uint64_t *)htags, hkeys, hvals, L.blog, fb, items, d_count);
-    bin::k_bin_item_scan<<<1, bin::kScanThreads, 0, s>>>(items, item_pre);
+    bin::k_bin_item_scan<<<1, bin::kScanThreads, 0, s>>>(items, item_pre, item_hdr);
+    // at most cap buckets and the sentinel
+    bin::k_bin_item_tab<<<blocks_for(bin::item_capacity(n) + 1, 256), 256, 0, s>>>(
+        item_pre, item_hdr, item_tab);
     const int64_t item_blocks = std::min<int64_t>(n / (4 * bin::kBigCell) + 1,
                                                   (int64_t)st->n_cu * 8);
-    bin::k_bin_count_items<<<(unsigned)item_blocks, bin::kBlock, 0, s>>>(so, items, item_pre,
-                                                                       d_count);
+    bin::k_bin_count_items<<<(unsigned)item_blocks, bin::kBlock, 0, s>>>(
+        so, items, item_pre, item_tab, item_hdr, d_count);
     PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;
 }

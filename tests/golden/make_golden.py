@@ -25,6 +25,9 @@ import workloads as w  # noqa: E402
 
 OUT = os.path.join(HERE, "config_values.json")
 FORCE_ROWS = [0, 1, 4096, 65535, 131072, 200000, 262142, 262143]
+# config 3 per-particle energies: both ends, around n/2, and 56 seeded rows
+ENERGY_ROWS = sorted(set([0, 1, 131071, 131072, 262142, 262143] +
+                         np.random.default_rng(33).integers(0, 2 ** 18, 58).tolist()))
 
 
 def compute(key, threads):
@@ -42,6 +45,31 @@ def compute(key, threads):
         return {"total": int(c.sum()),
                 "sha256_le_u64": hashlib.sha256(c.astype("<u8").tobytes()).hexdigest(),
                 "first16": [int(v) for v in c[:16]]}
+    if key == "config3_energy_rows":
+        rows = np.array(ENERGY_ROWS, np.int64)
+        E = oracle.energy_rows(*w.config3().arrays(), np.float32(1e-4), rows=rows,
+                               threads=threads)
+        return {"rows": ENERGY_ROWS, "E": E.tolist()}
+    if key == "config5_sampled_sets":
+        # 24 seeded sets of config 5, jittered by the oracle through 100 steps
+        # (seed 6, sigma 1e-3); per-set energy and pinned-float32 count after
+        # steps 0, 49 and 99
+        b = w.config5()
+        x, y, z, r = b.objs.arrays()
+        sets = sorted(np.random.default_rng(55).choice(b.n_sets, 24, replace=False).tolist())
+        out = {"sets": sets, "steps": [0, 49, 99], "energy": [], "count": []}
+        for st in sets:
+            a, e = int(b.offsets[st]), int(b.offsets[st + 1])
+            px, py, pz = x[a:e].copy(), y[a:e].copy(), z[a:e].copy()
+            en, cn = [], []
+            for k in range(100):
+                px, py, pz = oracle.jitter_f32(px, py, pz, 6, k, 1e-3, first_index=a)
+                if k in (0, 49, 99):
+                    en.append(oracle.energy_total(px, py, pz, np.float32(1e-4), threads=threads))
+                    cn.append(oracle.count_f32(px, py, pz, r[a:e], threads=threads))
+            out["energy"].append(en)
+            out["count"].append(cn)
+        return out
     if key == "config3_force_rows":
         rows = np.array(FORCE_ROWS, np.int64)
         F, S = oracle.force_rows(*w.config3().arrays(), np.float32(1e-4), rows=rows,
@@ -60,7 +88,8 @@ def compute(key, threads):
 
 KEYS = ["config1_count", "config4_counts", "config3_energy_total", "config2_odd_count",
         "config2_even_count", "lattice_paper_counts", "lattice_large_counts",
-        "config3_force_rows", "lattice_short_counts"]
+        "config3_force_rows", "lattice_short_counts", "config3_energy_rows",
+        "config5_sampled_sets"]
 
 
 def main():
