@@ -84,6 +84,53 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+class SclkSampler:
+    """Mean engine clock (MHz) while a region runs, read every few ms from the
+    amdgpu driver's sysfs table (the current level is the one marked '*');
+    None where the box does not expose it."""
+
+    def __init__(self, period_s=0.002):
+        import glob
+        self.paths = [q for q in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
+                      if os.access(q, os.R_OK)]
+        self.period = period_s
+        self.samples = []
+
+    def _read(self):
+        for q in self.paths:
+            try:
+                for line in open(q).read().splitlines():
+                    if line.strip().endswith("*"):
+                        return float(line.split(":")[1].strip().rstrip("*").strip().lower()
+                                     .replace("mhz", ""))
+            except (OSError, ValueError, IndexError):
+                continue
+        return None
+
+    def __enter__(self):
+        import threading
+        self.stop = threading.Event()
+
+        def run():
+            while not self.stop.is_set():
+                v = self._read()
+                if v is not None:
+                    self.samples.append(v)
+                time.sleep(self.period)
+        self.thread = threading.Thread(target=run, daemon=True)
+        if self.paths:
+            self.thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self.stop.set()
+        if self.paths:
+            self.thread.join()
+
+    def mean_mhz(self):
+        return sum(self.samples) / len(self.samples) if self.samples else None
+
+
 def timed_steps(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -335,7 +382,25 @@ def bench_batched(P, w, torch, np, dev, steps):
     ms, _ = timed_steps(lambda: P.pairs_count_i32_batched(x, y, z, r, toff, counts, ws),
                         max(5, steps), 2)
     m = float(np.mean(ms))
-    out["count_i32_binned_200k_sets_unplanned"] = {"ms": m, "G_pairs_per_s": pairs / m / 1e6}
+    # the same objects counted as one set through the binned path: cells of
+    # 2^14 are the sets' own grid cells (up to 8192 objects, so big cells and
+    # their neighbours go through the work items), cells of 1024 are about
+    # twice the largest radius
+    n4 = b.n_total
+    wsb = torch.empty(P.pairs_binned_workspace_size(n4), dtype=torch.uint8, device=dev)
+    outb = torch.empty(1, dtype=torch.int64, device=dev)
+    for cell in (1 << 14, 1024):
+        log(f"[bench] binned count of the {n4} objects as one set, cells of {cell}")
+        msb, _ = timed_steps(lambda: P.pairs_count_i32_binned(x, y, z, r, cell, outb, wsb), 3, 1)
+        out[f"count_i32_binned_one_set_cell{cell}"] = {
+            "workload": f"config 4's {n4} objects as one set, cells of {cell}",
+            "ms": float(np.median(msb)), "count": int(outb.item())}
+    del wsb
+    out["count_i32_binned_200k_sets_unplanned"] = {
+        "ms": m, "G_pairs_per_s": pairs / m / 1e6,
+        "valu_frac": pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK,
+        "matches_oracle": hashlib.sha256(counts.cpu().numpy().astype("<u8").tobytes()).hexdigest()
+                          == golden()["config4_counts"]["sha256_le_u64"]}
     plan.close()
     del x, y, z, r, ws
 
@@ -353,12 +418,29 @@ def bench_batched(P, w, torch, np, dev, steps):
     ms, _ = timed_steps(lambda: g.launch(), 3, 1)
     m = float(np.mean(ms)) / nsteps
     ms_j, _ = timed_steps(lambda: P.pairs_jitter_f32(x, y, z, 6, 0, 1e-3), 20, 2)
+    # one more replay from the initial positions, checked on sampled sets at
+    # steps 0, 49 and 99 against the oracle's stored values
+    for t, v in zip((x, y, z), b5.objs.arrays()[:3]):
+        t.copy_(torch.from_numpy(v).to(dev))
+    g.launch()
+    torch.cuda.synchronize()
+    g5 = golden()["config5_sampled_sets"]
+    En, Cn = E.cpu().numpy(), C.cpu().numpy()
+    errs, exact = [], True
+    for i, st in enumerate(g5["sets"]):
+        for j, k in enumerate(g5["steps"]):
+            want = g5["energy"][i][j]
+            errs.append(abs(En[k * b5.n_sets + st] - want) / want)
+            exact = exact and int(Cn[k * b5.n_sets + st]) == g5["count"][i][j]
     out["energy_count_f32_graph_100_steps"] = {
         "workload": "50000 sets, sizes lognormal(5,1) clipped to [2,4096], seed 6; "
                     "per step: jitter + per-set energy and pinned-fp32 count (r=0.01)",
         "pair_tests_per_step": pairs5, "ms_per_step": m, "G_pairs_per_s": pairs5 / m / 1e6,
         "valu_frac": pairs5 / (m * 1e-3) * C_ALG["energy_count_f32"] / VALU_PEAK,
-        "jitter_ms": float(np.mean(ms_j))}
+        "jitter_ms": float(np.mean(ms_j)),
+        "max_rel_err_per_set_energy_vs_fp64_oracle": float(max(errs)),
+        "counts_match_oracle": exact,
+        "sampled": f"{len(g5['sets'])} sets at steps {g5['steps']}"}
     g.close()
     plan5.close()
     return out
@@ -375,12 +457,13 @@ def bench_binned(P, torch, np, dev, xyzr, steps, ms_all_pairs=None):
     # algorithmic HBM bytes per object: read 16 B of input and write 28 B
     # of key, index and record; the histogram reads the 8 B keys; four
     # 10-bit radix passes over the 33 key bits read and write 12 B each;
-    # the gather reads 4 + 16 B and writes 16 B; run-length encoding
-    # reads 8 B and writes 12 B and the scan reads and writes 4 B; the
-    # table reads 16 B and writes 17 B per cell (about one per object
-    # here); the count reads the 16 B records
-    bpo = 16 + 28 + 8 + 4 * 24 + 36 + 20 + 8 + 33 + 16
+    # the gather reads 4 + 16 B and writes the 16 B record and its 8 B q;
+    # run-length encoding reads 8 B and writes 12 B and the scan reads and
+    # writes 4 B; the table reads 16 B and writes 17 B per cell (about one
+    # per object here); the count reads the 16 B records
+    bpo = 16 + 28 + 8 + 4 * 24 + 44 + 20 + 8 + 33 + 16
     res = {"ms": mb, "cell": 1 << 15, "count": int(outb.item()),
+           "workspace_bytes_per_object": wsb.numel() / n,
            "matches_oracle": int(outb.item()) == golden()["config2_even_count"],
            "roofline": {"bound": "hbm", "achieved": n * bpo / (mb * 1e-3) / 1e9,
                         "peak": HBM_PEAK / 1e9, "unit": "GB/s",
@@ -455,8 +538,10 @@ def main():
     out = torch.empty(1, dtype=torch.int64, device=dev)
     pairs = n * (n - 1) // 2
     log(f"[bench] count_i32 N={n}: {a.warmup} warmup + {a.steps} timed steps")
-    ms, wall = timed_steps(lambda: P.pairs_count_i32(x, y, z, r, out), a.steps, a.warmup)
+    with SclkSampler() as sclk:
+        ms, wall = timed_steps(lambda: P.pairs_count_i32(x, y, z, r, out), a.steps, a.warmup)
     ms_step = float(np.mean(ms))
+    sclk_mhz = sclk.mean_mhz()
     value = pairs / (ms_step * 1e-3) / 1e9
     achieved = pairs / (ms_step * 1e-3) * C_ALG["count_i32"]
     count = int(out.item())
@@ -491,7 +576,13 @@ def main():
                      "unit": "T VALU lane-op/s", "frac": achieved / VALU_PEAK,
                      "traffic": recorded_traffic(),
                      "per_pair_ops": C_ALG["count_i32"],
-                     "plain_definition_frac": pairs / (ms_step * 1e-3) * PLAIN_DEF_OPS / VALU_PEAK},
+                     "plain_definition_frac": pairs / (ms_step * 1e-3) * PLAIN_DEF_OPS / VALU_PEAK,
+                     "sclk_mhz_measured": sclk_mhz,
+                     "frac_at_measured_sclk": (achieved / (N_CU * VALU_LANES_PER_CU *
+                                                           sclk_mhz * 1e6)
+                                               if sclk_mhz else None),
+                     "sclk_source": ("amdgpu sysfs pp_dpm_sclk, sampled during the timed steps"
+                                     if sclk_mhz else "not exposed on this box")},
     }
 
     if not a.no_secondary:
@@ -524,12 +615,18 @@ def main():
         log(f"[bench] energy_f32 N={n3}")
         ms3, _ = timed_steps(lambda: P.pairs_energy_f32(*t3, 1e-4, E, tot), max(3, a.steps // 2), 1)
         m3 = float(np.mean(ms3))
+        ge = golden()["config3_energy_rows"]
+        got_rows = E[torch.tensor(ge["rows"], device=dev)].cpu().numpy()
+        want_rows = np.array(ge["E"])
         sec["energy_f32_2^18"] = {"ms": m3, "G_pairs_per_s": pp3 / m3 / 1e6,
                                   "valu_frac": pp3 / (m3 * 1e-3) * C_ALG["energy_f32"] / VALU_PEAK,
                                   "total": float(tot.item()),
                                   "rel_err_total_vs_fp64_oracle":
                                       abs(float(tot.item()) - golden()["config3_energy_total"])
-                                      / golden()["config3_energy_total"]}
+                                      / golden()["config3_energy_total"],
+                                  "max_rel_err_per_particle_vs_fp64_oracle":
+                                      float(np.max(np.abs(got_rows - want_rows) / want_rows)),
+                                  "sampled_particles": len(ge["rows"])}
         ms3b, _ = timed_steps(lambda: P.pairs_energy_f32(*t3, 1e-4, None, tot), max(3, a.steps // 2), 1)
         m3b = float(np.mean(ms3b))
         sec["energy_f32_2^18_total_only"] = {"ms": m3b, "G_pairs_per_s": pp3 / m3b / 1e6}

@@ -259,6 +259,37 @@ pairs_status_t pairs_energy_f32_batched(const float *x, const float *y, const fl
 
 /* ----------------------------------------------------------------- plans -- */
 /*
+ * Forces of the softened potential (pairs_force_f32) within every set of a
+ * CSR batch, on the balanced assignment of each set (Section 4: any
+ * symmetric pairwise interaction; each pair evaluated once, added to one
+ * object and subtracted from the other): d_fx, d_fy, d_fz (double[n_total])
+ * receive, for every object, the sum over the other objects of its own set.
+ * Offsets, workspace (pairs_batched_workspace_size) and validation as for
+ * the batched counts; eps2 > 0; inputs finite.  PAIRS_FLAG_DETERMINISTIC
+ * reduces the components in fixed point, with one scale for all objects
+ * (the bound of the largest possible set).
+ */
+pairs_status_t pairs_force_f32_batched(const float *x, const float *y, const float *z,
+                                       const int64_t *d_offsets, int64_t n_sets,
+                                       int64_t n_total, float eps2, double *d_fx, double *d_fy,
+                                       double *d_fz, void *d_ws, size_t ws_bytes, unsigned flags,
+                                       pairs_stream_t stream);
+
+/*
+ * The potential in double precision (pairs_energy_f64) within every set of a
+ * CSR batch: d_set_energy[s] = the sum over pairs of set s (double[n_sets]);
+ * d_energy (double[n_total] or NULL) = each object's sum over the other
+ * objects of its set.  Offsets, workspace and validation as for the batched
+ * counts; eps2 > 0.  PAIRS_FLAG_DETERMINISTIC as for pairs_energy_f32_batched
+ * (per-set scales for the set totals, one scale for the per-object sums).
+ */
+pairs_status_t pairs_energy_f64_batched(const double *x, const double *y, const double *z,
+                                        const int64_t *d_offsets, int64_t n_sets,
+                                        int64_t n_total, double eps2, double *d_set_energy,
+                                        double *d_energy, void *d_ws, size_t ws_bytes,
+                                        unsigned flags, pairs_stream_t stream);
+
+/*
  * A plan fixes the set sizes of a batch (h_offsets: HOST int64[n_sets + 1],
  * same rules as above, checked on the host) and precomputes its schedule: a
  * task table ordered so that the tasks of the largest sets run first.  The

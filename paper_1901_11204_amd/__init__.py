@@ -21,6 +21,7 @@ __all__ = [
     "pairs_force_f32",
     "pairs_batched_workspace_size", "pairs_count_i32_batched", "pairs_count_f32_batched",
     "pairs_energy_f32_batched", "pairs_count_i32_batched_noalloc", "NOALLOC_MAX_SETS",
+    "pairs_force_f32_batched", "pairs_energy_f64_batched",
     "pairs_jitter_f32", "pairs_debug_task_ranges",
     "pairs_debug_step_ranges", "pairs_debug_single_launch", "pairs_debug_task_at", "FORM_BROADCAST", "FORM_STEPPING",
     "KIND_ENERGY_F64", "KIND_FORCE_F32",
@@ -100,6 +101,10 @@ def _declare(L):
         "pairs_count_f32_batched": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _vp, _sz, _u32,
                                     _vp],
         "pairs_count_i32_batched_noalloc": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _u32, _vp],
+        "pairs_force_f32_batched": [_vp, _vp, _vp, _vp, _i64, _i64, _f32, _vp, _vp, _vp, _vp, _sz,
+                                    _u32, _vp],
+        "pairs_energy_f64_batched": [_vp, _vp, _vp, _vp, _i64, _i64, ctypes.c_double, _vp, _vp,
+                                     _vp, _sz, _u32, _vp],
         "pairs_energy_f32_batched": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _f32, _vp, _vp, _vp,
                                      _sz, _u32, _vp],
         "pairs_plan_create": [_int, _vp, _i64, ctypes.POINTER(_vp)],
@@ -342,6 +347,37 @@ def pairs_energy_f32_batched(x, y, z, r, offsets, eps2, energy, counts=None, ws=
                                           n_sets, n_total, float(eps2), _ptr(energy),
                                           _ptr(counts), _ptr(ws), nbytes, flags,
                                           _stream(stream)), "pairs_energy_f32_batched")
+
+
+def pairs_force_f32_batched(x, y, z, offsets, eps2, fx, fy, fz, ws=None, flags: int = 0,
+                            stream=None) -> None:
+    """Forces within every set of a CSR batch into float64[n_total] tensors."""
+    import torch
+    n_total, n_sets = _batch_checks(x, (x, y, z), torch.float32, offsets,
+                                    "pairs_force_f32_batched")
+    _require((fx, fy, fz), torch.float64, n_total, "pairs_force_f32_batched forces")
+    ws, nbytes = _workspace(ws, n_sets, n_total, x.device)
+    _check(lib().pairs_force_f32_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(offsets), n_sets,
+                                         n_total, float(eps2), _ptr(fx), _ptr(fy), _ptr(fz),
+                                         _ptr(ws), nbytes, flags, _stream(stream)),
+           "pairs_force_f32_batched")
+
+
+def pairs_energy_f64_batched(x, y, z, offsets, eps2, set_energy, energy=None, ws=None,
+                             flags: int = 0, stream=None) -> None:
+    """Double-precision potential per set (float64[n_sets]) and, if energy is
+    given, per object (float64[n_total]), for float64 inputs."""
+    import torch
+    n_total, n_sets = _batch_checks(x, (x, y, z), torch.float64, offsets,
+                                    "pairs_energy_f64_batched")
+    _require((set_energy,), torch.float64, n_sets, "pairs_energy_f64_batched set_energy")
+    if energy is not None:
+        _require((energy,), torch.float64, n_total, "pairs_energy_f64_batched energy")
+    ws, nbytes = _workspace(ws, n_sets, n_total, x.device)
+    _check(lib().pairs_energy_f64_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(offsets), n_sets,
+                                          n_total, float(eps2), _ptr(set_energy),
+                                          _ptr(energy), _ptr(ws), nbytes, flags,
+                                          _stream(stream)), "pairs_energy_f64_batched")
 
 
 def pairs_binned_workspace_size(n: int) -> int:

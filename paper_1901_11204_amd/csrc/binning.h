@@ -18,7 +18,7 @@
 //      2^25 / L + 2, the largest neighbour coordinate: 21 for L = 32, 11 for
 //      L = 2^15.  Each object is also written as one 16-byte record;
 //   2. radix sort of (key, index) over the key's 3 fb bits (rocPRIM);
-//   3. k_bin_gather: the records in key order;
+//   3. k_bin_gather: the records in key order, with each one's q = |p|^2 - r^2;
 //   4. run-length encoding of the sorted keys (rocPRIM) into the occupied
 //      cells' keys and sizes, and an exclusive scan of the sizes into cell
 //      offsets;
@@ -95,12 +95,15 @@ __global__ void k_bin_keys(const int32_t *__restrict__ x, const int32_t *__restr
     rec[i] = make_int4(xi, yi, zi, r[i]);
 }
 
-// The records in key order.
+// The records in key order, and each record's q = |p|^2 - r^2 (the partner
+// term of the Gram test, read by the work items' tasks).
 __global__ void k_bin_gather(const int4 *__restrict__ rec, const uint32_t *__restrict__ perm,
-                             int64_t n, int4 *__restrict__ so) {
+                             int64_t n, int4 *__restrict__ so, int64_t *__restrict__ sq) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    so[i] = rec[perm[i]];
+    const int4 o = rec[perm[i]];
+    so[i] = o;
+    sq[i] = pairs_dev::gram_q(o.x, o.y, o.z, o.w);
 }
 
 // Touch test: coordinates lie in [-2^24, 2^24] and radii in [0, 2^24], so
@@ -235,9 +238,26 @@ struct ItemList {
     uint32_t cap;
 };
 
-__device__ __forceinline__ void push_item(const ItemList &L, Item it) {
-    const uint32_t k = atomicAdd(L.n, 1u);
-    if (k < L.cap) L.items[k] = it;
+// Appends the calling lanes' items (a lane may push none, one or two) with
+// one atomic per wave: a lane's slots follow the items of the lanes below it.
+// Called by every active lane of the wave together.
+__device__ __forceinline__ void push_items(const ItemList &L, bool p0, const Item &i0, bool p1,
+                                           const Item &i1) {
+    const uint64_t b0 = __ballot(p0), b1 = __ballot(p1);
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t below = (1ull << lane) - 1;
+    const uint32_t total = __popcll(b0) + __popcll(b1);
+    if (total == 0) return;
+    const int first = __builtin_ctzll(__ballot(true));
+    uint32_t base = 0;
+    if (lane == first) base = atomicAdd(L.n, total);
+    base = (uint32_t)__shfl((int)base, first, kWave);
+    uint32_t k = base + __popcll(b0 & below) + __popcll(b1 & below);
+    if (p0) {
+        if (k < L.cap) L.items[k] = i0;
+        ++k;
+    }
+    if (p1 && k < L.cap) L.items[k] = i1;
 }
 
 __device__ __forceinline__ int64_t item_count(const ItemList &L) {
@@ -259,9 +279,9 @@ __device__ __forceinline__ uint64_t count_cell(int64_t a0, int64_t n, uint64_t k
     const bool big = n > kBigCell;
     // ranges with a big side go to the item list: the cell's own pairs, and
     // those with each big (or, for a big cell, every) occupied neighbour
-    if (big && gl == 0) push_item(items, Item{(uint32_t)a0, (uint32_t)n, (uint32_t)a0, (uint32_t)n});
-    if (gl < 13 && nb.y != 0 && (big || nb.y > (uint32_t)kBigCell))
-        push_item(items, Item{(uint32_t)a0, (uint32_t)n, nb.x, nb.y});
+    push_items(items, big && gl == 0, Item{(uint32_t)a0, (uint32_t)n, (uint32_t)a0, (uint32_t)n},
+               gl < 13 && nb.y != 0 && (big || nb.y > (uint32_t)kBigCell),
+               Item{(uint32_t)a0, (uint32_t)n, nb.x, nb.y});
     if (big) return 0;
     const int64_t h = (n - 1) / 2;
     for (int64_t i = gl; n >= 2 && i < n; i += G) {
@@ -364,41 +384,67 @@ struct ItemSched {
     int64_t nbuckets;  // ceil(T / B)
 };
 
-// One block: the exclusive prefix of the items' task counts and the header.
-constexpr int kScanThreads = 1024;
-__global__ __launch_bounds__(kScanThreads) void k_bin_item_scan(ItemList L,
-                                                               int64_t *__restrict__ pre,
-                                                               ItemSched *__restrict__ hdr) {
-    __shared__ int64_t part[kScanThreads];
+// The exclusive prefix of the items' task counts in three steps over blocks
+// of kScanBlock items (the item count is known on the device only, so the
+// grids cover the list's capacity and blocks past the items return):
+// per-block sums, one block scanning them and writing the header, and the
+// block-local prefixes.
+constexpr int kScanBlock = 1024;
+
+__global__ __launch_bounds__(kScanBlock) void k_bin_item_sums(ItemList L,
+                                                             int64_t *__restrict__ bsum) {
+    const int64_t m = item_count(L), k0 = (int64_t)blockIdx.x * kScanBlock;
+    if (k0 >= m) return;
+    __shared__ int64_t wave_tot[kScanBlock / kWave + 1];
+    const int64_t k = k0 + threadIdx.x;
+    int64_t sum;
+    pairs_dev::block_exclusive_scan<kScanBlock>(k < m ? item_tasks(L.items[k]) : 0, wave_tot,
+                                                &sum);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_bin_item_scan(ItemList L,
+                                                             int64_t *__restrict__ bsum,
+                                                             ItemSched *__restrict__ hdr) {
+    __shared__ int64_t wave_tot[kScanBlock / kWave + 1];
     const int tid = threadIdx.x;
-    const Item *items = L.items;
-    const int64_t m = item_count(L);
-    const int64_t chunk = (m + kScanThreads - 1) / kScanThreads;
-    const int64_t k0 = min((int64_t)tid * chunk, m), k1 = min(k0 + chunk, m);
-    int64_t sum = 0;
-    for (int64_t k = k0; k < k1; ++k) sum += item_tasks(items[k]);
-    part[tid] = sum;
-    __syncthreads();
+    const int64_t m = item_count(L), nb = (m + kScanBlock - 1) / kScanBlock;
+    const int64_t chunk = (nb + kScanBlock - 1) / kScanBlock;
+    const int64_t b0 = min((int64_t)tid * chunk, nb), b1 = min(b0 + chunk, nb);
+    int64_t part = 0;
+    for (int64_t b = b0; b < b1; ++b) part += bsum[b];
+    int64_t T;
+    int64_t run = pairs_dev::block_exclusive_scan<kScanBlock>(part, wave_tot, &T);
     if (tid == 0) {
-        int64_t run = 0;
-        for (int k = 0; k < kScanThreads; ++k) {
-            const int64_t v = part[k];
-            part[k] = run;
-            run += v;
-        }
-        pre[m] = run;
-        const int64_t B = m > 0 ? max((int64_t)1, (run + m - 1) / m) : 1;
+        const int64_t B = m > 0 ? max((int64_t)1, (T + m - 1) / m) : 1;
         hdr->m = m;
-        hdr->T = run;
+        hdr->T = T;
         hdr->B = B;
-        hdr->nbuckets = (run + B - 1) / B;
+        hdr->nbuckets = (T + B - 1) / B;
     }
-    __syncthreads();
-    int64_t run = part[tid];
-    for (int64_t k = k0; k < k1; ++k) {
-        pre[k] = run;
-        run += item_tasks(items[k]);
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t v = bsum[b];
+        bsum[b] = run;
+        run += v;
     }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_bin_item_prefix(ItemList L,
+                                                               const int64_t *__restrict__ bsum,
+                                                               const ItemSched *__restrict__ hdr,
+                                                               int64_t *__restrict__ pre) {
+    const int64_t m = item_count(L), k0 = (int64_t)blockIdx.x * kScanBlock;
+    if (k0 >= m) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) pre[0] = 0;  // no items
+        return;
+    }
+    __shared__ int64_t wave_tot[kScanBlock / kWave + 1];
+    const int64_t k = k0 + threadIdx.x;
+    int64_t sum;
+    const int64_t r = pairs_dev::block_exclusive_scan<kScanBlock>(
+        k < m ? item_tasks(L.items[k]) : 0, wave_tot, &sum);
+    if (k < m) pre[k] = bsum[blockIdx.x] + r;
+    if (k == m - 1) pre[m] = hdr->T;
 }
 
 // The bucket table: tab[q] = the item holding task q B; tab[nbuckets] = m - 1.
@@ -422,12 +468,16 @@ __global__ void k_bin_item_tab(const int64_t *__restrict__ pre,
 
 // One task of an item with K rows per lane: rows [ra, ra + 64 K) of A held as
 // in the pairs_count_i32 kernels (RowI32), partners u in [u0, u1) staged 64
-// at a time in LDS and read back as broadcasts.  The binned domain
-// (coordinates within 2^24) lies inside the box of the plain 64-bit Gram
-// test.  Padding rows (nq = -2^62) and padding partners (q = INT64_MAX) never
-// hit.
+// at a time in LDS (the next group's records in flight while a group is
+// counted) and read back as broadcasts, PU = 8 / K partners at a time for 8
+// independent multiply-add chains.  (Wave-uniform scalar reads of the
+// partners measured twice as slow: their latency exceeds the 40 VALU
+// operations each group of PU feeds.)  The binned domain (coordinates within
+// 2^24) lies inside the box of the plain 64-bit Gram test.  Padding rows
+// (nq = -2^62) and padding partners (q = INT64_MAX) never hit.
 template <int K>
-__device__ __forceinline__ uint32_t item_task(const int4 *__restrict__ so, const Item &it,
+__device__ __forceinline__ uint32_t item_task(const int4 *__restrict__ so,
+                                              const int64_t *__restrict__ sq, const Item &it,
                                               int64_t local, pairs_dev::PartnerI32 *wp,
                                               int64_t *wq) {
     using namespace pairs_dev;
@@ -458,19 +508,27 @@ __device__ __forceinline__ uint32_t item_task(const int4 *__restrict__ so, const
             nsteps[k] = self ? band.steps(i) : 0;
         }
     }
-    uint32_t cnt = 0;
-    for (int g0 = u0; g0 < u1; g0 += kWave) {
-        const int u = g0 + lane;
-        if (u < u1) {
-            const uint32_t j = self ? it.a0 + (uint32_t)(u >= (int)it.na ? u - (int)it.na : u)
-                                    : it.b0 + (uint32_t)u;
-            const int4 o = so[j];
-            wp[lane] = PartnerI32{o.x, o.y, o.z, o.w};
-            wq[lane] = gram_q(o.x, o.y, o.z, o.w);
-        } else {
-            wp[lane] = PartnerI32{0, 0, 0, 0};
-            wq[lane] = INT64_MAX;
+    // the partner record and q of virtual partner u (padding past u1)
+    auto fetch = [&](int u, int4 &o, int64_t &q) {
+        if (u >= u1) {
+            o = make_int4(0, 0, 0, 0);
+            q = INT64_MAX;
+            return;
         }
+        const uint32_t j = self ? it.a0 + (uint32_t)(u >= (int)it.na ? u - (int)it.na : u)
+                                : it.b0 + (uint32_t)u;
+        o = so[j];
+        q = sq[j];
+    };
+    constexpr int PU = 8 / K;
+    uint32_t cnt = 0;
+    int4 no;
+    int64_t nq;
+    fetch(u0 + lane, no, nq);
+    for (int g0 = u0; g0 < u1; g0 += kWave) {
+        wp[lane] = PartnerI32{no.x, no.y, no.z, no.w};
+        wq[lane] = nq;
+        fetch(g0 + kWave + lane, no, nq);  // in flight while this group is counted
         wave_sync();
         const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
         if (self) {
@@ -483,11 +541,19 @@ __device__ __forceinline__ uint32_t item_task(const int4 *__restrict__ so, const
                                            owns(g0 + q, row[k], nsteps[k]));
             }
         } else {
-            for (int q = 0; q < gn; ++q) {
-                const PartnerI32 b = wp[q];
-                const int64_t qb = wq[q];
+            // entries past gn are padding and never hit
+            for (int q = 0; q < gn; q += PU) {
+                PartnerI32 b[PU];
+                int64_t qb[PU];
 #pragma unroll
-                for (int k = 0; k < K; ++k) cnt += count_bits(gram_hit(rows[k], b, qb));
+                for (int d = 0; d < PU; ++d) {
+                    b[d] = wp[q + d];
+                    qb[d] = wq[q + d];
+                }
+#pragma unroll
+                for (int d = 0; d < PU; ++d)
+#pragma unroll
+                    for (int k = 0; k < K; ++k) cnt += count_bits(gram_hit(rows[k], b[d], qb[d]));
             }
         }
         wave_sync();
@@ -497,6 +563,7 @@ __device__ __forceinline__ uint32_t item_task(const int4 *__restrict__ so, const
 
 // The tasks of all items, taken by the waves with a grid stride.
 __global__ __launch_bounds__(kBlock) void k_bin_count_items(const int4 *__restrict__ so,
+                                                            const int64_t *__restrict__ sq,
                                                             ItemList L,
                                                             const int64_t *__restrict__ pre,
                                                             const int32_t *__restrict__ tab,
@@ -522,11 +589,11 @@ __global__ __launch_bounds__(kBlock) void k_bin_count_items(const int4 *__restri
         const int64_t local = t - pre[lo];
         const int K = item_rows(it.na);
         if (K == 1)
-            cnt += item_task<1>(so, it, local, wp, wq);
+            cnt += item_task<1>(so, sq, it, local, wp, wq);
         else if (K == 2)
-            cnt += item_task<2>(so, it, local, wp, wq);
+            cnt += item_task<2>(so, sq, it, local, wp, wq);
         else
-            cnt += item_task<4>(so, it, local, wp, wq);
+            cnt += item_task<4>(so, sq, it, local, wp, wq);
     }
     if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)count, (unsigned long long)cnt);
 }

@@ -45,6 +45,37 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Exclusive scan of v over a block of BLOCK threads (a multiple of 64);
+// *sum gets the block's total.  wave_tot: BLOCK / 64 + 1 words of LDS.
+// Every thread of the block calls it.
+template <int BLOCK>
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *wave_tot,
+                                                        int64_t *sum) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    int64_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) wave_tot[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int w = 0; w < BLOCK / kWave; ++w) {
+            const int64_t t = wave_tot[w];
+            wave_tot[w] = run;
+            run += t;
+        }
+        wave_tot[BLOCK / kWave] = run;
+    }
+    __syncthreads();
+    const int64_t r = wave_tot[wave] + x - v;
+    *sum = wave_tot[BLOCK / kWave];
+    __syncthreads();  // wave_tot is reused by the next scan
+    return r;
+}
+
 // DPP controls (GFX9 encoding).
 constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
 constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;

@@ -495,33 +495,6 @@ __global__ __launch_bounds__(kSchedBlock) void k_sched_scan(int64_t *blk, int64_
     }
 }
 
-// Exclusive scan of v over the block (kSchedBlock threads); *sum gets the total.
-__device__ __forceinline__ int64_t block_scan(int64_t v, int64_t *wave_tot, int64_t *sum) {
-    const int lane = lane_id(), wave = threadIdx.x / kWave;
-    int64_t x = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int64_t y = __shfl_up(x, d);
-        if (lane >= d) x += y;
-    }
-    if (lane == kWave - 1) wave_tot[wave] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t run = 0;
-        for (int w = 0; w < kSchedBlock / kWave; ++w) {
-            const int64_t t = wave_tot[w];
-            wave_tot[w] = run;
-            run += t;
-        }
-        wave_tot[kSchedBlock / kWave] = run;
-    }
-    __syncthreads();
-    const int64_t r = wave_tot[wave] + x - v;
-    *sum = wave_tot[kSchedBlock / kWave];
-    __syncthreads();  // wave_tot is reused by the next scan
-    return r;
-}
-
 // The list and the task prefixes.
 __global__ __launch_bounds__(kSchedBlock) void k_sched_list(
     const int64_t *__restrict__ off, int64_t n_sets, int64_t n_total, ClassTable ct,
@@ -534,8 +507,8 @@ __global__ __launch_bounds__(kSchedBlock) void k_sched_list(
     const int64_t *bb = blk + (int64_t)blockIdx.x * 2 * kMaxClasses;
     for (int q = 0; q < kMaxClasses; ++q) {
         int64_t sum;
-        const int64_t rank = block_scan(c == q ? 1 : 0, wave_tot, &sum);
-        const int64_t tpre = block_scan(c == q ? t : 0, wave_tot, &sum);
+        const int64_t rank = block_exclusive_scan<kSchedBlock>(c == q ? 1 : 0, wave_tot, &sum);
+        const int64_t tpre = block_exclusive_scan<kSchedBlock>(c == q ? t : 0, wave_tot, &sum);
         if (c == q) {
             const int64_t j = hdr->cbase[q] + bb[q] + rank;
             list[j] = (int32_t)s;
@@ -934,6 +907,87 @@ __global__ __launch_bounds__(kBlock, (batched_min_waves<KindV, KMAX>())) void k_
     }
 }
 
+// ------------------------------------------- batched forces and fp64 energy --
+//
+// Unplanned batches of the two interactions whose results are per object or
+// in double precision: forces of the softened potential (force_task) and the
+// potential in double precision (energy64_task).  Tasks come from the same
+// device-side schedule as the counts (ScanSource), in the broadcast form with
+// the rows per lane of each set's class; per-object outputs are written at
+// the set's base, so sets never touch each other's objects.
+
+enum XKind { kForceF32 = 4, kEnergyF64 = 5 };
+
+struct XBatchIO {
+    const void *x, *y, *z;
+    const int64_t *off;
+    int64_t n_total;
+    double eps2;
+    SumSink f[3];        // forces: per-object components; energy: f[0] = per-object sums (or null)
+    double *set_energy;  // energy: per-set totals
+    double emax;         // energy: > 0 for fixed-point set totals (bound on one term)
+};
+
+template <int K, int KindV>
+__device__ __forceinline__ void xbatched_task(const XBatchIO &io, int64_t base, const Band &band,
+                                              int ra, int u0, int u1, int64_t set, void *win) {
+    if constexpr (KindV == kForceF32) {
+        const float *X = (const float *)io.x, *Y = (const float *)io.y, *Z = (const float *)io.z;
+        TaskInputs<float, K> in;
+        load_task_inputs<float, K, K, false>(X, Y, Z, nullptr, base, band, ra, u0, u1, in);
+        force_task<K>(X, Y, Z, base, band, ra, u0, u1, (float)io.eps2, (float *)win, io.f[0],
+                      io.f[1], io.f[2], in);
+    } else {
+        const double *X = (const double *)io.x, *Y = (const double *)io.y,
+                     *Z = (const double *)io.z;
+        TaskInputs<double, K> in;
+        load_task_inputs<double, K, K, false>(X, Y, Z, nullptr, base, band, ra, u0, u1, in);
+        double e;
+        if (io.f[0].p)
+            e = energy64_task<K, true>(X, Y, Z, base, band, ra, u0, u1, io.eps2, (double *)win,
+                                       io.f[0], in);
+        else
+            e = energy64_task<K, false>(X, Y, Z, base, band, ra, u0, u1, io.eps2, (double *)win,
+                                        io.f[0], in);
+        if (lane_id() == 0) {
+            const double scale =
+                io.emax > 0.0 ? fixed_scale(0.5 * band.n * (band.n - 1.0) * io.emax) : 0.0;
+            SumSink{io.set_energy, scale}.add(set, e);
+        }
+    }
+}
+
+template <int KindV>
+__global__ __launch_bounds__(kBlock) void k_xbatched_scan(XBatchIO io, ScanSource src,
+                                                          ClassTable ct) {
+    constexpr int kLdsBytes = KindV == kForceF32 ? kForceLds * 4 : kEnergy64Lds * 8;
+    __shared__ __align__(16) unsigned char lds[kWavesPerBlock * kLdsBytes];
+    const int wave = wave_id();
+    void *win = lds + wave * kLdsBytes;
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t ntasks = src.hdr->T, B = src.hdr->B;
+    for (int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave; t < ntasks; t += stride) {
+        int64_t set;
+        int local;
+        src.decode(t, B, &set, &local);
+        int64_t base;
+        int n;
+        set_range(io.off, set, io.n_total, &base, &n);
+        if (n < 2) continue;
+        const int c = ct.class_of(n);
+        const Band band = Band::of(n);
+        const Tiling til = Tiling::of(band, ct.K[c], ct.U[c]);
+        if (local < 0 || (int64_t)local >= til.tasks()) continue;
+        int ra, u0, u1;
+        task_range(band, til, local / til.nchunks, local % til.nchunks, &ra, &u0, &u1);
+        if (u0 >= u1) continue;
+        if (ct.K[c] == 2)
+            xbatched_task<2, KindV>(io, base, band, ra, u0, u1, set, win);
+        else
+            xbatched_task<1, KindV>(io, base, band, ra, u0, u1, set, win);
+    }
+}
+
 // ------------------------------------------------------------------ jitter --
 //
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of two
@@ -1317,6 +1371,47 @@ pairs_status_t batched_common(int kind, const BatchIO &io, int64_t n_sets, void 
     return launch_scan(kind, io, src, ct, s);
 }
 
+// Size classes of the batched forces and double-precision energies: the
+// broadcast form, at most 2 rows per lane (three force components, or double
+// rows, take the registers of two float rows, and one kernel serves every
+// class, so its largest shape sets the occupancy of all).
+ClassTable xbatched_table() {
+    const int lo[3] = {1024, 128, 0}, K[3] = {2, 2, 1}, U[3] = {256, 128, 64};
+    return make_table(3, lo, K, U, nullptr);
+}
+
+pairs_status_t xbatched_common(int kind, const XBatchIO &io, int64_t n_sets, void *ws,
+                               size_t ws_bytes, hipStream_t s) {
+    if (!ws || ws_bytes < batched_ws_bytes(n_sets)) return PAIRS_ERR_WORKSPACE;
+    const SchedLayout L = sched_layout(n_sets);
+    unsigned char *p = (unsigned char *)ws;
+    SchedHeader *hdr = (SchedHeader *)(p + L.hdr);
+    int32_t *list = (int32_t *)(p + L.list);
+    int64_t *pre = (int64_t *)(p + L.pre);
+    int32_t *tab = (int32_t *)(p + L.tab);
+    int64_t *blk = (int64_t *)(p + L.blk);
+    const ClassTable ct = xbatched_table();
+    const unsigned nb = (unsigned)L.nb;
+    k_sched_count<<<nb, kSchedBlock, 0, s>>>(io.off, n_sets, io.n_total, ct, blk);
+    k_sched_scan<<<1, kSchedBlock, 0, s>>>(blk, L.nb, hdr);
+    k_sched_list<<<nb, kSchedBlock, 0, s>>>(io.off, n_sets, io.n_total, ct, blk, hdr, list, pre);
+    k_sched_tab<<<blocks_for(n_sets + 2, 256), 256, 0, s>>>(pre, hdr, tab);
+    PAIRS_HIP_CHECK(hipGetLastError());
+    DeviceState *st;
+    PAIRS_TRY(device_state(&st));
+    const ScanSource src{hdr, list, pre, tab};
+    auto go = [&](auto kern) {
+        const int64_t blocks = resident_blocks(st, kern) * kScanBlockFactor;
+        kern<<<(unsigned)blocks, kBlock, 0, s>>>(io, src, ct);
+    };
+    if (kind == kForceF32)
+        go(k_xbatched_scan<kForceF32>);
+    else
+        go(k_xbatched_scan<kEnergyF64>);
+    PAIRS_HIP_CHECK(hipGetLastError());
+    return PAIRS_OK;
+}
+
 pairs_status_t batched_args(const void *x, const void *y, const void *z,
                             const int64_t *d_offsets, int64_t n_sets, int64_t n_total,
                             unsigned flags, unsigned allowed = PAIRS_FLAG_VALIDATE) {
@@ -1351,8 +1446,8 @@ namespace bin = pairs_binning;
 
 // Workspace layout of a binned count of n objects.
 struct BinnedLayout {
-    size_t keys_in, keys_out, idx_in, idx_out, so, ukeys, sizes, off, runs, temp;
-    size_t htags, hkeys, hvals, hcnt, items, item_pre, item_tab, item_hdr, item_n;
+    size_t keys_in, keys_out, idx_in, idx_out, so, sq, ukeys, sizes, off, runs, temp;
+    size_t htags, hkeys, hvals, hcnt, items, item_pre, item_tab, item_hdr, item_bsum, item_n;
     size_t temp_bytes, total;
     int blog;  // cell table of 2^blog buckets of 8 slots, at least 2n slots
 };
@@ -1409,6 +1504,7 @@ pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
     L->idx_in = take(4 * un);
     L->idx_out = take(4 * un);
     L->so = take(16 * un);
+    L->sq = take(8 * un);
     L->ukeys = take(8 * un);
     L->sizes = take(4 * (un + 1));
     L->off = take(4 * (un + 1));
@@ -1427,6 +1523,7 @@ pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
     L->item_pre = take(8 * (cap + 1));
     L->item_tab = take(4 * (cap + 2));
     L->item_hdr = take(sizeof(bin::ItemSched));
+    L->item_bsum = take(8 * ((cap + bin::kScanBlock - 1) / bin::kScanBlock));
     L->item_n = take(8);
     L->temp_bytes = std::max(t1, std::max(t2, t3));
     L->temp = take(L->temp_bytes);
@@ -1808,6 +1905,77 @@ pairs_status_t pairs_energy_f32_batched(const float *x, const float *y, const fl
     if (flags & PAIRS_FLAG_DETERMINISTIC) io.emax = energy_term_bound(eps2);
     PAIRS_TRY(batched_common(kEnergyF32, io, n_sets, d_ws, ws_bytes, s));
     return finish_sets(io, n_sets, s);
+}
+
+pairs_status_t pairs_force_f32_batched(const float *x, const float *y, const float *z,
+                                       const int64_t *d_offsets, int64_t n_sets,
+                                       int64_t n_total, float eps2, double *d_fx, double *d_fy,
+                                       double *d_fz, void *d_ws, size_t ws_bytes, unsigned flags,
+                                       pairs_stream_t stream) {
+    PAIRS_TRY(batched_args(x, y, z, d_offsets, n_sets, n_total, flags, kSumFlags));
+    if (!(eps2 > 0.0f) || !isfinite(eps2)) return PAIRS_ERR_INVALID_ARG;
+    if (n_total > 0 && (!d_fx || !d_fy || !d_fz)) return PAIRS_ERR_INVALID_ARG;
+    if (!d_ws || ws_bytes < batched_ws_bytes(n_sets)) return PAIRS_ERR_WORKSPACE;
+    int dev;
+    PAIRS_TRY(current_device(&dev));
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & PAIRS_FLAG_VALIDATE) {
+        PAIRS_TRY(validate_offsets(d_offsets, n_sets, n_total, s));
+        PAIRS_TRY(validate_f32(x, y, z, nullptr, n_total, s));
+    }
+    PAIRS_TRY(fill_f64(d_fx, n_total, 0.0, s));
+    PAIRS_TRY(fill_f64(d_fy, n_total, 0.0, s));
+    PAIRS_TRY(fill_f64(d_fz, n_total, 0.0, s));
+    if (n_sets == 0 || n_total < 2) return PAIRS_OK;
+    // one scale for every object: the bound of the largest possible set
+    const bool det = flags & PAIRS_FLAG_DETERMINISTIC;
+    const double nmax = (double)std::min<int64_t>(n_total, PAIRS_MAX_BATCH_SET_SIZE);
+    const double bound = (nmax - 1.0) * force_term_bound(eps2);
+    XBatchIO io{x, y, z, d_offsets, n_total, eps2,
+                {sink(d_fx, det, bound), sink(d_fy, det, bound), sink(d_fz, det, bound)},
+                nullptr, 0.0};
+    PAIRS_TRY(xbatched_common(kForceF32, io, n_sets, d_ws, ws_bytes, s));
+    for (int c = 0; c < 3; ++c) PAIRS_TRY(finish(io.f[c], n_total, s));
+    return PAIRS_OK;
+}
+
+pairs_status_t pairs_energy_f64_batched(const double *x, const double *y, const double *z,
+                                        const int64_t *d_offsets, int64_t n_sets,
+                                        int64_t n_total, double eps2, double *d_set_energy,
+                                        double *d_energy, void *d_ws, size_t ws_bytes,
+                                        unsigned flags, pairs_stream_t stream) {
+    PAIRS_TRY(batched_args(x, y, z, d_offsets, n_sets, n_total, flags, kSumFlags));
+    if (!(eps2 > 0.0) || !isfinite(eps2)) return PAIRS_ERR_INVALID_ARG;
+    if (n_sets > 0 && !d_set_energy) return PAIRS_ERR_INVALID_ARG;
+    if (!d_ws || ws_bytes < batched_ws_bytes(n_sets)) return PAIRS_ERR_WORKSPACE;
+    int dev;
+    PAIRS_TRY(current_device(&dev));
+    hipStream_t s = (hipStream_t)stream;
+    if (flags & PAIRS_FLAG_VALIDATE) {
+        PAIRS_TRY(validate_offsets(d_offsets, n_sets, n_total, s));
+        PAIRS_TRY(run_validation(s, [&](int *flag) {
+            if (n_total > 0)
+                k_validate_f64<<<blocks_for(n_total, 256), 256, 0, s>>>(x, y, z, n_total, flag);
+        }));
+    }
+    PAIRS_TRY(fill_f64(d_set_energy, n_sets, 0.0, s));
+    PAIRS_TRY(fill_f64(d_energy, n_total, 0.0, s));
+    if (n_sets == 0) return PAIRS_OK;
+    const bool det = flags & PAIRS_FLAG_DETERMINISTIC;
+    const double emax = energy_term_bound(eps2);
+    const double nmax = (double)std::min<int64_t>(n_total, PAIRS_MAX_BATCH_SET_SIZE);
+    XBatchIO io{x, y, z, d_offsets, n_total, eps2,
+                {sink(d_energy, det, (nmax - 1.0) * emax), SumSink{nullptr, 0.0},
+                 SumSink{nullptr, 0.0}},
+                d_set_energy, det ? emax : 0.0};
+    PAIRS_TRY(xbatched_common(kEnergyF64, io, n_sets, d_ws, ws_bytes, s));
+    PAIRS_TRY(finish(io.f[0], n_total, s));
+    BatchIO bio{};
+    bio.energy = d_set_energy;
+    bio.off = d_offsets;
+    bio.n_total = n_total;
+    bio.emax = io.emax;
+    return finish_sets(bio, n_sets, s);
 }
 
 pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_sets,
@@ -2368,7 +2536,8 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
     bin::k_bin_keys<<<nb, 256, 0, s>>>(x, y, z, r, n, cell, fb, keys_in, idx_in, rec);
     PAIRS_HIP_CHECK(hipGetLastError());
     PAIRS_HIP_CHECK(binned_sort(temp, tb, keys_in, keys_out, idx_in, idx_out, n, 3 * fb, s));
-    bin::k_bin_gather<<<nb, 256, 0, s>>>(rec, idx_out, n, so);
+    int64_t *sq = (int64_t *)(w + L.sq);
+    bin::k_bin_gather<<<nb, 256, 0, s>>>(rec, idx_out, n, so, sq);
     PAIRS_HIP_CHECK(hipGetLastError());
     tb = L.temp_bytes;
     PAIRS_HIP_CHECK(rocprim::run_length_encode(temp, tb, keys_out, (unsigned)n, ukeys, sizes,
@@ -2382,14 +2551,20 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
     const int64_t blocks = std::min<int64_t>((n + 15) / 16, (int64_t)st->n_cu * 16);
     bin::k_bin_count<<<(unsigned)blocks, bin::kBlock, 0, s>>>(
         so, ukeys, off, runs, (const uint64_t *)htags, hkeys, hvals, L.blog, fb, items, d_count);
-    bin::k_bin_item_scan<<<1, bin::kScanThreads, 0, s>>>(items, item_pre, item_hdr);
+    int64_t *item_bsum = (int64_t *)(w + L.item_bsum);
+    const unsigned item_nb =
+        (unsigned)((bin::item_capacity(n) + bin::kScanBlock - 1) / bin::kScanBlock);
+    bin::k_bin_item_sums<<<item_nb, bin::kScanBlock, 0, s>>>(items, item_bsum);
+    bin::k_bin_item_scan<<<1, bin::kScanBlock, 0, s>>>(items, item_bsum, item_hdr);
+    bin::k_bin_item_prefix<<<item_nb, bin::kScanBlock, 0, s>>>(items, item_bsum, item_hdr,
+                                                               item_pre);
     // at most cap buckets and the sentinel
     bin::k_bin_item_tab<<<blocks_for(bin::item_capacity(n) + 1, 256), 256, 0, s>>>(
         item_pre, item_hdr, item_tab);
     const int64_t item_blocks = std::min<int64_t>(n / (4 * bin::kBigCell) + 1,
                                                   (int64_t)st->n_cu * 8);
     bin::k_bin_count_items<<<(unsigned)item_blocks, bin::kBlock, 0, s>>>(
-        so, items, item_pre, item_tab, item_hdr, d_count);
+        so, sq, items, item_pre, item_tab, item_hdr, d_count);
     PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;
 }

@@ -581,8 +581,11 @@ __device__ __forceinline__ void energy_group(const float (&xr)[K], const float (
                     e = __builtin_amdgcn_rsqf(d2);
                 }
                 if (Masked) e = valid ? e : 0.0f;
-                part[k] += e;
-                if (PerObject) js += e;
+                // the first term of a fold and of a partner sum is stored,
+                // not added to zero (an add of 0 is no IEEE identity, so the
+                // compiler keeps it)
+                part[k] = tt == 0 ? e : part[k] + e;
+                if (PerObject) js = k == 0 ? e : js + e;
             }
             if (PerObject) js_all[tt] = js;
         }
@@ -592,10 +595,7 @@ __device__ __forceinline__ void energy_group(const float (&xr)[K], const float (
             win[4 * kWave + t0 + slot] = s;
         }
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            acc[k] += (double)part[k];
-            part[k] = 0.0f;
-        }
+        for (int k = 0; k < K; ++k) acc[k] += (double)part[k];
     }
 }
 
@@ -717,12 +717,13 @@ __device__ __forceinline__ void force_group(const float (&xr)[K], const float (&
                 float e3 = e * e * e;
                 if (Masked) e3 = owns(u, row[k], nsteps[k]) ? e3 : 0.0f;
                 const float fx = dx * e3, fy = dy * e3, fz = dz * e3;
-                part[0][k] += fx;
-                part[1][k] += fy;
-                part[2][k] += fz;
-                sx += fx;
-                sy += fy;
-                sz += fz;
+                // first terms stored, not added to zero
+                part[0][k] = tt == 0 ? fx : part[0][k] + fx;
+                part[1][k] = tt == 0 ? fy : part[1][k] + fy;
+                part[2][k] = tt == 0 ? fz : part[2][k] + fz;
+                sx = k == 0 ? fx : sx + fx;
+                sy = k == 0 ? fy : sy + fy;
+                sz = k == 0 ? fz : sz + fz;
             }
             sx_all[tt] = sx;
             sy_all[tt] = sy;
@@ -735,10 +736,7 @@ __device__ __forceinline__ void force_group(const float (&xr)[K], const float (&
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                acc[c][k] += (double)part[c][k];
-                part[c][k] = 0.0f;
-            }
+            for (int k = 0; k < K; ++k) acc[c][k] += (double)part[c][k];
         }
     }
 }
@@ -867,7 +865,7 @@ __device__ __forceinline__ void energy64_group(const double (&xr)[K], const doub
                 double e = rsq_f64(d2);
                 if (Masked) e = owns(u, row[k], nsteps[k]) ? e : 0.0;
                 acc[k] += e;
-                if (PerObject) js += e;
+                if (PerObject) js = k == 0 ? e : js + e;
             }
             if (PerObject) js_all[tt] = js;
         }

@@ -93,6 +93,19 @@ def test_batched_argument_errors_on_the_host():
                                              None) == INVALID
     assert L.pairs_count_i32_batched_noalloc(x, y, z, r, off, 10, 100, None, 0,
                                              None) == INVALID
+    # batched forces and double-precision energies
+    assert L.pairs_force_f32_batched(x, y, z, off, 10, 100, 1e-4, out, out, out, ws, need - 1, 0,
+                                     None) == WORKSPACE
+    assert L.pairs_force_f32_batched(x, y, z, off, 10, 100, 0.0, out, out, out, ws, need, 0,
+                                     None) == INVALID
+    assert L.pairs_force_f32_batched(x, y, z, off, 10, 100, 1e-4, None, out, out, ws, need, 0,
+                                     None) == INVALID
+    assert L.pairs_energy_f64_batched(x, y, z, off, 10, 100, 1e-4, None, None, ws, need, 0,
+                                      None) == INVALID
+    assert L.pairs_energy_f64_batched(x, y, z, off, 10, 100, -1.0, out, None, ws, need, 0,
+                                      None) == INVALID
+    assert L.pairs_energy_f64_batched(x, y, z, off, 10, 100, 1e-4, out, None, ws, need, 0x80,
+                                      None) == INVALID
     # energies: r and counts must be both given or both absent
     assert L.pairs_energy_f32_batched(x, y, z, r, off, 10, 100, 1e-4, out, None, ws, need, 0,
                                       None) == INVALID
