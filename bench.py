@@ -382,20 +382,7 @@ def bench_batched(P, w, torch, np, dev, steps):
     ms, _ = timed_steps(lambda: P.pairs_count_i32_batched(x, y, z, r, toff, counts, ws),
                         max(5, steps), 2)
     m = float(np.mean(ms))
-    # the same objects counted as one set through the binned path: cells of
-    # 2^14 are the sets' own grid cells (up to 8192 objects, so big cells and
-    # their neighbours go through the work items), cells of 1024 are about
-    # twice the largest radius
-    n4 = b.n_total
-    wsb = torch.empty(P.pairs_binned_workspace_size(n4), dtype=torch.uint8, device=dev)
-    outb = torch.empty(1, dtype=torch.int64, device=dev)
-    for cell in (1 << 14, 1024):
-        log(f"[bench] binned count of the {n4} objects as one set, cells of {cell}")
-        msb, _ = timed_steps(lambda: P.pairs_count_i32_binned(x, y, z, r, cell, outb, wsb), 3, 1)
-        out[f"count_i32_binned_one_set_cell{cell}"] = {
-            "workload": f"config 4's {n4} objects as one set, cells of {cell}",
-            "ms": float(np.median(msb)), "count": int(outb.item())}
-    del wsb
+    out.update(bench_binned_config4(P, torch, np, dev, b, (x, y, z, r), toff))
     out["count_i32_binned_200k_sets_unplanned"] = {
         "ms": m, "G_pairs_per_s": pairs / m / 1e6,
         "valu_frac": pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK,
@@ -446,6 +433,35 @@ def bench_batched(P, w, torch, np, dev, steps):
     return out
 
 
+def bench_binned_config4(P, torch, np, dev, b, xyzr, toff):
+    """Config 4's objects through the binned path: all 22.5 M as one set in
+    cells of 2^14 (the sets' own grid cells, up to 8192 objects, so big cells
+    and their neighbours go through the work items) and of 1024 (about twice
+    the largest radius), and the 200 000 sets binned per set as a CSR batch
+    in cells of 2^14 and 4096."""
+    out = {}
+    n4 = b.n_total
+    wsb = torch.empty(P.pairs_binned_workspace_size(n4), dtype=torch.uint8, device=dev)
+    outb = torch.empty(1, dtype=torch.int64, device=dev)
+    for cell in (1 << 14, 1024):
+        log(f"[bench] binned count of the {n4} objects as one set, cells of {cell}")
+        msb, _ = timed_steps(lambda: P.pairs_count_i32_binned(*xyzr, cell, outb, wsb), 3, 1)
+        out[f"count_i32_binned_one_set_cell{cell}"] = {
+            "workload": f"config 4's {n4} objects as one set, cells of {cell}",
+            "ms": float(np.median(msb)), "count": int(outb.item())}
+    countsb = torch.empty(b.n_sets, dtype=torch.int64, device=dev)
+    for cell in (1 << 14, 4096):
+        log(f"[bench] binned count of the {b.n_sets} sets as a CSR batch, cells of {cell}")
+        msb, _ = timed_steps(lambda: P.pairs_count_i32_binned_batched(*xyzr, toff, cell, countsb,
+                                                                      wsb), 3, 1)
+        out[f"count_i32_binned_batched_200k_sets_cell{cell}"] = {
+            "workload": f"config 4's {b.n_sets} sets binned per set, cells of {cell}",
+            "ms": float(np.median(msb)),
+            "matches_oracle": hashlib.sha256(countsb.cpu().numpy().astype("<u8").tobytes())
+                              .hexdigest() == golden()["config4_counts"]["sha256_le_u64"]}
+    return out
+
+
 def bench_binned(P, torch, np, dev, xyzr, steps, ms_all_pairs=None):
     """The binned count of the 2^20-sphere set with cells of 2^15."""
     n = xyzr[0].numel()
@@ -454,14 +470,16 @@ def bench_binned(P, torch, np, dev, xyzr, steps, ms_all_pairs=None):
     outb = torch.empty(1, dtype=torch.int64, device=dev)
     msb, _ = timed_steps(lambda: P.pairs_count_i32_binned(*xyzr, 1 << 15, outb, wsb), steps, 2)
     mb = float(np.median(msb))
-    # algorithmic HBM bytes per object: read 16 B of input and write 28 B
-    # of key, index and record; the histogram reads the 8 B keys; four
-    # 10-bit radix passes over the 33 key bits read and write 12 B each;
-    # the gather reads 4 + 16 B and writes the 16 B record and its 8 B q;
-    # run-length encoding reads 8 B and writes 12 B and the scan reads and
-    # writes 4 B; the table reads 16 B and writes 17 B per cell (about one
-    # per object here); the count reads the 16 B records
-    bpo = 16 + 28 + 8 + 4 * 24 + 44 + 20 + 8 + 33 + 16
+    # algorithmic HBM bytes per object (about one occupied cell per object
+    # here, two table slots per object): clearing the slots' keys, tags and
+    # sizes (26 B); the insert reads 16 B of input, probes and sets an 8 B
+    # key, writes a tag byte, the 8 B (slot, rank) and the 16 B record
+    # (49 B); the slot sums read 10 B; the slot prefix reads 10 B and, per
+    # cell, the 8 B key, and writes 20 B (38 B); the scatter reads 16 B and
+    # writes a 4 B index (20 B); the gather reads 4 + 16 B and writes the
+    # 16 B record and its 8 B q (44 B); the count reads 4 B of offset, the
+    # 8 B key and the 16 B record (28 B)
+    bpo = 26 + 49 + 10 + 38 + 20 + 44 + 28
     res = {"ms": mb, "cell": 1 << 15, "count": int(outb.item()),
            "workspace_bytes_per_object": wsb.numel() / n,
            "matches_oracle": int(outb.item()) == golden()["config2_even_count"],
@@ -490,7 +508,9 @@ def main():
     ap.add_argument("--lattice-only", action="store_true",
                     help="only the lattice-bead counts (for profiling)")
     ap.add_argument("--binned-only", action="store_true",
-                    help="only the binned count of the 2^20 set (for profiling)")
+                    help="only the binned counts of the 2^20 set and of config 4 (for profiling)")
+    ap.add_argument("--binned-workload", choices=["2p20", "config4", "all"], default="all",
+                    help="with --binned-only: which binned workloads")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
@@ -527,8 +547,17 @@ def main():
         print(json.dumps({"lattice": bench_lattice(P, w, torch, np, dev, a.steps)}), flush=True)
         return
     if a.binned_only:
-        xyzr = tuple(torch.from_numpy(v).to(dev) for v in w.config2(2 ** 20).arrays())
-        print(json.dumps({"binned": bench_binned(P, torch, np, dev, xyzr, a.steps)}), flush=True)
+        res = {}
+        if a.binned_workload in ("2p20", "all"):
+            xyzr = tuple(torch.from_numpy(v).to(dev) for v in w.config2(2 ** 20).arrays())
+            res["count_i32_binned_2^20"] = bench_binned(P, torch, np, dev, xyzr, a.steps)
+            del xyzr
+        if a.binned_workload in ("config4", "all"):
+            b4 = w.config4()
+            xyzr = tuple(torch.from_numpy(v).to(dev) for v in b4.objs.arrays())
+            res.update(bench_binned_config4(P, torch, np, dev, b4, xyzr,
+                                            torch.from_numpy(b4.offsets).to(dev)))
+        print(json.dumps({"binned": res}), flush=True)
         return
 
     # headline workload

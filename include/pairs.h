@@ -396,26 +396,28 @@ pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t
  * with the pairwise count inside each cell on the balanced assignment.  With
  * every radius at most cell/2, touching spheres lie in the same or in
  * neighbouring cells, so only the pairs inside a cell and between each cell
- * and its 13 forward neighbours are tested.  The objects are sorted by cell
- * on the device (a radix sort), so the time grows with n times the objects
- * per cell rather than with n^2.
+ * and its 13 forward neighbours are tested.  The objects are grouped by cell
+ * on the device through a hash table of the occupied cells, so the time
+ * grows with n times the objects per cell rather than with n^2.
  *
  * Domain: coordinates in [-2^24, 2^24], radii in [0, cell/2],
  * PAIRS_BINNED_MIN_CELL <= cell <= PAIRS_BINNED_MAX_CELL, at most
  * PAIRS_BINNED_MAX_SET_SIZE objects.  Outside it the result is undefined
  * unless PAIRS_FLAG_VALIDATE is given (then PAIRS_ERR_DOMAIN).
  * Workspace: pairs_binned_workspace_size(n) bytes of device memory, owned by
- * the caller (about 110 bytes per object at 2^20 objects, the sort's
- * temporary storage included).  For n > 0 the size query asks rocPRIM for
- * the sort's storage on the current device, so it needs a HIP device
- * (PAIRS_ERR_NO_DEVICE without one).
- * Stream-ordered, with no host synchronisation, but not to be captured into
- * a HIP graph: the radix sort (rocPRIM) clears its own state with
- * hipMemsetAsync.
+ * the caller (about 120 to 160 bytes per object, with the cell table
+ * rounded up to a power of two of at least 2n slots); the size query needs
+ * no device.
+ * Every call clears what it needs, so a workspace serves calls in a row.
+ * Stream-ordered, with no host synchronisation and no allocation; the call
+ * can be captured into a HIP graph (without PAIRS_FLAG_VALIDATE, whose check
+ * waits on the host), since it clears its state with kernels, not memsets.
+ * The counts are exact, so they do not depend on the order in which the
+ * device groups the objects.
  */
 #define PAIRS_BINNED_MIN_CELL 32
 #define PAIRS_BINNED_MAX_CELL (1 << 25)
-#define PAIRS_BINNED_MAX_SET_SIZE (((int64_t)1 << 31) - 1)
+#define PAIRS_BINNED_MAX_SET_SIZE ((int64_t)1 << 30)
 
 pairs_status_t pairs_binned_workspace_size(int64_t n, size_t *bytes);
 
@@ -423,6 +425,24 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
                                       const int32_t *r, int64_t n, int32_t cell,
                                       uint64_t *d_count, void *d_ws, size_t ws_bytes,
                                       unsigned flags, pairs_stream_t stream);
+
+/*
+ * The binned count of every set of a CSR batch (the objects of set s are
+ * [d_offsets[s], d_offsets[s+1]), d_offsets[n_sets] = n_total, on the device)
+ * into d_counts[n_sets] (uint64, device): pairs of objects of different sets
+ * are never counted.  A set's cells are keyed by the set index above the
+ * cells' 3 fb bits, fb = the fewest bits that hold 2^25 / cell + 2 (11 for
+ * cells of 2^15, 16 for cells of 1024), so 3 fb + ceil(log2 n_sets) must not
+ * pass 64 (else PAIRS_ERR_INVALID_ARG).  Same domain, workspace
+ * (pairs_binned_workspace_size(n_total)) and stream behaviour as
+ * pairs_count_i32_binned; PAIRS_FLAG_VALIDATE also checks the offsets.
+ */
+pairs_status_t pairs_count_i32_binned_batched(const int32_t *x, const int32_t *y,
+                                              const int32_t *z, const int32_t *r,
+                                              const int64_t *d_offsets, int64_t n_sets,
+                                              int64_t n_total, int32_t cell, uint64_t *d_counts,
+                                              void *d_ws, size_t ws_bytes, unsigned flags,
+                                              pairs_stream_t stream);
 
 /* --------------------------------------------------------- lattice beads -- */
 /*

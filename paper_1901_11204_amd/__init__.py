@@ -28,7 +28,7 @@ __all__ = [
     "Plan", "Graph", "ShapeTable", "pairs_get_shapes", "pairs_set_shapes",
     "count_i32", "count_f32", "energy_f32",
     "pairs_lattice_workspace_size", "pairs_lattice_count", "pairs_lattice_count_batched",
-    "pairs_binned_workspace_size", "pairs_count_i32_binned",
+    "pairs_binned_workspace_size", "pairs_count_i32_binned", "pairs_count_i32_binned_batched",
     "LATTICE_LDS_BEADS", "LATTICE_MAX_BEADS",
 ]
 
@@ -127,6 +127,8 @@ def _declare(L):
         "pairs_binned_workspace_size": [_i64, ctypes.POINTER(_sz)],
         "pairs_count_i32_binned": [_vp, _vp, _vp, _vp, _i64, ctypes.c_int32, _vp, _vp, _sz, _u32,
                                    _vp],
+        "pairs_count_i32_binned_batched": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, ctypes.c_int32,
+                                           _vp, _vp, _sz, _u32, _vp],
         "pairs_lattice_count": [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _u32, _vp],
         "pairs_lattice_count_batched": [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp, _sz,
                                         _u32, _vp],
@@ -402,6 +404,25 @@ def pairs_count_i32_binned(x, y, z, r, cell: int, out, ws=None, flags: int = 0,
     _check(lib().pairs_count_i32_binned(_ptr(x), _ptr(y), _ptr(z), _ptr(r), n, int(cell),
                                         _ptr(out), _ptr(ws), nbytes, flags, _stream(stream)),
            "pairs_count_i32_binned")
+
+
+def pairs_count_i32_binned_batched(x, y, z, r, offsets, cell: int, counts, ws=None,
+                                   flags: int = 0, stream=None) -> None:
+    """Binned collision count of every set of a CSR batch into counts
+    (int64[n_sets], read as uint64); pairs across sets are never counted."""
+    import torch
+    n_total, n_sets = _batch_checks(x, (x, y, z, r), torch.int32, offsets,
+                                    "pairs_count_i32_binned_batched")
+    _require((counts,), torch.int64, n_sets, "pairs_count_i32_binned_batched counts")
+    need = pairs_binned_workspace_size(n_total)
+    if ws is None and need > 0:
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    nbytes = 0 if ws is None else int(ws.numel() * ws.element_size())
+    _check(lib().pairs_count_i32_binned_batched(_ptr(x), _ptr(y), _ptr(z), _ptr(r),
+                                                _ptr(offsets), n_sets, n_total, int(cell),
+                                                _ptr(counts), _ptr(ws), nbytes, flags,
+                                                _stream(stream)),
+           "pairs_count_i32_binned_batched")
 
 
 def pairs_lattice_workspace_size(n_sets: int, n_total: int, max_n: int) -> int:

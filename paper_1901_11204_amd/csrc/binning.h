@@ -10,36 +10,41 @@
 // forward neighbours (offsets (dx, dy, dz) after (0, 0, 0) in lexicographic
 // order), which meets every pair of neighbouring cells once.
 //
-// Pipeline (all on the device, no host synchronisation):
+// Pipeline (all on the device, no host synchronisation, no library call, so
+// a call can be captured into a HIP graph):
 //   0. k_bin_clear: every buffer that has to start at zero, in one launch;
-//   1. k_bin_keys: cell coordinates (x + 2^24) / L + 1 per axis (the +1 keeps
-//      the -1 neighbours of cell 0 in range), packed fb bits per axis into a
-//      64-bit key, and the object index.  fb is the fewest bits that hold
-//      2^25 / L + 2, the largest neighbour coordinate: 21 for L = 32, 11 for
-//      L = 2^15.  Each object is also written as one 16-byte record;
-//   2. radix sort of (key, index) over the key's 3 fb bits (rocPRIM);
-//   3. k_bin_gather: the records in key order, with each one's q = |p|^2 - r^2;
-//   4. run-length encoding of the sorted keys (rocPRIM) into the occupied
-//      cells' keys and sizes, and an exclusive scan of the sizes into cell
-//      offsets;
-//   5. k_bin_hash_build: a hash table of 8-slot buckets from occupied cell
-//      keys to each cell's first object and size;
-//   6. k_bin_count: 16 lanes per occupied cell.  Lanes 0..12 of a group
+//   1. k_bin_insert: cell coordinates (x + 2^24) / L + 1 per axis (the +1
+//      keeps the -1 neighbours of cell 0 in range), packed fb bits per axis
+//      into a 64-bit key above which sits the object's set (batched calls).
+//      fb is the fewest bits that hold 2^25 / L + 2, the largest neighbour
+//      coordinate: 21 for L = 32, 11 for L = 2^15.  Each object finds or
+//      inserts its cell's key in a hash table of 8-slot buckets and takes a
+//      rank in the cell;
+//   2. k_bin_slot_sums, k_bin_slot_scan, k_bin_slot_prefix: a prefix over
+//      the table's slots numbers the cells in slot order and gives each its
+//      first object, stored with the size in the table and, with the key,
+//      in per-cell arrays;
+//   3. k_bin_scatter, k_bin_gather: each object's record (x, y, z, r) and
+//      its q = |p|^2 - r^2 at its cell's first object plus its rank;
+//   4. k_bin_count: 16 lanes per occupied cell.  Lanes 0..12 of a group
 //      look up the 13 forward neighbours in the table; the pairs inside a
 //      cell of at most kBigCell objects run on the balanced circular
 //      assignment (each lane takes rows and their steps s = 1 ..
 //      floor((n-1)/2), rows i < n/2 also s = n/2 when n is even); the pairs
 //      with each occupied neighbour of at most kBigCell objects run with the
-//      lanes taking the cell's objects against all of the neighbour's.  Wave
-//      sums go to the count with one atomic per wave.  Every pair of ranges
-//      with more than kBigCell objects on one side -- a big cell's own pairs,
-//      and the pairs between a cell and a neighbour when either is big -- is
-//      appended instead to a list of work items;
-//   7. k_bin_item_scan and k_bin_count_items: each item is tiled into wave
-//      tasks of at most 64 K rows against kItemChunk partners (the balanced
-//      assignment's row blocks and chunks for a cell's own pairs, a
-//      rectangle of rows and partners between two cells), and all waves
-//      share the tasks, so no wave's work grows with a cell's size.
+//      lanes taking the cell's objects against all of the neighbour's.
+//      Every pair of ranges with more than kBigCell objects on one side -- a
+//      big cell's own pairs, and the pairs between a cell and a neighbour
+//      when either is big -- is appended instead to a list of work items;
+//   5. k_bin_item_sums, k_bin_item_scan, k_bin_item_prefix, k_bin_item_tab
+//      and k_bin_count_items: each item is tiled into wave tasks of at most
+//      64 K rows against kItemChunk partners (the balanced assignment's row
+//      blocks and chunks for a cell's own pairs, a rectangle of rows and
+//      partners between two cells), and all waves share the tasks, so no
+//      wave's work grows with a cell's size.
+// The cells follow the table's slot order; the order of the objects in a
+// cell follows the order of the atomic operations, which varies from run to
+// run; the count does not.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -62,10 +67,25 @@ __device__ __forceinline__ uint32_t cell_of(int v, int L) {
     return (uint32_t)(v + kOffsetBias) / (uint32_t)L + 1;
 }
 
-// Key of a cell: fb bits per axis, x in the high field.  Sorting by key sorts
-// the cells in (x, y, z) lexicographic order.
+// Key of a cell: fb bits per axis, x in the high field; a batched call puts
+// the object's set above the 3 fb cell bits, so cells of different sets
+// never meet.  Occupied cells have z >= 1, so no occupied cell's key is 0,
+// the key of an empty table slot.
 __device__ __forceinline__ uint64_t cell_key(uint32_t cx, uint32_t cy, uint32_t cz, int fb) {
     return ((uint64_t)cx << (2 * fb)) | ((uint64_t)cy << fb) | (uint64_t)cz;
+}
+constexpr uint64_t kEmptyKey = 0;
+
+// Set of object i of a CSR batch: the largest s with off[s] <= i (empty
+// sets share their offset with the next set, which is then the larger s).
+__device__ __forceinline__ uint32_t set_of(const int64_t *__restrict__ off, int64_t n_sets,
+                                           int64_t i) {
+    int64_t lo = 0, hi = n_sets;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return (uint32_t)lo;
 }
 
 // Domain check of the binned count: coordinates in [-2^24, 2^24] and radii
@@ -80,32 +100,6 @@ __global__ void k_bin_validate(const int32_t *x, const int32_t *y, const int32_t
     if (!ok) atomicOr(bad, 1);
 }
 
-// Keys and indices for the sort, and each object as one 16-byte record
-// (x, y, z, r), so that the gather after the sort reads one record per
-// object rather than four scattered words.
-__global__ void k_bin_keys(const int32_t *__restrict__ x, const int32_t *__restrict__ y,
-                           const int32_t *__restrict__ z, const int32_t *__restrict__ r,
-                           int64_t n, int L, int fb, uint64_t *__restrict__ keys,
-                           uint32_t *__restrict__ idx, int4 *__restrict__ rec) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int xi = x[i], yi = y[i], zi = z[i];
-    keys[i] = cell_key(cell_of(xi, L), cell_of(yi, L), cell_of(zi, L), fb);
-    idx[i] = (uint32_t)i;
-    rec[i] = make_int4(xi, yi, zi, r[i]);
-}
-
-// The records in key order, and each record's q = |p|^2 - r^2 (the partner
-// term of the Gram test, read by the work items' tasks).
-__global__ void k_bin_gather(const int4 *__restrict__ rec, const uint32_t *__restrict__ perm,
-                             int64_t n, int4 *__restrict__ so, int64_t *__restrict__ sq) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int4 o = rec[perm[i]];
-    so[i] = o;
-    sq[i] = pairs_dev::gram_q(o.x, o.y, o.z, o.w);
-}
-
 // Touch test: coordinates lie in [-2^24, 2^24] and radii in [0, 2^24], so
 // the differences and the radius sum fit 32 bits (at most 2^25 in size) and
 // the squares and their sum fit 64 bits exactly.
@@ -115,12 +109,14 @@ __device__ __forceinline__ bool touch(int4 a, int4 b) {
 }
 
 // Cells by key: a table of 2^blog buckets of kSlots slots (at least twice as
-// many slots as objects).  Per slot: a tag byte in htags (0 = empty, else 8
-// bits of the key's hash), the key in hkeys and the cell's first object and
-// size in hvals; per bucket, the number of claims in hcnt.  A key goes to the
-// first bucket, from its home bucket on, whose claim count is below kSlots,
-// so a bucket's slots fill in order and a key can be further on only if its
-// home bucket is full.
+// many slots as objects, so at most half full).  Per slot: the key in hkeys
+// (kEmptyKey = free), a tag byte in htags (0 = free, else 8 bits of the
+// key's hash), the cell's size minus one in hsize and its first object and
+// size in hvals.  A key
+// takes the first free slot from its home bucket's first slot on (one
+// compare-and-swap per free slot probed), so a bucket's slots fill in order
+// and a key lies past its home bucket only if every bucket in between is
+// full.
 //
 // A lookup reads the bucket's eight tags as one 8-byte word, from a tag array
 // of one byte per slot that the L2 cache holds, and reads a key only where
@@ -142,27 +138,99 @@ __device__ __forceinline__ uint32_t cell_tag(uint64_t h, int blog) {
     return t ? t : 1u;
 }
 
-__global__ void k_bin_hash_build(const uint64_t *__restrict__ ukeys,
-                                 const uint32_t *__restrict__ off,
-                                 const uint32_t *__restrict__ m_ptr, uint8_t *htags,
-                                 uint64_t *hkeys, uint2 *hvals, uint32_t *hcnt, int blog) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= (int64_t)*m_ptr) return;
-    const uint64_t key = ukeys[c], h = cell_hash(key);
-    const uint2 val = make_uint2(off[c], off[c + 1] - off[c]);
-    const uint32_t mask = (1u << blog) - 1;
-    uint32_t b = home_bucket(h, blog);
-    // the slots outnumber the cells, so some bucket has room
-    for (uint32_t p = 0; p <= mask; ++p, b = (b + 1) & mask) {
-        const uint32_t at = atomicAdd(&hcnt[b], 1u);
-        if (at < (uint32_t)kSlots) {
-            const size_t slot = (size_t)b * kSlots + at;
+// Slot of `key`, inserted if absent; *won tells whether this call inserted
+// it.  Keys only ever go from free to set during the insert pass, so a
+// plain load that sees a key is final, and one that sees a free slot is
+// settled by the compare-and-swap.  The slots outnumber the keys, so the
+// probe ends.
+__device__ __forceinline__ uint32_t find_or_insert(uint64_t *hkeys, uint8_t *htags, int blog,
+                                                   uint64_t key, bool *won) {
+    const uint64_t h = cell_hash(key);
+    const uint32_t last = ((uint32_t)kSlots << blog) - 1;
+    uint32_t slot = home_bucket(h, blog) * (uint32_t)kSlots;
+    for (;;) {
+        uint64_t cur = __atomic_load_n(&hkeys[slot], __ATOMIC_RELAXED);
+        if (cur == kEmptyKey)
+            cur = atomicCAS((unsigned long long *)&hkeys[slot], (unsigned long long)kEmptyKey,
+                            (unsigned long long)key);
+        if (cur == kEmptyKey) {
             htags[slot] = (uint8_t)cell_tag(h, blog);
-            hkeys[slot] = key;
-            hvals[slot] = val;
-            return;
+            *won = true;
+            return slot;
+        }
+        if (cur == key) {
+            *won = false;
+            return slot;
+        }
+        slot = slot == last ? 0 : slot + 1;
+    }
+}
+
+// Ranks in a cell: the object that inserts the cell's key takes rank 0 with
+// no further atomic (in a sparse grid, nearly every object), every other
+// object 1 + the value it adds 1 to in the slot's counter hsize, which so
+// ends at the cell's size minus one.  Lanes that share a key are served by
+// one probe and one counter update while the first pending lane's key is
+// shared by at least kPeelMin lanes, for at most kPeelMax keys per wave
+// (objects listed by cell or by set come in such runs); the other lanes
+// probe and count one by one.
+constexpr int kPeelMax = 4, kPeelMin = 4;
+
+// Step 1: the cell of every object: obj[i] = (slot, rank in the cell), and
+// the object as one 16-byte record rec[i] = (x, y, z, r).  off: the batch's
+// set offsets (null for one set).
+__global__ __launch_bounds__(kBlock) void k_bin_insert(
+    const int32_t *__restrict__ x, const int32_t *__restrict__ y, const int32_t *__restrict__ z,
+    const int32_t *__restrict__ r, const int64_t *__restrict__ off, int64_t n_sets, int64_t n,
+    int L, int fb, int blog, uint64_t *hkeys, uint8_t *htags, uint32_t *hsize,
+    uint2 *__restrict__ obj, int4 *__restrict__ rec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t below = (1ull << lane) - 1;
+    const bool active = i < n;
+    uint64_t key = 0;
+    if (active) {
+        const int xi = x[i], yi = y[i], zi = z[i];
+        rec[i] = make_int4(xi, yi, zi, r[i]);
+        key = cell_key(cell_of(xi, L), cell_of(yi, L), cell_of(zi, L), fb);
+        if (off) key |= (uint64_t)set_of(off, n_sets, i) << (3 * fb);
+    }
+    bool pending = active;
+    uint32_t slot = 0, rank = 0;
+    for (int it = 0; it < kPeelMax; ++it) {
+        const uint64_t pend = __ballot(pending);
+        if (!pend) break;
+        const int leader = __builtin_ctzll(pend);
+        const uint64_t lk = __shfl((unsigned long long)key, leader, kWave);
+        const bool mine = pending && key == lk;
+        const uint64_t grp = __ballot(mine);
+        const uint32_t g = (uint32_t)__popcll(grp);
+        if (g < (uint32_t)kPeelMin) break;
+        uint32_t s = 0, base = 0, won = 0;
+        if (lane == leader) {
+            bool w;
+            s = find_or_insert(hkeys, htags, blog, lk, &w);
+            won = w;
+            // the group's j-th lane takes rank base + j, except an inserting
+            // leader (j = 0), which takes rank 0
+            base = w ? atomicAdd(&hsize[s], g - 1) : atomicAdd(&hsize[s], g) + 1;
+        }
+        s = (uint32_t)__shfl((int)s, leader, kWave);
+        base = (uint32_t)__shfl((int)base, leader, kWave);
+        won = (uint32_t)__shfl((int)won, leader, kWave);
+        if (mine) {
+            const uint32_t j = (uint32_t)__popcll(grp & below);
+            slot = s;
+            rank = (won && j == 0) ? 0u : base + j;
+            pending = false;
         }
     }
+    if (pending) {
+        bool won;
+        slot = find_or_insert(hkeys, htags, blog, key, &won);
+        rank = won ? 0u : atomicAdd(&hsize[slot], 1u) + 1;
+    }
+    if (active) obj[i] = make_uint2(slot, rank);
 }
 
 // 0x80 in each byte of x that is zero, 0 elsewhere (exact: no carry crosses
@@ -196,9 +264,9 @@ __device__ __forceinline__ uint2 find_cell(const uint64_t *__restrict__ htags,
     return make_uint2(0, 0);
 }
 
-// Key of forward neighbour d of a cell.  Cell coordinates are at least 1
-// (the +1 offset) and at most 2^25 / L + 1, so every neighbour's coordinates
-// stay inside their fb-bit fields.
+// Key of forward neighbour d of a cell, in the cell's set.  Cell
+// coordinates are at least 1 (the +1 offset) and at most 2^25 / L + 1, so
+// every neighbour's coordinates stay inside their fb-bit fields.
 __device__ __forceinline__ uint64_t neighbour_key(uint64_t key, int d, int fb) {
     // d = 0..12 enumerates (dx, dy, dz) > (0, 0, 0) lexicographically
     const int e = d + 14;  // index in the 3x3x3 cube, 13 being the centre
@@ -207,7 +275,140 @@ __device__ __forceinline__ uint64_t neighbour_key(uint64_t key, int d, int fb) {
     const uint64_t cx = (key >> (2 * fb)) & mask;
     const uint64_t cy = (key >> fb) & mask;
     const uint64_t cz = key & mask;
-    return cell_key((uint32_t)(cx + dx), (uint32_t)(cy + dy), (uint32_t)(cz + dz), fb);
+    const uint64_t set_bits = key & ~((uint64_t(1) << (3 * fb)) - 1);
+    return set_bits |
+           cell_key((uint32_t)(cx + dx), (uint32_t)(cy + dy), (uint32_t)(cz + dz), fb);
+}
+
+// Prefix sums over lists whose length is known on the device only run over
+// blocks of kScanBlock entries: per-block sums, one block scanning them, and
+// the block-local prefixes.
+constexpr int kScanBlock = 1024;
+
+// Exclusive scan, in place, of the nb block sums in bsum, by one block of
+// kScanBlock threads; returns the total to every thread.
+__device__ __forceinline__ int64_t scan_block_sums(int64_t nb, int64_t *__restrict__ bsum,
+                                                   int64_t *wave_tot) {
+    const int tid = threadIdx.x;
+    const int64_t chunk = (nb + kScanBlock - 1) / kScanBlock;
+    const int64_t b0 = min((int64_t)tid * chunk, nb), b1 = min(b0 + chunk, nb);
+    int64_t part = 0;
+    for (int64_t b = b0; b < b1; ++b) part += bsum[b];
+    int64_t T;
+    int64_t run = pairs_dev::block_exclusive_scan<kScanBlock>(part, wave_tot, &T);
+    for (int64_t b = b0; b < b1; ++b) {
+        const int64_t v = bsum[b];
+        bsum[b] = run;
+        run += v;
+    }
+    return T;
+}
+
+// Step 2: the first object of every cell and the cells' order, by an
+// exclusive prefix over the table's slots in slot order of the pair (objects,
+// cells) packed in one 64-bit word (objects in the high half, 1 per
+// occupied slot in the low half; both stay below 2^31), in three launches:
+// per-block sums over blocks of kSlotBlock slots (4 per thread, read as one
+// word of tags and one 16-byte load of sizes), one block scanning them (and
+// setting *ncell, the number of cells), and the block-local prefixes.
+constexpr int kSlotsPerThread = 4, kSlotBlock = kScanBlock * kSlotsPerThread;
+
+struct SlotPairs {
+    uint64_t v[kSlotsPerThread];
+    uint64_t sum;
+};
+
+// The pairs of slots [k, k + 4) (k a multiple of 4; the slot count is a
+// multiple of 8, so a group starting below it ends within it).
+__device__ __forceinline__ SlotPairs slot_pairs(const uint8_t *__restrict__ htags,
+                                                const uint32_t *__restrict__ hsize, int64_t k,
+                                                int64_t slots) {
+    SlotPairs p;
+    p.sum = 0;
+    uint32_t tw = 0;
+    uint4 sz = make_uint4(0, 0, 0, 0);
+    if (k < slots) {
+        tw = *(const uint32_t *)(htags + k);
+        sz = *(const uint4 *)(hsize + k);
+    }
+    const uint32_t szs[kSlotsPerThread] = {sz.x, sz.y, sz.z, sz.w};
+#pragma unroll
+    for (int j = 0; j < kSlotsPerThread; ++j) {
+        const bool occ = (tw >> (8 * j)) & 0xFFu;
+        p.v[j] = occ ? ((uint64_t)(szs[j] + 1) << 32) | 1u : 0;
+        p.sum += p.v[j];
+    }
+    return p;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_bin_slot_sums(const uint8_t *__restrict__ htags,
+                                                             const uint32_t *__restrict__ hsize,
+                                                             int64_t slots,
+                                                             int64_t *__restrict__ bsum) {
+    __shared__ int64_t wave_tot[kScanBlock / kWave + 1];
+    const int64_t k = ((int64_t)blockIdx.x * kScanBlock + threadIdx.x) * kSlotsPerThread;
+    const SlotPairs p = slot_pairs(htags, hsize, k, slots);
+    int64_t sum;
+    pairs_dev::block_exclusive_scan<kScanBlock>((int64_t)p.sum, wave_tot, &sum);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_bin_slot_scan(int64_t nb,
+                                                             int64_t *__restrict__ bsum,
+                                                             uint32_t *__restrict__ ncell) {
+    __shared__ int64_t wave_tot[kScanBlock / kWave + 1];
+    const int64_t T = scan_block_sums(nb, bsum, wave_tot);
+    if (threadIdx.x == 0) *ncell = (uint32_t)(T & 0xFFFFFFFFu);
+}
+
+// Per occupied slot sl, the cell c it holds in slot order: off[c] its first
+// object, ukeys[c] its key, hvals[sl] = (first object, size) for the
+// lookups; off[m] = n.
+__global__ __launch_bounds__(kScanBlock) void k_bin_slot_prefix(
+    const uint8_t *__restrict__ htags, const uint32_t *__restrict__ hsize,
+    const uint64_t *__restrict__ hkeys, int64_t slots, const int64_t *__restrict__ bsum,
+    const uint32_t *__restrict__ ncell, int64_t n, uint32_t *__restrict__ off,
+    uint64_t *__restrict__ ukeys, uint2 *__restrict__ hvals) {
+    __shared__ int64_t wave_tot[kScanBlock / kWave + 1];
+    const int64_t k = ((int64_t)blockIdx.x * kScanBlock + threadIdx.x) * kSlotsPerThread;
+    const SlotPairs p = slot_pairs(htags, hsize, k, slots);
+    int64_t sum;
+    uint64_t at = (uint64_t)bsum[blockIdx.x] +
+                  (uint64_t)pairs_dev::block_exclusive_scan<kScanBlock>((int64_t)p.sum, wave_tot,
+                                                                         &sum);
+#pragma unroll
+    for (int j = 0; j < kSlotsPerThread; ++j) {
+        if (p.v[j]) {
+            const uint32_t c = (uint32_t)(at & 0xFFFFFFFFu), first = (uint32_t)(at >> 32);
+            off[c] = first;
+            ukeys[c] = hkeys[k + j];
+            hvals[k + j] = make_uint2(first, (uint32_t)(p.v[j] >> 32));
+        }
+        at += p.v[j];
+    }
+    if (k == 0) off[*ncell] = (uint32_t)n;
+}
+
+// Step 3: the records grouped by cell, in two passes: each object's index
+// at its cell's first object plus its rank (a 4-byte scattered write), then
+// the records and each one's q = |p|^2 - r^2 (the partner term of the Gram
+// test, read by the work items' tasks) gathered in that order (scattered
+// 16-byte reads, written in order).
+__global__ void k_bin_scatter(int64_t n, const uint2 *__restrict__ obj,
+                              const uint2 *__restrict__ hvals, uint32_t *__restrict__ perm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint2 o = obj[i];
+    perm[hvals[o.x].x + o.y] = (uint32_t)i;
+}
+
+__global__ void k_bin_gather(const int4 *__restrict__ rec, const uint32_t *__restrict__ perm,
+                             int64_t n, int4 *__restrict__ so, int64_t *__restrict__ sq) {
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n) return;
+    const int4 o = rec[perm[d]];
+    so[d] = o;
+    sq[d] = pairs_dev::gram_q(o.x, o.y, o.z, o.w);
 }
 
 // Pairs of one occupied cell (first object a0, n objects, key `key`),
@@ -217,9 +418,10 @@ __device__ __forceinline__ uint64_t neighbour_key(uint64_t key, int d, int fb) {
 // assignment, and the pairs with each occupied neighbour with the lanes
 // taking the cell's objects against all of the neighbour's.
 // A work item: the pairs between objects [a0, a0 + na) and [b0, b0 + nb) of
-// the sorted records, or the pairs within [a0, a0 + na) when b0 == a0.
+// the grouped records, or the pairs within [a0, a0 + na) when b0 == a0, all
+// in set `set`.
 struct Item {
-    uint32_t a0, na, b0, nb;
+    uint32_t a0, na, b0, nb, set;
 };
 constexpr int64_t kBigCell = 64;
 
@@ -266,8 +468,8 @@ __device__ __forceinline__ int64_t item_count(const ItemList &L) {
 }
 
 template <int G>
-__device__ __forceinline__ uint64_t count_cell(int64_t a0, int64_t n, uint64_t key, int gl, int g0,
-                                               const int4 *__restrict__ so,
+__device__ __forceinline__ uint64_t count_cell(int64_t a0, int64_t n, uint64_t key, uint32_t set,
+                                               int gl, int g0, const int4 *__restrict__ so,
                                                const uint64_t *__restrict__ htags,
                                                const uint64_t *__restrict__ hkeys,
                                                const uint2 *__restrict__ hvals, int blog,
@@ -279,9 +481,10 @@ __device__ __forceinline__ uint64_t count_cell(int64_t a0, int64_t n, uint64_t k
     const bool big = n > kBigCell;
     // ranges with a big side go to the item list: the cell's own pairs, and
     // those with each big (or, for a big cell, every) occupied neighbour
-    push_items(items, big && gl == 0, Item{(uint32_t)a0, (uint32_t)n, (uint32_t)a0, (uint32_t)n},
+    push_items(items, big && gl == 0,
+               Item{(uint32_t)a0, (uint32_t)n, (uint32_t)a0, (uint32_t)n, set},
                gl < 13 && nb.y != 0 && (big || nb.y > (uint32_t)kBigCell),
-               Item{(uint32_t)a0, (uint32_t)n, nb.x, nb.y});
+               Item{(uint32_t)a0, (uint32_t)n, nb.x, nb.y, set});
     if (big) return 0;
     const int64_t h = (n - 1) / 2;
     for (int64_t i = gl; n >= 2 && i < n; i += G) {
@@ -295,8 +498,20 @@ __device__ __forceinline__ uint64_t count_cell(int64_t a0, int64_t n, uint64_t k
     }
     // only the occupied neighbours of at most kBigCell objects, usually none
     // in a sparse grid
-    uint32_t occ =
-        (uint32_t)(__ballot(nb.y != 0 && nb.y <= (uint32_t)kBigCell) >> g0) & ((1u << 13) - 1);
+    const bool small_nb = nb.y != 0 && nb.y <= (uint32_t)kBigCell;
+    uint32_t occ = (uint32_t)(__ballot(small_nb) >> g0) & ((1u << 13) - 1);
+    if (n < __popc(occ)) {
+        // fewer objects in the cell than occupied neighbours: each of lanes
+        // 0..12 takes its own neighbour's pairs with the whole cell, in
+        // place of the lanes sharing the cell's objects one neighbour after
+        // the other
+        if (small_nb)
+            for (int64_t i = 0; i < n; ++i) {
+                const int4 oi = so[a0 + i];
+                for (uint32_t j = 0; j < nb.y; ++j) cnt += touch(oi, so[nb.x + j]);
+            }
+        return cnt;
+    }
     while (occ) {
         const int d = __builtin_ctz(occ);
         occ &= occ - 1;
@@ -321,17 +536,20 @@ __device__ __forceinline__ void wave_count_to(uint64_t *count, uint64_t cnt) {
 // 16 lanes per occupied cell, four cells per wave in flight, which hides the
 // latency of a cell's dependent loads.  Ranges with a big side go to `items`
 // (their number in item_n).  m_ptr: number of occupied cells (device); ukeys:
-// their keys; off: their first object in the sorted arrays, off[m] = n;
+// their keys; off: their first object in the grouped records, off[m] = n;
 // htags, hkeys, hvals, blog: the table from keys to cell ranges; fb: bits per
-// axis of a key; so: the object records in key order.
+// axis of a key; so: the object records grouped by cell.  counts: one count
+// per set; with one set, each wave adds its cells' pairs once at the end,
+// otherwise each group adds each cell's pairs (when any) to its set's count.
 constexpr int kGroup = 16;
 
 // Eight waves per SIMD: the loop waits on loads, so occupancy pays.
+template <bool Batched>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_bin_count(
     const int4 *__restrict__ so, const uint64_t *__restrict__ ukeys,
     const uint32_t *__restrict__ off, const uint32_t *__restrict__ m_ptr,
     const uint64_t *__restrict__ htags, const uint64_t *__restrict__ hkeys,
-    const uint2 *__restrict__ hvals, int blog, int fb, ItemList items, uint64_t *count) {
+    const uint2 *__restrict__ hvals, int blog, int fb, ItemList items, uint64_t *counts) {
     const int lane = threadIdx.x & (kWave - 1);
     const int gl = lane % kGroup, g0 = lane - gl;
     const int64_t m = *m_ptr;
@@ -349,10 +567,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         uint64_t pk = 0;
         if (cn < m) p0 = off[cn], p1 = off[cn + 1], pk = ukeys[cn];
         const int64_t n = (int64_t)o1 - o0;
-        cnt += count_cell<kGroup>(o0, n, key, gl, g0, so, htags, hkeys, hvals, blog, fb, items);
+        const uint32_t set = Batched ? (uint32_t)(key >> (3 * fb)) : 0u;
+        uint64_t cc = count_cell<kGroup>(o0, n, key, set, gl, g0, so, htags, hkeys, hvals, blog,
+                                         fb, items);
+        if (Batched) {
+            // the 16 lanes of a group run the same cells, so the xor partners
+            // stay inside the group and are active together
+            for (int o = kGroup / 2; o >= 1; o >>= 1) cc += __shfl_xor(cc, o, kWave);
+            if (gl == 0 && cc) atomicAdd((unsigned long long *)&counts[set], (unsigned long long)cc);
+        } else {
+            cnt += cc;
+        }
         o0 = p0, o1 = p1, key = pk;
     }
-    wave_count_to(count, cnt);
+    if (!Batched) wave_count_to(counts, cnt);
 }
 
 // ------------------------------------------------------------- work items --
@@ -389,7 +617,6 @@ struct ItemSched {
 // grids cover the list's capacity and blocks past the items return):
 // per-block sums, one block scanning them and writing the header, and the
 // block-local prefixes.
-constexpr int kScanBlock = 1024;
 
 __global__ __launch_bounds__(kScanBlock) void k_bin_item_sums(ItemList L,
                                                              int64_t *__restrict__ bsum) {
@@ -407,25 +634,14 @@ __global__ __launch_bounds__(kScanBlock) void k_bin_item_scan(ItemList L,
                                                              int64_t *__restrict__ bsum,
                                                              ItemSched *__restrict__ hdr) {
     __shared__ int64_t wave_tot[kScanBlock / kWave + 1];
-    const int tid = threadIdx.x;
-    const int64_t m = item_count(L), nb = (m + kScanBlock - 1) / kScanBlock;
-    const int64_t chunk = (nb + kScanBlock - 1) / kScanBlock;
-    const int64_t b0 = min((int64_t)tid * chunk, nb), b1 = min(b0 + chunk, nb);
-    int64_t part = 0;
-    for (int64_t b = b0; b < b1; ++b) part += bsum[b];
-    int64_t T;
-    int64_t run = pairs_dev::block_exclusive_scan<kScanBlock>(part, wave_tot, &T);
-    if (tid == 0) {
+    const int64_t m = item_count(L);
+    const int64_t T = scan_block_sums((m + kScanBlock - 1) / kScanBlock, bsum, wave_tot);
+    if (threadIdx.x == 0) {
         const int64_t B = m > 0 ? max((int64_t)1, (T + m - 1) / m) : 1;
         hdr->m = m;
         hdr->T = T;
         hdr->B = B;
         hdr->nbuckets = (T + B - 1) / B;
-    }
-    for (int64_t b = b0; b < b1; ++b) {
-        const int64_t v = bsum[b];
-        bsum[b] = run;
-        run += v;
     }
 }
 
@@ -561,14 +777,15 @@ __device__ __forceinline__ uint32_t item_task(const int4 *__restrict__ so,
     return cnt;
 }
 
-// The tasks of all items, taken by the waves with a grid stride.
+// The tasks of all items, taken by the waves with a grid stride; each task
+// adds its pairs (when any) to its item's set's count.
 __global__ __launch_bounds__(kBlock) void k_bin_count_items(const int4 *__restrict__ so,
                                                             const int64_t *__restrict__ sq,
                                                             ItemList L,
                                                             const int64_t *__restrict__ pre,
                                                             const int32_t *__restrict__ tab,
                                                             const ItemSched *__restrict__ hdr,
-                                                            uint64_t *count) {
+                                                            uint64_t *counts) {
     using namespace pairs_dev;
     __shared__ PartnerI32 wp_all[kBlock / kWave][kWave];
     __shared__ int64_t wq_all[kBlock / kWave][kWave];
@@ -577,7 +794,6 @@ __global__ __launch_bounds__(kBlock) void k_bin_count_items(const int4 *__restri
     int64_t *wq = wq_all[wave];
     const int64_t total = hdr->T, B = hdr->B;
     const int64_t stride = (int64_t)gridDim.x * (kBlock / kWave);
-    uint64_t cnt = 0;
     for (int64_t t = (int64_t)blockIdx.x * (kBlock / kWave) + wave; t < total; t += stride) {
         const int64_t b = t / B;
         int64_t lo = tab[b], hi = (int64_t)tab[b + 1] + 1;  // pre[lo] <= t < pre[hi]
@@ -588,20 +804,21 @@ __global__ __launch_bounds__(kBlock) void k_bin_count_items(const int4 *__restri
         const Item it = L.items[lo];
         const int64_t local = t - pre[lo];
         const int K = item_rows(it.na);
+        uint32_t cnt;
         if (K == 1)
-            cnt += item_task<1>(so, sq, it, local, wp, wq);
+            cnt = item_task<1>(so, sq, it, local, wp, wq);
         else if (K == 2)
-            cnt += item_task<2>(so, sq, it, local, wp, wq);
+            cnt = item_task<2>(so, sq, it, local, wp, wq);
         else
-            cnt += item_task<4>(so, sq, it, local, wp, wq);
+            cnt = item_task<4>(so, sq, it, local, wp, wq);
+        if (lane_id() == 0 && cnt)
+            atomicAdd((unsigned long long *)&counts[it.set], (unsigned long long)cnt);
     }
-    if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)count, (unsigned long long)cnt);
 }
 
 // Ranges of 32-bit words that the pipeline needs zeroed, cleared by one
-// launch (blockIdx.y picks the range): the count, the cell sizes (the scan
-// runs over n + 1 sizes, zero past the m occupied cells, so that off[m] = n),
-// the table's tags and claim counts, and the number of work items.
+// launch (blockIdx.y picks the range): the counts, the table's keys, tags
+// and per-slot object counts, and the numbers of cells and work items.
 constexpr int kClearRanges = 5;
 struct ClearRanges {
     uint32_t *p[kClearRanges];

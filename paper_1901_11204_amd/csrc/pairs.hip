@@ -30,9 +30,6 @@
 #include <new>
 #include <vector>
 
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_run_length_encode.hpp>
-#include <rocprim/device/device_scan.hpp>
 
 #include "band.h"
 #include "binning.h"
@@ -1446,21 +1443,11 @@ namespace bin = pairs_binning;
 
 // Workspace layout of a binned count of n objects.
 struct BinnedLayout {
-    size_t keys_in, keys_out, idx_in, idx_out, so, sq, ukeys, sizes, off, runs, temp;
-    size_t htags, hkeys, hvals, hcnt, items, item_pre, item_tab, item_hdr, item_bsum, item_n;
-    size_t temp_bytes, total;
+    size_t obj, rec, perm, so, sq, ukeys, off, slot_bsum;
+    size_t htags, hkeys, hvals, hsize, counters, items, item_pre, item_tab, item_hdr, item_bsum;
+    size_t total;
     int blog;  // cell table of 2^blog buckets of 8 slots, at least 2n slots
 };
-
-// The key sort always runs as radix passes over the key's bits (rocPRIM's
-// onesweep).  By default rocPRIM merge-sorts up to 2^20 keys, in a block sort
-// and ten merge passes whatever the key width.
-using BinSortConfig = rocprim::radix_sort_config<
-    rocprim::default_config, rocprim::default_config,
-    rocprim::radix_sort_onesweep_config<rocprim::kernel_config<512, 32>,
-                                        rocprim::kernel_config<512, 12>, 10,
-                                        rocprim::block_radix_rank_algorithm::match>,
-    0>;
 
 // Bits per axis of a cell key: the fewest that hold the largest neighbour
 // coordinate, 2^25 / cell + 2.
@@ -1471,27 +1458,14 @@ int binned_field_bits(int32_t cell) {
     return fb;
 }
 
-hipError_t binned_sort(void *temp, size_t &bytes, const uint64_t *keys_in, uint64_t *keys_out,
-                       const uint32_t *idx_in, uint32_t *idx_out, int64_t n, int end_bit,
-                       hipStream_t s) {
-    return rocprim::radix_sort_pairs<BinSortConfig>(temp, bytes, keys_in, keys_out, idx_in,
-                                                    idx_out, (size_t)n, 0u, (unsigned)end_bit, s);
+// Bits of a batch's set index in a cell key (0 for one set).
+int binned_set_bits(int64_t n_sets) {
+    int sb = 0;
+    while (sb < 63 && ((int64_t)1 << sb) < n_sets) ++sb;
+    return sb;
 }
 
 pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
-    size_t t1 = 0, t2 = 0, t3 = 0;
-    if (n > 0) {
-        // the widest keys (cells of 32) need the most temporary storage;
-        // rocPRIM sizes it for the current device's architecture
-        PAIRS_HIP_CHECK(binned_sort(nullptr, t1, nullptr, nullptr, nullptr, nullptr, n,
-                                    3 * bin::kMaxCellBits, 0));
-        PAIRS_HIP_CHECK(rocprim::run_length_encode(nullptr, t2, (const uint64_t *)nullptr,
-                                                   (unsigned)n, (uint64_t *)nullptr,
-                                                   (uint32_t *)nullptr, (uint32_t *)nullptr));
-        PAIRS_HIP_CHECK(rocprim::exclusive_scan(nullptr, t3, (const uint32_t *)nullptr,
-                                                (uint32_t *)nullptr, 0u, (size_t)n + 1,
-                                                rocprim::plus<uint32_t>()));
-    }
     size_t p = 0;
     auto take = [&](size_t bytes) {
         size_t at = p;
@@ -1499,35 +1473,118 @@ pairs_status_t binned_layout(int64_t n, BinnedLayout *L) {
         return at;
     };
     const size_t un = (size_t)n;
-    L->keys_in = take(8 * un);
-    L->keys_out = take(8 * un);
-    L->idx_in = take(4 * un);
-    L->idx_out = take(4 * un);
+    L->obj = take(8 * un);
+    L->rec = take(16 * un);
+    L->perm = take(4 * un);
     L->so = take(16 * un);
     L->sq = take(8 * un);
     L->ukeys = take(8 * un);
-    L->sizes = take(4 * (un + 1));
     L->off = take(4 * (un + 1));
-    L->runs = take(4);
+    // at least 2n slots, so the table is at most half full (n cells at most):
+    // at 3/4 the lookups of the count kernel took a quarter longer
     L->blog = 1;
     while ((int64_t(bin::kSlots) << L->blog) < 2 * std::max<int64_t>(n, 1)) ++L->blog;
     const size_t slots = size_t(bin::kSlots) << L->blog;
+    L->slot_bsum = take(8 * ((slots + bin::kSlotBlock - 1) / bin::kSlotBlock));
     L->htags = take(slots);
-    // hkeys also holds the unsorted object records (16 bytes each, at most
-    // 8 * slots) until the gather, before the table is cleared
     L->hkeys = take(8 * slots);
     L->hvals = take(8 * slots);
-    L->hcnt = take(4 * (size_t(1) << L->blog));
+    L->hsize = take(4 * slots);
+    L->counters = take(8);  // cells, work items
     const size_t cap = (size_t)bin::item_capacity(n);
     L->items = take(sizeof(bin::Item) * cap);
     L->item_pre = take(8 * (cap + 1));
     L->item_tab = take(4 * (cap + 2));
     L->item_hdr = take(sizeof(bin::ItemSched));
     L->item_bsum = take(8 * ((cap + bin::kScanBlock - 1) / bin::kScanBlock));
-    L->item_n = take(8);
-    L->temp_bytes = std::max(t1, std::max(t2, t3));
-    L->temp = take(L->temp_bytes);
     L->total = p;
+    return PAIRS_OK;
+}
+
+// The binned count of n objects in n_sets sets (d_offsets null: one set)
+// into d_counts[n_sets]; arguments already checked.
+pairs_status_t binned_common(const int32_t *x, const int32_t *y, const int32_t *z,
+                             const int32_t *r, const int64_t *d_offsets, int64_t n_sets,
+                             int64_t n, int32_t cell, uint64_t *d_counts, void *d_ws,
+                             size_t ws_bytes, unsigned flags, hipStream_t s) {
+    const int fb = binned_field_bits(cell);
+    if (3 * fb + binned_set_bits(n_sets) > 64) return PAIRS_ERR_INVALID_ARG;
+    BinnedLayout L;
+    PAIRS_TRY(binned_layout(n, &L));
+    if (n > 0 && (!d_ws || ws_bytes < L.total)) return PAIRS_ERR_WORKSPACE;
+    DeviceState *st;
+    PAIRS_TRY(device_state(&st));
+    if (flags & PAIRS_FLAG_VALIDATE) {
+        if (d_offsets) PAIRS_TRY(validate_offsets(d_offsets, n_sets, n, s));
+        PAIRS_TRY(run_validation(s, [&](int *flag) {
+            if (n > 0)
+                bin::k_bin_validate<<<blocks_for(n, 256), 256, 0, s>>>(x, y, z, r, n, cell, flag);
+        }));
+    }
+    if (n < 2) return fill_u64(d_counts, n_sets, 0, s);
+    unsigned char *w = (unsigned char *)d_ws;
+    uint2 *obj = (uint2 *)(w + L.obj);
+    int4 *rec = (int4 *)(w + L.rec);
+    uint32_t *perm = (uint32_t *)(w + L.perm);
+    int4 *so = (int4 *)(w + L.so);
+    int64_t *sq = (int64_t *)(w + L.sq);
+    uint32_t *off = (uint32_t *)(w + L.off);
+    uint64_t *ukeys = (uint64_t *)(w + L.ukeys);
+    int64_t *slot_bsum = (int64_t *)(w + L.slot_bsum);
+    uint8_t *htags = (uint8_t *)(w + L.htags);
+    uint64_t *hkeys = (uint64_t *)(w + L.hkeys);
+    uint2 *hvals = (uint2 *)(w + L.hvals);
+    uint32_t *hsize = (uint32_t *)(w + L.hsize);
+    uint32_t *ncell = (uint32_t *)(w + L.counters), *item_n = ncell + 1;
+    const bin::ItemList items{(bin::Item *)(w + L.items), item_n,
+                              (uint32_t)bin::item_capacity(n)};
+    int64_t *item_pre = (int64_t *)(w + L.item_pre);
+    int32_t *item_tab = (int32_t *)(w + L.item_tab);
+    bin::ItemSched *item_hdr = (bin::ItemSched *)(w + L.item_hdr);
+    int64_t *item_bsum = (int64_t *)(w + L.item_bsum);
+    const int64_t slots = int64_t(bin::kSlots) << L.blog;
+    // 0. everything that starts at zero, by a kernel (no memset nodes when
+    //    the call is captured into a graph)
+    bin::ClearRanges cr = {{(uint32_t *)d_counts, (uint32_t *)hkeys, (uint32_t *)htags, hsize,
+                            ncell},
+                           {2 * n_sets, 2 * slots, slots / 4, slots, 2}};
+    bin::k_bin_clear<<<dim3((unsigned)std::min<int64_t>(blocks_for(2 * slots, 256), 4096),
+                            bin::kClearRanges),
+                       256, 0, s>>>(cr);
+    // 1. cells: find or insert, ranks
+    const int nb = blocks_for(n, bin::kBlock);
+    bin::k_bin_insert<<<nb, bin::kBlock, 0, s>>>(x, y, z, r, d_offsets, n_sets, n, cell, fb,
+                                                L.blog, hkeys, htags, hsize, obj, rec);
+    // 2. the cells in slot order and their first objects
+    const unsigned snb = (unsigned)((slots + bin::kSlotBlock - 1) / bin::kSlotBlock);
+    bin::k_bin_slot_sums<<<snb, bin::kScanBlock, 0, s>>>(htags, hsize, slots, slot_bsum);
+    bin::k_bin_slot_scan<<<1, bin::kScanBlock, 0, s>>>(snb, slot_bsum, ncell);
+    bin::k_bin_slot_prefix<<<snb, bin::kScanBlock, 0, s>>>(htags, hsize, hkeys, slots, slot_bsum,
+                                                          ncell, n, off, ukeys, hvals);
+    // 3. the records grouped by cell
+    bin::k_bin_scatter<<<blocks_for(n, 256), 256, 0, s>>>(n, obj, hvals, perm);
+    bin::k_bin_gather<<<blocks_for(n, 256), 256, 0, s>>>(rec, perm, n, so, sq);
+    PAIRS_HIP_CHECK(hipGetLastError());
+    // 4. 16 lanes per occupied cell, at most a few waves per SIMD of the
+    //    device; 5. the work items' tasks, shared by every wave
+    const int64_t blocks = std::min<int64_t>((n + 15) / 16, (int64_t)st->n_cu * 16);
+    auto count = d_offsets ? bin::k_bin_count<true> : bin::k_bin_count<false>;
+    count<<<(unsigned)blocks, bin::kBlock, 0, s>>>(so, ukeys, off, ncell, (const uint64_t *)htags,
+                                                  hkeys, hvals, L.blog, fb, items, d_counts);
+    const unsigned item_nb =
+        (unsigned)((bin::item_capacity(n) + bin::kScanBlock - 1) / bin::kScanBlock);
+    bin::k_bin_item_sums<<<item_nb, bin::kScanBlock, 0, s>>>(items, item_bsum);
+    bin::k_bin_item_scan<<<1, bin::kScanBlock, 0, s>>>(items, item_bsum, item_hdr);
+    bin::k_bin_item_prefix<<<item_nb, bin::kScanBlock, 0, s>>>(items, item_bsum, item_hdr,
+                                                               item_pre);
+    // at most cap buckets and the sentinel
+    bin::k_bin_item_tab<<<blocks_for(bin::item_capacity(n) + 1, 256), 256, 0, s>>>(
+        item_pre, item_hdr, item_tab);
+    const int64_t item_blocks = std::min<int64_t>(n / (4 * bin::kBigCell) + 1,
+                                                  (int64_t)st->n_cu * 8);
+    bin::k_bin_count_items<<<(unsigned)item_blocks, bin::kBlock, 0, s>>>(
+        so, sq, items, item_pre, item_tab, item_hdr, d_counts);
+    PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;
 }
 
@@ -2472,11 +2529,6 @@ pairs_status_t pairs_debug_single_launch(int kind, int64_t n, int64_t *n_tasks,
 
 pairs_status_t pairs_binned_workspace_size(int64_t n, size_t *bytes) {
     if (!bytes || n < 0 || n > PAIRS_BINNED_MAX_SET_SIZE) return PAIRS_ERR_INVALID_ARG;
-    if (n > 0) {
-        // the sort's storage is sized for the current device
-        int dev;
-        PAIRS_TRY(current_device(&dev));
-    }
     BinnedLayout L;
     PAIRS_TRY(binned_layout(n, &L));
     *bytes = L.total;
@@ -2491,82 +2543,25 @@ pairs_status_t pairs_count_i32_binned(const int32_t *x, const int32_t *y, const 
         return PAIRS_ERR_INVALID_ARG;
     if (cell < PAIRS_BINNED_MIN_CELL || cell > PAIRS_BINNED_MAX_CELL) return PAIRS_ERR_INVALID_ARG;
     if (n > 0 && (!x || !y || !z || !r)) return PAIRS_ERR_INVALID_ARG;
-    BinnedLayout L;
-    PAIRS_TRY(binned_layout(n, &L));
-    if (n > 0 && (!d_ws || ws_bytes < L.total)) return PAIRS_ERR_WORKSPACE;
-    DeviceState *st;
-    PAIRS_TRY(device_state(&st));
-    hipStream_t s = (hipStream_t)stream;
-    if (flags & PAIRS_FLAG_VALIDATE)
-        PAIRS_TRY(run_validation(s, [&](int *flag) {
-            if (n > 0)
-                bin::k_bin_validate<<<blocks_for(n, 256), 256, 0, s>>>(x, y, z, r, n, cell, flag);
-        }));
-    if (n < 2) return fill_u64(d_count, 1, 0, s);
-    unsigned char *w = (unsigned char *)d_ws;
-    uint64_t *keys_in = (uint64_t *)(w + L.keys_in), *keys_out = (uint64_t *)(w + L.keys_out);
-    uint32_t *idx_in = (uint32_t *)(w + L.idx_in), *idx_out = (uint32_t *)(w + L.idx_out);
-    int4 *so = (int4 *)(w + L.so), *rec = (int4 *)(w + L.hkeys);
-    uint64_t *ukeys = (uint64_t *)(w + L.ukeys);
-    uint32_t *sizes = (uint32_t *)(w + L.sizes), *off = (uint32_t *)(w + L.off);
-    uint32_t *runs = (uint32_t *)(w + L.runs);
-    void *temp = w + L.temp;
-    size_t tb = L.temp_bytes;
-    const int nb = blocks_for(n, 256);
-    const int fb = binned_field_bits(cell);
-    size_t need = 0;
-    PAIRS_HIP_CHECK(binned_sort(nullptr, need, nullptr, nullptr, nullptr, nullptr, n, 3 * fb, s));
-    if (need > tb) return PAIRS_ERR_WORKSPACE;
-    uint64_t *hkeys = (uint64_t *)(w + L.hkeys);
-    uint2 *hvals = (uint2 *)(w + L.hvals);
-    uint32_t *hcnt = (uint32_t *)(w + L.hcnt);
-    uint8_t *htags = (uint8_t *)(w + L.htags);
-    uint32_t *item_n = (uint32_t *)(w + L.item_n);
-    const bin::ItemList items{(bin::Item *)(w + L.items), item_n,
-                              (uint32_t)bin::item_capacity(n)};
-    int64_t *item_pre = (int64_t *)(w + L.item_pre);
-    int32_t *item_tab = (int32_t *)(w + L.item_tab);
-    bin::ItemSched *item_hdr = (bin::ItemSched *)(w + L.item_hdr);
-    const int64_t buckets = int64_t(1) << L.blog;
-    bin::ClearRanges cr = {{(uint32_t *)d_count, sizes, (uint32_t *)htags, hcnt, item_n},
-                           {2, n + 1, buckets * bin::kSlots / 4, buckets, 1}};
-    bin::k_bin_clear<<<dim3((unsigned)std::min<int64_t>(blocks_for(n + 1, 256), 2048),
-                            bin::kClearRanges),
-                       256, 0, s>>>(cr);
-    bin::k_bin_keys<<<nb, 256, 0, s>>>(x, y, z, r, n, cell, fb, keys_in, idx_in, rec);
-    PAIRS_HIP_CHECK(hipGetLastError());
-    PAIRS_HIP_CHECK(binned_sort(temp, tb, keys_in, keys_out, idx_in, idx_out, n, 3 * fb, s));
-    int64_t *sq = (int64_t *)(w + L.sq);
-    bin::k_bin_gather<<<nb, 256, 0, s>>>(rec, idx_out, n, so, sq);
-    PAIRS_HIP_CHECK(hipGetLastError());
-    tb = L.temp_bytes;
-    PAIRS_HIP_CHECK(rocprim::run_length_encode(temp, tb, keys_out, (unsigned)n, ukeys, sizes,
-                                               runs, s));
-    tb = L.temp_bytes;
-    PAIRS_HIP_CHECK(rocprim::exclusive_scan(temp, tb, sizes, off, 0u, (size_t)n + 1,
-                                            rocprim::plus<uint32_t>(), s));
-    bin::k_bin_hash_build<<<nb, 256, 0, s>>>(ukeys, off, runs, htags, hkeys, hvals, hcnt, L.blog);
-    // 16 lanes per occupied cell, at most a few waves per SIMD of the device;
-    // then the work items' tasks, shared by every wave
-    const int64_t blocks = std::min<int64_t>((n + 15) / 16, (int64_t)st->n_cu * 16);
-    bin::k_bin_count<<<(unsigned)blocks, bin::kBlock, 0, s>>>(
-        so, ukeys, off, runs, (const uint64_t *)htags, hkeys, hvals, L.blog, fb, items, d_count);
-    int64_t *item_bsum = (int64_t *)(w + L.item_bsum);
-    const unsigned item_nb =
-        (unsigned)((bin::item_capacity(n) + bin::kScanBlock - 1) / bin::kScanBlock);
-    bin::k_bin_item_sums<<<item_nb, bin::kScanBlock, 0, s>>>(items, item_bsum);
-    bin::k_bin_item_scan<<<1, bin::kScanBlock, 0, s>>>(items, item_bsum, item_hdr);
-    bin::k_bin_item_prefix<<<item_nb, bin::kScanBlock, 0, s>>>(items, item_bsum, item_hdr,
-                                                               item_pre);
-    // at most cap buckets and the sentinel
-    bin::k_bin_item_tab<<<blocks_for(bin::item_capacity(n) + 1, 256), 256, 0, s>>>(
-        item_pre, item_hdr, item_tab);
-    const int64_t item_blocks = std::min<int64_t>(n / (4 * bin::kBigCell) + 1,
-                                                  (int64_t)st->n_cu * 8);
-    bin::k_bin_count_items<<<(unsigned)item_blocks, bin::kBlock, 0, s>>>(
-        so, sq, items, item_pre, item_tab, item_hdr, d_count);
-    PAIRS_HIP_CHECK(hipGetLastError());
-    return PAIRS_OK;
+    return binned_common(x, y, z, r, nullptr, 1, n, cell, d_count, d_ws, ws_bytes, flags,
+                         (hipStream_t)stream);
+}
+
+pairs_status_t pairs_count_i32_binned_batched(const int32_t *x, const int32_t *y,
+                                              const int32_t *z, const int32_t *r,
+                                              const int64_t *d_offsets, int64_t n_sets,
+                                              int64_t n_total, int32_t cell, uint64_t *d_counts,
+                                              void *d_ws, size_t ws_bytes, unsigned flags,
+                                              pairs_stream_t stream) {
+    if (n_sets < 0 || n_sets >= INT32_MAX || n_total < 0 || n_total > PAIRS_BINNED_MAX_SET_SIZE ||
+        !d_offsets || (flags & ~PAIRS_FLAG_VALIDATE))
+        return PAIRS_ERR_INVALID_ARG;
+    if (n_sets > 0 && !d_counts) return PAIRS_ERR_INVALID_ARG;
+    if (cell < PAIRS_BINNED_MIN_CELL || cell > PAIRS_BINNED_MAX_CELL) return PAIRS_ERR_INVALID_ARG;
+    if (n_total > 0 && (!x || !y || !z || !r)) return PAIRS_ERR_INVALID_ARG;
+    if (n_sets == 0) return n_total == 0 ? PAIRS_OK : PAIRS_ERR_INVALID_ARG;
+    return binned_common(x, y, z, r, d_offsets, n_sets, n_total, cell, d_counts, d_ws, ws_bytes,
+                         flags, (hipStream_t)stream);
 }
 
 pairs_status_t pairs_lattice_workspace_size(int64_t n_sets, int64_t n_total, int64_t max_n,

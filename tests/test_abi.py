@@ -209,16 +209,28 @@ def test_binned_arguments_are_rejected_on_the_host():
     n_sz = ctypes.c_size_t(0)
     assert L.pairs_binned_workspace_size(-1, ctypes.byref(n_sz)) == INVALID
     assert L.pairs_binned_workspace_size(0, ctypes.byref(n_sz)) == OK
-    # n > 0 sizes the sort's storage for the current device
-    st = L.pairs_binned_workspace_size(1000, ctypes.byref(n_sz))
-    import torch
-    if torch.cuda.device_count() == 0:
-        assert st == NODEV
-    else:
-        assert st == OK and n_sz.value >= 1000 * 100
+    # the size query needs no device: 48 bytes per object plus the table of
+    # at least 2n slots of 21 bytes and the work-item list
+    assert L.pairs_binned_workspace_size(1000, ctypes.byref(n_sz)) == OK
+    assert n_sz.value >= 1000 * (48 + 42)
+    assert L.pairs_binned_workspace_size(1 << 30, ctypes.byref(n_sz)) == OK
+    assert L.pairs_binned_workspace_size((1 << 30) + 1, ctypes.byref(n_sz)) == INVALID
     assert L.pairs_count_i32_binned(x, y, z, r, -1, 64, out, ws, 0, 0, None) == INVALID
     assert L.pairs_count_i32_binned(x, y, z, r, 10, 16, out, ws, 0, 0, None) == INVALID
     assert L.pairs_count_i32_binned(x, y, z, r, 10, 1 << 26, out, ws, 0, 0, None) == INVALID
     assert L.pairs_count_i32_binned(x, y, z, r, 10, 64, None, ws, 0, 0, None) == INVALID
     assert L.pairs_count_i32_binned(None, y, z, r, 10, 64, out, ws, 0, 0, None) == INVALID
     assert L.pairs_count_i32_binned(x, y, z, r, 10, 64, out, ws, 0, 0x10, None) == INVALID
+    off = fake(7)
+    B = L.pairs_count_i32_binned_batched
+    assert B(x, y, z, r, off, -1, 10, 64, out, ws, 0, 0, None) == INVALID
+    assert B(x, y, z, r, None, 2, 10, 64, out, ws, 0, 0, None) == INVALID
+    assert B(x, y, z, r, off, 2, 10, 64, None, ws, 0, 0, None) == INVALID
+    assert B(x, y, z, r, off, 2, 10, 16, out, ws, 0, 0, None) == INVALID
+    assert B(None, y, z, r, off, 2, 10, 64, out, ws, 0, 0, None) == INVALID
+    assert B(x, y, z, r, off, 2, 10, 64, out, ws, 0, 0x10, None) == INVALID
+    assert B(x, y, z, r, off, 0, 10, 64, out, ws, 0, 0, None) == INVALID
+    assert B(x, y, z, r, off, 0, 0, 64, out, ws, 0, 0, None) == OK
+    # cells of 32 take 3 x 21 key bits, so a batch of two sets needs 64 bits
+    # and one of three sets 65
+    assert B(x, y, z, r, off, 3, 10, 32, out, ws, 1 << 20, 0, None) == INVALID

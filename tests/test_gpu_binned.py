@@ -159,3 +159,126 @@ def test_big_cells_next_to_small_and_big():
     r = rng.integers(0, cell // 2, len(x), endpoint=True).astype(np.int32)
     announce("binned big cells next to small and big", len(x))
     assert binned([x, y, z, r], cell) == oracle.count_i32(x, y, z, r)
+
+
+# ------------------------------------------------------------ CSR batches --
+
+def binned_batched(arrays, off, cell, flags=0, ws=None):
+    import torch
+    t = dev(*arrays)
+    toff = dev(off)[0]
+    out = torch.full((len(off) - 1,), -1, dtype=torch.int64, device="cuda")
+    P.pairs_count_i32_binned_batched(*t, toff, cell, out, ws=ws, flags=flags)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def overlapping_batch(sizes, seed, span, cell):
+    """Sets that all occupy the same region, so that pairs across sets touch
+    as often as pairs within one: a count that leaked across sets would be
+    far off."""
+    off = w.offsets_from_sizes(np.array(sizes, np.int64))
+    a = spheres(int(off[-1]), seed, -span, span, cell // 2)
+    return off, a
+
+
+@pytest.mark.parametrize("sizes,span,cell", [
+    ([0, 1, 2, 3, 0, 50, 0], 100, 64),
+    ([2000, 1, 0, 3000, 17, 2], 600, 64),           # crowded cells: work items
+    ([500] * 40, 1 << 12, 256),
+    ([150, 180], 2000, 32),                          # cells of 32: 63 key bits and 1 set bit
+])
+def test_batched_matches_oracle_per_set(sizes, span, cell):
+    off, a = overlapping_batch(sizes, len(sizes) + cell, span, cell)
+    announce("binned batched", len(sizes), span, cell)
+    got = binned_batched(a, off, cell)
+    for s in range(len(sizes)):
+        lo, hi = int(off[s]), int(off[s + 1])
+        assert got[s] == oracle.count_i32(*[v[lo:hi] for v in a]), s
+
+
+def test_batched_one_set_equals_single_call():
+    a = spheres(30000, 5, -(1 << 14), 1 << 14, 128)
+    off = np.array([0, 30000], np.int64)
+    announce("binned batched one set")
+    assert binned_batched(a, off, 256)[0] == binned(a, 256) == oracle.count_i32(*a)
+
+
+def test_batched_config4_full_size(golden_dir):
+    """Config 4's 200 000 sets, each the content of one 2^14 cell, binned
+    again inside each set: cells of 2^14 (one cell per set, so every set of
+    more than 64 objects is a work item) and of 4096 (up to 64 cells per
+    set); the per-set counts equal the stored oracle counts."""
+    import hashlib
+    with open(os.path.join(golden_dir, "config_values.json")) as f:
+        g = json.load(f)["config4_counts"]
+    b = w.config4()
+    for cell in (1 << 14, 4096):
+        announce("binned batched config 4", cell)
+        got = binned_batched(b.objs.arrays(), b.offsets, cell)
+        assert int(got.sum()) == g["total"]
+        assert hashlib.sha256(got.astype("<u8").tobytes()).hexdigest() == g["sha256_le_u64"]
+
+
+def test_batched_validation_and_key_bits():
+    off, a = overlapping_batch([10, 20, 30], 3, 100, 32)
+    announce("binned batched validation")
+    # cells of 32: 63 key bits, no room for three sets
+    with pytest.raises(P.PairsError) as e:
+        binned_batched(a, off, 32)
+    assert e.value.status == -1
+    bad = off.copy()
+    bad[1] = 25  # offsets must not decrease
+    bad[2] = 20
+    with pytest.raises(P.PairsError):
+        binned_batched(a, bad, 64, flags=P.FLAG_VALIDATE)
+    big = [v.copy() for v in a]
+    big[3][7] = 40  # radius above cell / 2
+    with pytest.raises(P.PairsError) as e:
+        binned_batched(big, off, 64, flags=P.FLAG_VALIDATE)
+    assert e.value.status == -2
+    got = binned_batched(a, off, 64, flags=P.FLAG_VALIDATE)
+    for s in range(3):
+        lo, hi = int(off[s]), int(off[s + 1])
+        assert got[s] == oracle.count_i32(*[v[lo:hi] for v in a])
+
+
+def test_binned_calls_in_a_graph():
+    """A single-set and a batched binned count captured into one graph and
+    replayed three times, with eager binned calls of other sizes on the same
+    workspaces in between and the outputs overwritten before each replay:
+    every replay gives the oracle's counts."""
+    import torch
+    a = spheres(20000, 61, -(1 << 13), 1 << 13, 64)
+    off, b = overlapping_batch([3000, 0, 1, 5000, 700], 62, 3000, 128)
+    ta, tb, toff = dev(*a), dev(*b), dev(off)[0]
+    wa = torch.empty(P.pairs_binned_workspace_size(20000), dtype=torch.uint8, device="cuda")
+    wb = torch.empty(P.pairs_binned_workspace_size(int(off[-1])), dtype=torch.uint8,
+                     device="cuda")
+    oa = torch.empty(1, dtype=torch.int64, device="cuda")
+    ob = torch.empty(len(off) - 1, dtype=torch.int64, device="cuda")
+    want_a = oracle.count_i32(*a)
+    want_b = [oracle.count_i32(*[v[int(off[s]):int(off[s + 1])] for v in b])
+              for s in range(len(off) - 1)]
+    # warm the library's device state outside the capture
+    P.pairs_count_i32_binned(*ta, 128, oa, wa)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        P.pairs_count_i32_binned(*ta, 128, oa, wa)
+        P.pairs_count_i32_binned_batched(*tb, toff, 128, ob, wb)
+    announce("binned graph replays")
+    other = spheres(5000, 63, -500, 500, 16)
+    for rep in range(3):
+        oa.fill_(-7)
+        ob.fill_(-7)
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(oa.item()) == want_a, rep
+        assert list(ob.cpu().numpy()) == want_b, rep
+        # eager work on the same workspaces between replays
+        P.pairs_count_i32_binned(*dev(*other), 32, oa, wa)
+        P.pairs_count_i32_binned_batched(*dev(*other), dev(np.array([0, 2500, 5000]))[0], 64,
+                                         ob[:2], wb)
+        torch.cuda.synchronize()
+        assert int(oa.item()) == oracle.count_i32(*other)
