@@ -149,6 +149,28 @@ def timed_steps(fn, steps, warmup):
     return ms, wall
 
 
+def sclk_during(fn, seconds=0.25):
+    """Mean engine clock (MHz) while fn runs back to back for about `seconds`
+    (None where the clock is not exposed): the VALU fraction of a kernel at
+    the clock it actually ran at."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    reps = max(1, int(seconds / max(time.perf_counter() - t0, 1e-5)))
+    with SclkSampler() as sclk:
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+    return sclk.mean_mhz()
+
+
+def at_sclk(frac, mhz):
+    """A VALU fraction of the nominal 2.4 GHz peak restated at a measured clock."""
+    return frac * SCLK_HZ / (mhz * 1e6) if mhz else None
+
+
 def valu_probe(torch):
     """Lane-operations per second of each probe pattern, as a fraction of the
     256 CU x 64 lane x 2.4 GHz issue peak."""
@@ -369,10 +391,12 @@ def bench_batched(P, w, torch, np, dev, steps):
     log(f"[bench] batched count_i32: {b.n_sets} sets, {pairs} pair tests")
     ms, _ = timed_steps(lambda: plan.execute((x, y, z, r), (counts,)), max(5, steps), 2)
     m = float(np.mean(ms))
+    mhz = sclk_during(lambda: plan.execute((x, y, z, r), (counts,)))
+    frac = pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK
     out["count_i32_binned_200k_sets"] = {
         "workload": "200000 sets, sizes lognormal(4,1.2) clipped to [2,8192], seed 5",
         "pair_tests": pairs, "ms": m, "G_pairs_per_s": pairs / m / 1e6,
-        "valu_frac": pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK,
+        "valu_frac": frac, "sclk_mhz_measured": mhz, "valu_frac_at_measured_sclk": at_sclk(frac, mhz),
         "n_tasks": plan.info()["n_tasks"], "total_count": int(counts.sum().item()),
         "matches_oracle": hashlib.sha256(counts.cpu().numpy().astype("<u8").tobytes()).hexdigest()
                           == golden()["config4_counts"]["sha256_le_u64"]}
@@ -382,10 +406,12 @@ def bench_batched(P, w, torch, np, dev, steps):
     ms, _ = timed_steps(lambda: P.pairs_count_i32_batched(x, y, z, r, toff, counts, ws),
                         max(5, steps), 2)
     m = float(np.mean(ms))
+    mhz = sclk_during(lambda: P.pairs_count_i32_batched(x, y, z, r, toff, counts, ws))
+    frac = pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK
     out.update(bench_binned_config4(P, torch, np, dev, b, (x, y, z, r), toff))
     out["count_i32_binned_200k_sets_unplanned"] = {
         "ms": m, "G_pairs_per_s": pairs / m / 1e6,
-        "valu_frac": pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK,
+        "valu_frac": frac, "sclk_mhz_measured": mhz, "valu_frac_at_measured_sclk": at_sclk(frac, mhz),
         "matches_oracle": hashlib.sha256(counts.cpu().numpy().astype("<u8").tobytes()).hexdigest()
                           == golden()["config4_counts"]["sha256_le_u64"]}
     plan.close()
@@ -404,6 +430,8 @@ def bench_batched(P, w, torch, np, dev, steps):
     log(f"[bench] graph of {nsteps} steps: {b5.n_sets} sets, {pairs5} pair tests per step")
     ms, _ = timed_steps(lambda: g.launch(), 3, 1)
     m = float(np.mean(ms)) / nsteps
+    mhz = sclk_during(lambda: g.launch())
+    frac = pairs5 / (m * 1e-3) * C_ALG["energy_count_f32"] / VALU_PEAK
     ms_j, _ = timed_steps(lambda: P.pairs_jitter_f32(x, y, z, 6, 0, 1e-3), 20, 2)
     # one more replay from the initial positions, checked on sampled sets at
     # steps 0, 49 and 99 against the oracle's stored values
@@ -423,7 +451,7 @@ def bench_batched(P, w, torch, np, dev, steps):
         "workload": "50000 sets, sizes lognormal(5,1) clipped to [2,4096], seed 6; "
                     "per step: jitter + per-set energy and pinned-fp32 count (r=0.01)",
         "pair_tests_per_step": pairs5, "ms_per_step": m, "G_pairs_per_s": pairs5 / m / 1e6,
-        "valu_frac": pairs5 / (m * 1e-3) * C_ALG["energy_count_f32"] / VALU_PEAK,
+        "valu_frac": frac, "sclk_mhz_measured": mhz, "valu_frac_at_measured_sclk": at_sclk(frac, mhz),
         "jitter_ms": float(np.mean(ms_j)),
         "max_rel_err_per_set_energy_vs_fp64_oracle": float(max(errs)),
         "counts_match_oracle": exact,
@@ -644,11 +672,14 @@ def main():
         log(f"[bench] energy_f32 N={n3}")
         ms3, _ = timed_steps(lambda: P.pairs_energy_f32(*t3, 1e-4, E, tot), max(3, a.steps // 2), 1)
         m3 = float(np.mean(ms3))
+        mhz3 = sclk_during(lambda: P.pairs_energy_f32(*t3, 1e-4, E, tot))
+        frac3 = pp3 / (m3 * 1e-3) * C_ALG["energy_f32"] / VALU_PEAK
         ge = golden()["config3_energy_rows"]
         got_rows = E[torch.tensor(ge["rows"], device=dev)].cpu().numpy()
         want_rows = np.array(ge["E"])
         sec["energy_f32_2^18"] = {"ms": m3, "G_pairs_per_s": pp3 / m3 / 1e6,
-                                  "valu_frac": pp3 / (m3 * 1e-3) * C_ALG["energy_f32"] / VALU_PEAK,
+                                  "valu_frac": frac3, "sclk_mhz_measured": mhz3,
+                                  "valu_frac_at_measured_sclk": at_sclk(frac3, mhz3),
                                   "total": float(tot.item()),
                                   "rel_err_total_vs_fp64_oracle":
                                       abs(float(tot.item()) - golden()["config3_energy_total"])
@@ -676,11 +707,14 @@ def main():
         Fxyz = [torch.empty(n3, dtype=torch.float64, device=dev) for _ in range(3)]
         ms4, _ = timed_steps(lambda: P.pairs_force_f32(*t3, 1e-4, *Fxyz), max(3, a.steps // 2), 1)
         m4 = float(np.mean(ms4))
+        mhz4 = sclk_during(lambda: P.pairs_force_f32(*t3, 1e-4, *Fxyz))
+        frac4 = pp3 / (m4 * 1e-3) * C_ALG["force_f32"] / VALU_PEAK
         gf = golden()["config3_force_rows"]
         got = np.stack([f[torch.tensor(gf["rows"], device=dev)].cpu().numpy() for f in Fxyz], 1)
         err = float((np.abs(got - np.array(gf["F"])).max(axis=1) / np.array(gf["S"])).max())
         sec["force_f32_2^18"] = {"ms": m4, "G_pairs_per_s": pp3 / m4 / 1e6,
-                                 "valu_frac": pp3 / (m4 * 1e-3) * C_ALG["force_f32"] / VALU_PEAK,
+                                 "valu_frac": frac4, "sclk_mhz_measured": mhz4,
+                                 "valu_frac_at_measured_sclk": at_sclk(frac4, mhz4),
                                  "per_pair_ops": C_ALG["force_f32"],
                                  "max_err_over_norm_sum_vs_fp64_oracle": err,
                                  "sampled_rows": len(gf["rows"])}
