@@ -480,11 +480,15 @@ __device__ __forceinline__ uint64_t count_cell(int64_t a0, int64_t n, uint64_t k
     if (gl < 13) nb = find_cell(htags, hkeys, hvals, blog, neighbour_key(key, gl, fb));
     const bool big = n > kBigCell;
     // ranges with a big side go to the item list: the cell's own pairs, and
-    // those with each big (or, for a big cell, every) occupied neighbour
+    // those with each big (or, for a big cell, every) occupied neighbour,
+    // with the larger range as the rows (more rows per lane, so each staged
+    // partner feeds more tests)
+    const bool swap = nb.y > (uint32_t)n;
     push_items(items, big && gl == 0,
                Item{(uint32_t)a0, (uint32_t)n, (uint32_t)a0, (uint32_t)n, set},
                gl < 13 && nb.y != 0 && (big || nb.y > (uint32_t)kBigCell),
-               Item{(uint32_t)a0, (uint32_t)n, nb.x, nb.y, set});
+               Item{swap ? nb.x : (uint32_t)a0, swap ? nb.y : (uint32_t)n,
+                    swap ? (uint32_t)a0 : nb.x, swap ? (uint32_t)n : nb.y, set});
     if (big) return 0;
     const int64_t h = (n - 1) / 2;
     for (int64_t i = gl; n >= 2 && i < n; i += G) {
@@ -737,6 +741,8 @@ __device__ __forceinline__ uint32_t item_task(const int4 *__restrict__ so,
         q = sq[j];
     };
     constexpr int PU = 8 / K;
+    const int rlast = min(ra + kWave * K, (int)it.na) - 1;
+    const int core_lo = rlast + 1, core_hi = self ? ra + band.steps(ra) : INT32_MAX;
     uint32_t cnt = 0;
     int4 no;
     int64_t nq;
@@ -747,7 +753,9 @@ __device__ __forceinline__ uint32_t item_task(const int4 *__restrict__ so,
         fetch(g0 + kWave + lane, no, nq);  // in flight while this group is counted
         wave_sync();
         const int gn = __builtin_amdgcn_readfirstlane(min(kWave, u1 - g0));
-        if (self) {
+        // a cell's own pairs need the ownership mask only at the band's edges:
+        // every row of the block owns the partners in [core_lo, core_hi]
+        if (self && !(g0 >= core_lo && g0 + gn - 1 <= core_hi)) {
             for (int q = 0; q < gn; ++q) {
                 const PartnerI32 b = wp[q];
                 const int64_t qb = wq[q];
