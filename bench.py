@@ -373,8 +373,55 @@ def assignment_comparison(torch, x, y, z, r, n, want, steps):
             ms[name] = float(np.mean(t))
         res[f"rows_per_lane_{K}"] = {"balanced_ms": ms["balanced"],
                                      "straightforward_ms": ms["straightforward"],
-                                     "speedup": ms["straightforward"] / ms["balanced"]}
+                                     "speedup": ms["straightforward"] / ms["balanced"],
+                                     "waves": {name: wave_timeline(L, torch, np, variant, x, y, z,
+                                                                   r, n, K, out, stream)
+                                               for variant, name in ((0, "balanced"),
+                                                                     (1, "straightforward"))}}
     return res
+
+
+def wave_timeline(L, torch, np, variant, x, y, z, r, n, K, out, stream):
+    """One timed run of the comparison kernel: every wave's start and end on
+    the device's wall clock, summarised as the span, the waves' durations,
+    the mean number of waves running over the span against the most that ran
+    at once, the time at the end with fewer than 90 % of that maximum running,
+    and the rank correlation of start order with row-block order."""
+    import ctypes
+    t = L.pairs_ab_count_i32_timed
+    t.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_int,
+                                                           ctypes.c_void_p, ctypes.c_void_p,
+                                                           ctypes.c_void_p]
+    t.restype = ctypes.c_int
+    L.pairs_ab_waves.argtypes = [ctypes.c_int64, ctypes.c_int]
+    L.pairs_ab_waves.restype = ctypes.c_int64
+    waves = L.pairs_ab_waves(n, K)
+    times = torch.zeros(2 * waves, dtype=torch.int64, device=x.device)
+    if t(variant, x.data_ptr(), y.data_ptr(), z.data_ptr(), r.data_ptr(), n, K, out.data_ptr(),
+         times.data_ptr(), stream) != 0:
+        raise RuntimeError("pairs_ab_count_i32_timed failed")
+    torch.cuda.synchronize()
+    khz = ctypes.c_int64(0)
+    L.pairs_ab_wall_clock_khz(ctypes.byref(khz))
+    tt = times.cpu().numpy().reshape(-1, 2).astype(np.float64)
+    t0 = tt[:, 0].min()
+    st, en = (tt[:, 0] - t0) / khz.value, (tt[:, 1] - t0) / khz.value  # ms
+    span = float(en.max())
+    ev = np.concatenate([np.stack([st, np.ones_like(st)], 1), np.stack([en, -np.ones_like(en)], 1)])
+    ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]
+    active = np.cumsum(ev[:, 1])
+    dt = np.diff(ev[:, 0], append=span)
+    peak = float(active.max())
+    above = np.nonzero(active >= 0.9 * peak)[0]
+    last_full = float(ev[above[-1], 0] + dt[above[-1]]) if len(above) else 0.0
+    order = np.argsort(np.argsort(st))
+    rank_corr = float(np.corrcoef(order, np.arange(len(st)))[0, 1]) if len(st) > 1 else 1.0
+    dur = en - st
+    return {"span_ms": span, "wave_ms_mean": float(dur.mean()), "wave_ms_min": float(dur.min()),
+            "wave_ms_max": float(dur.max()), "max_running": int(peak),
+            "mean_running_over_span": float((active * dt).sum() / span),
+            "tail_ms_below_90pct": span - last_full,
+            "start_order_vs_block_order_rank_corr": rank_corr}
 
 
 def bench_batched(P, w, torch, np, dev, steps):

@@ -34,6 +34,21 @@ int pairs_ab_count_i32(int variant, const int32_t *x, const int32_t *y, const in
                        const int32_t *r, int64_t n, int rows_per_lane, uint64_t *d_count,
                        void *stream);
 
+/*
+ * The same run with the start and end of every wave on the device's
+ * constant-rate wall clock (the dispatch-order evidence of the comparison):
+ * d_times is a device uint64 array of 2 * pairs_ab_waves(n, rows_per_lane)
+ * entries, the start of wave w (row block w) at [2w] and its end at [2w+1].
+ * Returns as pairs_ab_count_i32, and -1 for a null d_times.
+ */
+int64_t pairs_ab_waves(int64_t n, int rows_per_lane);
+int pairs_ab_count_i32_timed(int variant, const int32_t *x, const int32_t *y, const int32_t *z,
+                             const int32_t *r, int64_t n, int rows_per_lane, uint64_t *d_count,
+                             uint64_t *d_times, void *stream);
+
+/* Ticks per millisecond of that clock on the current device (0 on success). */
+int pairs_ab_wall_clock_khz(int64_t *khz);
+
 #ifdef __cplusplus
 }
 #endif

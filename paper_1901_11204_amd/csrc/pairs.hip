@@ -1,20 +1,20 @@
 // libpairs: all-pairs interactions within sets of objects, for gfx950.
 //
-// Kernels (the wave-task bodies are in tasks.h):
-//   single set : one wave per task, tasks enumerated row block by chunk;
-//   batched    : one persistent grid; each wave walks the task list with a
-//                grid stride.  The task list is either a table built on the
-//                host by a plan (set, local task) sorted so that the tasks of
-//                the largest size class come first, or, for unplanned calls,
-//                per-class prefix sums built on the device by one scheduling
-//                kernel, searched by each wave;
+// Kernels (the wave-task bodies are in tasks.h and steps.h):
+//   single set : tasks (row block x partner chunk) enumerated row block by
+//                chunk; each wave takes tasks with a grid stride over the
+//                64-bit task index;
+//   batched    : persistent grids.  A plan gives each wave a task list
+//                balanced on the host (longest processing time first); an
+//                unplanned call builds a class-major task prefix and a
+//                bucket table on the device (four small kernels) and the
+//                waves take tasks with a grid stride;
 //   jitter     : the per-step perturbation of the repeated-step workload;
 //   lattice    : collision and contact counts of lattice beads (lattice.h);
-//   binned     : the count of one set through a uniform grid of cells
-//                (binning.h; the sort, run-length encoding and scan are
-//                rocPRIM's);
+//   binned     : counts through a uniform grid of cells, objects grouped by
+//                cell through a hash table (binning.h);
 //   helpers    : fills (in place of memsets, so every launch can be
-//                captured into a graph), validation.
+//                captured into a graph), validation, fixed-point finishes.
 #include <hip/hip_runtime.h>
 
 #include <math.h>

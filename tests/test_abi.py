@@ -138,8 +138,11 @@ def test_comparison_library_exports_and_checks_arguments():
     text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "pairs_ab.h")).read(),
                   flags=re.S)
     names = sorted(set(re.findall(r"\b(pairs_[a-z0-9_]+)\s*\(", text)))
-    assert names == ["pairs_ab_count_i32"]
+    assert names == ["pairs_ab_count_i32", "pairs_ab_count_i32_timed", "pairs_ab_wall_clock_khz",
+                     "pairs_ab_waves"]
     L = ctypes.CDLL(B.AB_LIB)
+    for name in names:
+        assert hasattr(L, name), name
     f = L.pairs_ab_count_i32
     f.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_int,
                                                            ctypes.c_void_p, ctypes.c_void_p]
@@ -150,6 +153,18 @@ def test_comparison_library_exports_and_checks_arguments():
     assert f(0, None, y, z, r, 10, 1, out, None) == -1   # missing input
     assert f(1, x, y, z, r, 10, 1, None, None) == -1     # missing output
     assert f(1, x, y, z, r, -1, 1, out, None) == -1
+    t = L.pairs_ab_count_i32_timed
+    t.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_int,
+                                                           ctypes.c_void_p, ctypes.c_void_p,
+                                                           ctypes.c_void_p]
+    t.restype = ctypes.c_int
+    assert t(0, x, y, z, r, 10, 1, out, None, None) == -1   # no timestamp buffer
+    assert t(2, x, y, z, r, 10, 1, out, fake(5), None) == -1
+    wv = L.pairs_ab_waves
+    wv.argtypes = [ctypes.c_int64, ctypes.c_int]
+    wv.restype = ctypes.c_int64
+    assert wv(1 << 20, 1) == 16384 and wv(1 << 20, 8) == 2048 and wv(65, 1) == 2
+    assert wv(1, 1) == 0 and wv(100, 4) == 0
 
 
 def test_lattice_arguments_are_rejected_on_the_host():

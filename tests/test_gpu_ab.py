@@ -49,3 +49,35 @@ def test_ab_variants_agree_on_config1():
     for variant in (0, 1):
         for K in (1, 8):
             assert ab_count(variant, s.arrays(), K) == want
+
+
+@pytest.mark.parametrize("K", [1, 8])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_ab_timed_run_records_every_wave(variant, K):
+    """The timed run gives the same count and a start no later than the end
+    for every wave (row block) of the launch."""
+    import torch
+    L = ab_lib()
+    L.pairs_ab_count_i32_timed.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 4 + [
+        ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.pairs_ab_count_i32_timed.restype = ctypes.c_int
+    L.pairs_ab_waves.argtypes = [ctypes.c_int64, ctypes.c_int]
+    L.pairs_ab_waves.restype = ctypes.c_int64
+    s = w.spheres_i32(5000, 77, 64, 6, radius_lo=0)
+    n = 5000
+    waves = L.pairs_ab_waves(n, K)
+    assert waves == (n + 64 * K - 1) // (64 * K)
+    x, y, zz, r = dev(*s.arrays())
+    out = torch.empty(1, dtype=torch.int64, device="cuda")
+    times = torch.zeros(2 * waves, dtype=torch.int64, device="cuda")
+    announce("ab timed", variant, K)
+    rc = L.pairs_ab_count_i32_timed(variant, x.data_ptr(), y.data_ptr(), zz.data_ptr(),
+                                    r.data_ptr(), n, K, out.data_ptr(), times.data_ptr(),
+                                    torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert int(out.item()) == oracle.count_i32(*s.arrays())
+    t = times.cpu().numpy().reshape(-1, 2)
+    assert np.all(t[:, 0] > 0) and np.all(t[:, 1] >= t[:, 0])
+    khz = ctypes.c_int64(0)
+    assert L.pairs_ab_wall_clock_khz(ctypes.byref(khz)) == 0 and khz.value > 0
