@@ -886,7 +886,9 @@ __global__ __launch_bounds__(kBlock, (batched_min_waves<KindV, KMAX>())) void k_
             d.a = r0;
             d.b = s0;
             d.c = T;
-            d.K = (uint8_t)ct.K[c];
+            // a last row block of at most 64 rows (a whole small set, or the
+            // tail of a larger one) runs one row per lane, as in plans
+            d.K = (uint8_t)(n - r0 <= kWave ? 1 : ct.K[c]);
             d.form = PAIRS_FORM_STEPPING;
             d.m = 1;
             d.x = (uint8_t)x;
@@ -2106,7 +2108,10 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
                 continue;
             }
             const StepTiling til = StepTiling::of(band, K, ct.U[c]);
-            for (int b = 0; b < til.nblocks; ++b)
+            for (int b = 0; b < til.nblocks; ++b) {
+                // a last row block of at most 64 rows runs one row per lane,
+                // so that it does not leave half of its lanes' rows empty
+                const int Kb = (K > 1 && n - b * til.rows <= kWave) ? 1 : K;
                 for (int ch = 0; ch < til.nchunks; ++ch) {
                     int r0, s0, T, x;
                     step_range(band, til, b, ch, &r0, &s0, &T, &x);
@@ -2118,13 +2123,14 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
                     d.a = r0;
                     d.b = s0;
                     d.c = T;
-                    d.K = (uint8_t)K;
+                    d.K = (uint8_t)Kb;
                     d.form = PAIRS_FORM_STEPPING;
                     d.m = 1;
                     d.x = (uint8_t)x;
-                    if (!add(d, step_cost(K, T, x, step_window_entries(K, kWave, T, x), kWave)))
+                    if (!add(d, step_cost(Kb, T, x, step_window_entries(Kb, kWave, T, x), kWave)))
                         return PAIRS_ERR_NO_MEMORY;
                 }
+            }
             continue;
         }
         const Tiling til = Tiling::of(band, ct.K[c], ct.U[c]);
