@@ -152,7 +152,9 @@ def timed_steps(fn, steps, warmup):
 def sclk_during(fn, seconds=0.25):
     """Mean engine clock (MHz) while fn runs back to back for about `seconds`
     (None where the clock is not exposed): the VALU fraction of a kernel at
-    the clock it actually ran at."""
+    the clock it actually ran at.  Run before a line's timed steps, it is
+    also their warm-up: a millisecond-scale call timed after two warm-up
+    calls reads up to a tenth slower than in steady state."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -436,9 +438,9 @@ def bench_batched(P, w, torch, np, dev, steps):
     counts = torch.empty(b.n_sets, dtype=torch.int64, device=dev)
     plan = P.Plan(P.KIND_COUNT_I32, b.offsets)
     log(f"[bench] batched count_i32: {b.n_sets} sets, {pairs} pair tests")
-    ms, _ = timed_steps(lambda: plan.execute((x, y, z, r), (counts,)), max(5, steps), 2)
-    m = float(np.mean(ms))
     mhz = sclk_during(lambda: plan.execute((x, y, z, r), (counts,)))
+    ms, _ = timed_steps(lambda: plan.execute((x, y, z, r), (counts,)), max(10, steps), 2)
+    m = float(np.mean(ms))
     frac = pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK
     out["count_i32_binned_200k_sets"] = {
         "workload": "200000 sets, sizes lognormal(4,1.2) clipped to [2,8192], seed 5",
@@ -450,10 +452,10 @@ def bench_batched(P, w, torch, np, dev, steps):
     toff = torch.from_numpy(b.offsets).to(dev)
     ws = torch.empty(P.pairs_batched_workspace_size(b.n_sets, b.n_total), dtype=torch.uint8,
                      device=dev)
-    ms, _ = timed_steps(lambda: P.pairs_count_i32_batched(x, y, z, r, toff, counts, ws),
-                        max(5, steps), 2)
-    m = float(np.mean(ms))
     mhz = sclk_during(lambda: P.pairs_count_i32_batched(x, y, z, r, toff, counts, ws))
+    ms, _ = timed_steps(lambda: P.pairs_count_i32_batched(x, y, z, r, toff, counts, ws),
+                        max(10, steps), 2)
+    m = float(np.mean(ms))
     frac = pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK
     out.update(bench_binned_config4(P, torch, np, dev, b, (x, y, z, r), toff))
     out["count_i32_binned_200k_sets_unplanned"] = {
@@ -475,9 +477,9 @@ def bench_batched(P, w, torch, np, dev, steps):
     g = plan5.capture_steps(x, y, z, r, seed=6, sigma=1e-3, first_step=0, n_steps=nsteps,
                             eps2=1e-4, energy=E, counts=C)
     log(f"[bench] graph of {nsteps} steps: {b5.n_sets} sets, {pairs5} pair tests per step")
+    mhz = sclk_during(lambda: g.launch())
     ms, _ = timed_steps(lambda: g.launch(), 3, 1)
     m = float(np.mean(ms)) / nsteps
-    mhz = sclk_during(lambda: g.launch())
     frac = pairs5 / (m * 1e-3) * C_ALG["energy_count_f32"] / VALU_PEAK
     ms_j, _ = timed_steps(lambda: P.pairs_jitter_f32(x, y, z, 6, 0, 1e-3), 20, 2)
     # one more replay from the initial positions, checked on sampled sets at
@@ -717,9 +719,9 @@ def main():
         tot = torch.empty(1, dtype=torch.float64, device=dev)
         pp3 = n3 * (n3 - 1) // 2
         log(f"[bench] energy_f32 N={n3}")
+        mhz3 = sclk_during(lambda: P.pairs_energy_f32(*t3, 1e-4, E, tot))
         ms3, _ = timed_steps(lambda: P.pairs_energy_f32(*t3, 1e-4, E, tot), max(3, a.steps // 2), 1)
         m3 = float(np.mean(ms3))
-        mhz3 = sclk_during(lambda: P.pairs_energy_f32(*t3, 1e-4, E, tot))
         frac3 = pp3 / (m3 * 1e-3) * C_ALG["energy_f32"] / VALU_PEAK
         ge = golden()["config3_energy_rows"]
         got_rows = E[torch.tensor(ge["rows"], device=dev)].cpu().numpy()
@@ -752,9 +754,9 @@ def main():
         del t3d
         log(f"[bench] force_f32 N={n3}")
         Fxyz = [torch.empty(n3, dtype=torch.float64, device=dev) for _ in range(3)]
+        mhz4 = sclk_during(lambda: P.pairs_force_f32(*t3, 1e-4, *Fxyz))
         ms4, _ = timed_steps(lambda: P.pairs_force_f32(*t3, 1e-4, *Fxyz), max(3, a.steps // 2), 1)
         m4 = float(np.mean(ms4))
-        mhz4 = sclk_during(lambda: P.pairs_force_f32(*t3, 1e-4, *Fxyz))
         frac4 = pp3 / (m4 * 1e-3) * C_ALG["force_f32"] / VALU_PEAK
         gf = golden()["config3_force_rows"]
         got = np.stack([f[torch.tensor(gf["rows"], device=dev)].cpu().numpy() for f in Fxyz], 1)
