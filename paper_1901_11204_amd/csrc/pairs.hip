@@ -45,6 +45,12 @@ namespace {
 
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
+// The batched kernels run one wave per workgroup: a wave's LDS window is its
+// workgroup's, so a wave that finishes early frees its slot at once rather
+// than when the slowest wave of a four-wave workgroup is done (the unplanned
+// config-4 call: 1.49 -> 1.43 ms).
+constexpr int kBatchWaves = 1;
+constexpr int kBatchBlock = kWave * kBatchWaves;
 
 thread_local hipError_t g_last_hip_error = hipSuccess;
 
@@ -812,7 +818,7 @@ __device__ __forceinline__ void run_task(const BatchIO &io, int64_t base, const 
 // the current task runs.
 // Wave lists of a plan per resident wave, and blocks of an unplanned call per
 // resident block.
-constexpr int kPlanWaveFactor = 8;
+constexpr int kPlanWaveFactor = 16;
 constexpr int kScanBlockFactor = 16;
 
 // Waves per SIMD the batched kernels are compiled for: four where the
@@ -824,15 +830,15 @@ constexpr int batched_min_waves() {
 }
 
 template <int KindV, int KMAX>
-__global__ __launch_bounds__(kBlock, (batched_min_waves<KindV, KMAX>())) void k_batched_plan(BatchIO io,
+__global__ __launch_bounds__(kBatchBlock, (batched_min_waves<KindV, KMAX>())) void k_batched_plan(BatchIO io,
                                                          const TaskDesc *__restrict__ descs,
                                                          const int32_t *__restrict__ wave_start,
                                                          int64_t n_waves) {
     constexpr int kLdsBytes = batched_lds_bytes<KindV>();
-    __shared__ __align__(16) unsigned char lds[kWavesPerBlock * kLdsBytes];
+    __shared__ __align__(16) unsigned char lds[kBatchWaves * kLdsBytes];
     const int wave = wave_id();
     void *win = lds + wave * kLdsBytes;
-    const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+    const int64_t w = (int64_t)blockIdx.x * kBatchWaves + wave;
     if (w >= n_waves) return;
     int i = wave_start[w];
     const int e = wave_start[w + 1];
@@ -855,15 +861,15 @@ __global__ __launch_bounds__(kBlock, (batched_min_waves<KindV, KMAX>())) void k_
 // Unplanned calls: tasks decoded from the device-built prefix sums, taken by
 // the waves with a grid stride.
 template <int KindV, int KMAX>
-__global__ __launch_bounds__(kBlock, (batched_min_waves<KindV, KMAX>())) void k_batched_scan(BatchIO io, ScanSource src,
+__global__ __launch_bounds__(kBatchBlock, (batched_min_waves<KindV, KMAX>())) void k_batched_scan(BatchIO io, ScanSource src,
                                                          ClassTable ct) {
     constexpr int kLdsBytes = batched_lds_bytes<KindV>();
-    __shared__ __align__(16) unsigned char lds[kWavesPerBlock * kLdsBytes];
+    __shared__ __align__(16) unsigned char lds[kBatchWaves * kLdsBytes];
     const int wave = wave_id();
     void *win = lds + wave * kLdsBytes;
-    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t stride = (int64_t)gridDim.x * kBatchWaves;
     const int64_t ntasks = src.hdr->T, B = src.hdr->B;
-    for (int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave; t < ntasks; t += stride) {
+    for (int64_t t = (int64_t)blockIdx.x * kBatchWaves + wave; t < ntasks; t += stride) {
         int64_t set;
         int local;
         src.decode(t, B, &set, &local);
@@ -957,15 +963,15 @@ __device__ __forceinline__ void xbatched_task(const XBatchIO &io, int64_t base, 
 }
 
 template <int KindV>
-__global__ __launch_bounds__(kBlock) void k_xbatched_scan(XBatchIO io, ScanSource src,
+__global__ __launch_bounds__(kBatchBlock) void k_xbatched_scan(XBatchIO io, ScanSource src,
                                                           ClassTable ct) {
     constexpr int kLdsBytes = KindV == kForceF32 ? kForceLds * 4 : kEnergy64Lds * 8;
-    __shared__ __align__(16) unsigned char lds[kWavesPerBlock * kLdsBytes];
+    __shared__ __align__(16) unsigned char lds[kBatchWaves * kLdsBytes];
     const int wave = wave_id();
     void *win = lds + wave * kLdsBytes;
-    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t stride = (int64_t)gridDim.x * kBatchWaves;
     const int64_t ntasks = src.hdr->T, B = src.hdr->B;
-    for (int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave; t < ntasks; t += stride) {
+    for (int64_t t = (int64_t)blockIdx.x * kBatchWaves + wave; t < ntasks; t += stride) {
         int64_t set;
         int local;
         src.decode(t, B, &set, &local);
@@ -1277,9 +1283,9 @@ int max_rows(const ClassTable &ct) {
 
 // Resident blocks of a kernel on the current device.
 template <typename Kern>
-int64_t resident_blocks(const DeviceState *st, Kern kern) {
+int64_t resident_blocks(const DeviceState *st, Kern kern, int block = kBlock) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, 0) != hipSuccess ||
         per_cu <= 0)
         per_cu = 1;
     return (int64_t)per_cu * (st->n_cu > 0 ? st->n_cu : 1);
@@ -1333,8 +1339,8 @@ pairs_status_t launch_scan(int kind, const BatchIO &io, const ScanSource &src,
     // sixteen times the resident blocks: each block takes fewer grid-stride
     // tasks, and blocks that start as others finish even out the tail
     with_scan_kernel(kind, max_rows(ct), [&](auto kern) {
-        const int64_t blocks = resident_blocks(st, kern) * kScanBlockFactor;
-        kern<<<blocks, kBlock, 0, s>>>(io, src, ct);
+        const int64_t blocks = resident_blocks(st, kern, kBatchBlock) * kScanBlockFactor;
+        kern<<<blocks, kBatchBlock, 0, s>>>(io, src, ct);
     });
     PAIRS_HIP_CHECK(hipGetLastError());
     return PAIRS_OK;
@@ -1400,8 +1406,8 @@ pairs_status_t xbatched_common(int kind, const XBatchIO &io, int64_t n_sets, voi
     PAIRS_TRY(device_state(&st));
     const ScanSource src{hdr, list, pre, tab};
     auto go = [&](auto kern) {
-        const int64_t blocks = resident_blocks(st, kern) * kScanBlockFactor;
-        kern<<<(unsigned)blocks, kBlock, 0, s>>>(io, src, ct);
+        const int64_t blocks = resident_blocks(st, kern, kBatchBlock) * kScanBlockFactor;
+        kern<<<(unsigned)blocks, kBatchBlock, 0, s>>>(io, src, ct);
     };
     if (kind == kForceF32)
         go(k_xbatched_scan<kForceF32>);
@@ -2062,11 +2068,11 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
     const int kk = kind == PAIRS_KIND_COUNT_I32 ? kCountI32
                    : kind == PAIRS_KIND_COUNT_F32 ? kCountF32 : kEnergyF32;
     int64_t n_waves = 0;
-    // Task lists for eight times the resident waves: the lists are balanced by
-    // a cost estimate, and as resident waves finish, the hardware starts the
-    // waiting ones, which evens out what the estimate misses.
+    // Task lists for sixteen times the resident waves: the lists are balanced
+    // by a cost estimate, and as resident waves finish, the hardware starts
+    // the waiting ones, which evens out what the estimate misses.
     with_plan_kernel(kk, kmax, [&](auto kern) {
-        n_waves = resident_blocks(st, kern) * kWavesPerBlock * kPlanWaveFactor;
+        n_waves = resident_blocks(st, kern, kBatchBlock) * kBatchWaves * kPlanWaveFactor;
     });
 
     // every task with its cost in VALU issue slots.  Broadcast tasks: per
@@ -2334,9 +2340,9 @@ pairs_status_t pairs_plan_execute(pairs_plan_t plan, const void *const *in, void
     const int kind = plan->kind == PAIRS_KIND_COUNT_I32   ? kCountI32
                      : plan->kind == PAIRS_KIND_COUNT_F32 ? kCountF32
                                                           : kEnergyF32;
-    const int64_t blocks = (plan->n_waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int64_t blocks = (plan->n_waves + kBatchWaves - 1) / kBatchWaves;
     with_plan_kernel(kind, plan->kmax, [&](auto kern) {
-        kern<<<blocks, kBlock, 0, s>>>(io, plan->d_descs, plan->d_wave_start,
+        kern<<<blocks, kBatchBlock, 0, s>>>(io, plan->d_descs, plan->d_wave_start,
                                                   plan->n_waves);
     });
     PAIRS_HIP_CHECK(hipGetLastError());
