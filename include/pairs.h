@@ -354,8 +354,8 @@ pairs_status_t pairs_graph_destroy(pairs_graph_t graph);
  * Tile shapes of the kernels, chosen per size class.  Entry c of a table
  * applies to sets with n > min_n[c] that no earlier entry takes; the last
  * entry takes the rest.  Entries are listed from the largest sets down
- * (min_n strictly decreasing).  Each entry names one of two wave-task forms
- * of the balanced assignment (Section 4):
+ * (min_n strictly decreasing).  Each entry names one of three wave-task
+ * forms of the balanced assignment (Section 4):
  *
  * PAIRS_FORM_BROADCAST: a wave holds 64 * rows_per_lane consecutive rows of a
  *   set, K = rows_per_lane per lane in lane-major order, and sweeps a chunk of
@@ -369,6 +369,14 @@ pairs_status_t pairs_graph_destroy(pairs_graph_t graph);
  *   plan packs whole sets of equal size that fit one wave (ceil(n/K) <= 64)
  *   into shared waves; unplanned calls give each set its own waves.
  *
+ * PAIRS_FORM_MATRIX: the exact int32 count of single sets only (kind
+ *   PAIRS_KIND_COUNT_I32, batched = 0).  A wave holds 64 consecutive rows as
+ *   four 16-row tiles, and the Gram sums of each tile with 16 partners are
+ *   one double-precision matrix instruction (exact inside the double form's
+ *   box, the wide VALU test outside it); the VALU compares.  rows_per_lane
+ *   is 1; chunk as for the broadcast form.  The default tables do not use
+ *   it: on gfx950 it runs slower than the broadcast form.
+ *
  * Tables are per kind (PAIRS_KIND_*) and per mode (batched = 0: single-set
  * calls, 1: batched calls and plans).  A plan keeps the table of its
  * creation.  set(NULL) restores the defaults.  Results never depend on the
@@ -376,6 +384,7 @@ pairs_status_t pairs_graph_destroy(pairs_graph_t graph);
  */
 #define PAIRS_FORM_BROADCAST 0
 #define PAIRS_FORM_STEPPING 1
+#define PAIRS_FORM_MATRIX 2
 
 typedef struct {
     int32_t count;            /* entries used, 1..4 */

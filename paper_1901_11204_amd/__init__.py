@@ -23,7 +23,7 @@ __all__ = [
     "pairs_energy_f32_batched", "pairs_count_i32_batched_noalloc", "NOALLOC_MAX_SETS",
     "pairs_force_f32_batched", "pairs_energy_f64_batched",
     "pairs_jitter_f32", "pairs_debug_task_ranges",
-    "pairs_debug_step_ranges", "pairs_debug_single_launch", "pairs_debug_task_at", "FORM_BROADCAST", "FORM_STEPPING",
+    "pairs_debug_step_ranges", "pairs_debug_single_launch", "pairs_debug_task_at", "FORM_BROADCAST", "FORM_STEPPING", "FORM_MATRIX",
     "KIND_ENERGY_F64", "KIND_FORCE_F32",
     "Plan", "Graph", "ShapeTable", "pairs_get_shapes", "pairs_set_shapes",
     "count_i32", "count_f32", "energy_f32",
@@ -79,6 +79,7 @@ _int = ctypes.c_int
 
 FORM_BROADCAST = 0
 FORM_STEPPING = 1
+FORM_MATRIX = 2
 
 
 class ShapeTable(ctypes.Structure):

@@ -22,13 +22,15 @@ import os
 import sys
 import time
 
-from . import (FORM_BROADCAST, FORM_STEPPING, KIND_COUNT_F32, KIND_COUNT_I32, KIND_ENERGY_F32,
-               Plan, pairs_get_shapes, pairs_set_shapes)
+from . import (FORM_BROADCAST, FORM_MATRIX, FORM_STEPPING, KIND_COUNT_F32, KIND_COUNT_I32,
+               KIND_ENERGY_F32, Plan, pairs_get_shapes, pairs_set_shapes)
 
 ROWS = (1, 2, 4, 8)
 CHUNKS = (128, 256, 512, 1024, 2048, 4096, 8192)
 # (rows per lane, step chunks) of the row-stepping form (batched tables only)
 STEP_SHAPES = ((1, (64, 128, 192, 288)), (2, (48, 96, 144, 208, 272)))
+# chunks of the matrix-core form (single-set int32 counts only)
+MATRIX_CHUNKS = (1024, 4096)
 
 
 def candidates(batched: bool):
@@ -129,9 +131,17 @@ def tune_batched(kind, offsets, inputs, outputs, eps2=1e-4, start=None, rounds=1
     return table, best
 
 
+def single_candidates(kind, rows=ROWS, chunks=CHUNKS):
+    """Every (K, U, form) the tuner tries for one size class of single sets."""
+    out = [(k, u, FORM_BROADCAST) for k in rows for u in chunks]
+    if kind == KIND_COUNT_I32:
+        out += [(1, u, FORM_MATRIX) for u in MATRIX_CHUNKS]
+    return out
+
+
 def tune_single(kind, n_values, make_call, start=None, log=print, rows=ROWS, chunks=CHUNKS,
                 trace=None):
-    """For each size n (largest first) pick the (K, U) with the fastest
+    """For each size n (largest first) pick the (K, U, form) with the fastest
     single-set call; make_call(n) returns a zero-argument callable.  Returns
     the table and the best time of each size."""
     entries, times = [], []
@@ -142,17 +152,16 @@ def tune_single(kind, n_values, make_call, start=None, log=print, rows=ROWS, chu
         call = make_call(n)
         best = None
         lo = ns[i + 1] if i + 1 < len(ns) else 0
-        for k in rows:
-            for u in chunks:
-                pairs_set_shapes(kind, False, entries + [(lo, k, u)])
-                ms = _time(call)
-                if trace:
-                    trace(f"    n={n} K={k} U={u}: {ms:.3f} ms")
-                if best is None or ms < best[0]:
-                    best = (ms, k, u)
-        entries.append((lo, best[1], best[2]))
+        for k, u, form in single_candidates(kind, rows, chunks):
+            pairs_set_shapes(kind, False, entries + [(lo, k, u, form)])
+            ms = _time(call)
+            if trace:
+                trace(f"    n={n} K={k} U={u} form={form}: {ms:.3f} ms")
+            if best is None or ms < best[0]:
+                best = (ms, k, u, form)
+        entries.append((lo,) + best[1:])
         times.append(best[0])
-        log(f"n={n}: K={best[1]} U={best[2]} {best[0]:.3f} ms")
+        log(f"n={n}: K={best[1]} U={best[2]} form={best[3]} {best[0]:.3f} ms")
     pairs_set_shapes(kind, False, entries)
     return entries, times
 

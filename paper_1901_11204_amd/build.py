@@ -33,6 +33,9 @@ def build_cmd(out: str, extra=(), sources=None):
             # the SLP vectorizer packs per-pair predicate bits into vectors in
             # the unrolled sweeps, which costs VALU instructions on gfx950
             "-fno-slp-vectorize",
+            # matrix-instruction results in VGPRs, where the comparisons read
+            # them, rather than in AGPRs copied out one register at a time
+            "-mllvm", "-amdgpu-mfma-vgpr-form",
             "-I", INCLUDE, "-I", CSRC, *extra, "-o", out, *(sources or SOURCES)]
 
 

@@ -35,6 +35,7 @@
 #include "binning.h"
 #include "device.h"
 #include "lattice.h"
+#include "mfma.h"
 #include "pairs.h"
 #include "steps.h"
 #include "tasks.h"
@@ -134,11 +135,15 @@ ClassTable shapes(int kind, bool batched) {
                                            : default_table(kind, batched);
 }
 
-bool valid_table(const ClassTable &t, bool batched) {
+bool valid_table(const ClassTable &t, bool batched, int kind) {
     if (t.count < 1 || t.count > kMaxClasses) return false;
     for (int c = 0; c < t.count; ++c) {
         if (t.lo[c] < 0 || (c > 0 && t.lo[c] >= t.lo[c - 1])) return false;
-        if (t.form[c] == PAIRS_FORM_STEPPING) {
+        if (t.form[c] == PAIRS_FORM_MATRIX) {
+            // single-set exact int32 counts only: 64-row tasks
+            if (batched || kind != PAIRS_KIND_COUNT_I32 || t.K[c] != 1) return false;
+            if (t.U[c] < 64 || t.U[c] % 64 != 0 || t.U[c] > (1 << 22)) return false;
+        } else if (t.form[c] == PAIRS_FORM_STEPPING) {
             if (!batched || (t.K[c] != 1 && t.K[c] != 2)) return false;
             if (t.U[c] < 16 || t.U[c] % 16 != 0 || t.U[c] > step_max_chunk(t.K[c])) return false;
         } else if (t.form[c] == PAIRS_FORM_BROADCAST) {
@@ -259,6 +264,26 @@ __global__ __launch_bounds__(kBlock) void k_count_i32(const int32_t *__restrict_
         load_task_inputs<int32_t, K, K, true>(x, y, z, r, 0, band, ra, u0, u1, in);
         uint32_t cnt = count_i32_task<K, K>(x, y, z, r, 0, band, ra, u0, u1,
                                             lds + wave * kCountI32Lds, in);
+        if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)out, (unsigned long long)cnt);
+    });
+}
+
+// The exact int32 count with the Gram sums on the matrix cores (mfma.h):
+// tasks of 64 rows (the broadcast tiling with one row per lane).
+__global__ __launch_bounds__(kBlock) void k_count_i32_mfma(const int32_t *__restrict__ x,
+                                                           const int32_t *__restrict__ y,
+                                                           const int32_t *__restrict__ z,
+                                                           const int32_t *__restrict__ r, int n,
+                                                           int U, uint64_t *out) {
+    __shared__ int64_t lds[kWavesPerBlock * kCountI32Lds];
+    const int wave = wave_id();
+    const Band band = Band::of(n);
+    const Tiling til = Tiling::of(band, 1, U);
+    for_each_task(band, til, [&](int ra, int u0, int u1) {
+        TaskInputs<int32_t, 1> in;
+        load_task_inputs<int32_t, 1, 1, true>(x, y, z, r, 0, band, ra, u0, u1, in);
+        const uint32_t cnt = count_i32_task_mfma(x, y, z, r, 0, band, ra, u0, u1,
+                                                 lds + wave * kCountI32Lds, in);
         if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)out, (unsigned long long)cnt);
     });
 }
@@ -1179,6 +1204,7 @@ pairs_status_t validate_offsets(const int64_t *off, int64_t n_sets, int64_t n_to
 struct Shape {
     int K;
     int U;
+    int form;
 };
 
 // The double-precision energy and the forces run the float32 energy's shapes
@@ -1188,7 +1214,7 @@ Shape single_set_shape(int kind, int64_t n) {
     const bool wide = kind == PAIRS_KIND_ENERGY_F64 || kind == PAIRS_KIND_FORCE_F32;
     const ClassTable t = shapes(wide ? PAIRS_KIND_ENERGY_F32 : kind, false);
     const int c = t.class_of((int)n);
-    return {wide ? std::min(t.K[c], 4) : t.K[c], t.U[c]};
+    return {wide ? std::min(t.K[c], 4) : t.K[c], t.U[c], t.form[c]};
 }
 
 // Blocks of a single-set launch: one wave per task, at most kMaxSingleBlocks
@@ -1766,6 +1792,12 @@ pairs_status_t pairs_count_i32(const int32_t *x, const int32_t *y, const int32_t
     PAIRS_TRY(fill_u64(d_count, 1, 0, s));
     if (n < 2) return PAIRS_OK;
     Shape sh = single_set_shape(PAIRS_KIND_COUNT_I32, n);
+    if (sh.form == PAIRS_FORM_MATRIX) {
+        const unsigned blocks = single_blocks((int)n, 1, sh.U);
+        if (blocks > 0) k_count_i32_mfma<<<blocks, kBlock, 0, s>>>(x, y, z, r, (int)n, sh.U, d_count);
+        PAIRS_HIP_CHECK(hipGetLastError());
+        return PAIRS_OK;
+    }
     switch (sh.K) {
         case 1: launch_count_i32<1>(x, y, z, r, (int)n, sh.U, d_count, s); break;
         case 2: launch_count_i32<2>(x, y, z, r, (int)n, sh.U, d_count, s); break;
@@ -2475,7 +2507,7 @@ pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t
     if (table->count < 1 || table->count > kMaxClasses) return PAIRS_ERR_INVALID_ARG;
     ClassTable t = make_table(table->count, table->min_n, table->rows_per_lane, table->chunk,
                               table->form);
-    if (!valid_table(t, batched != 0)) return PAIRS_ERR_INVALID_ARG;
+    if (!valid_table(t, batched != 0, kind)) return PAIRS_ERR_INVALID_ARG;
     g_shapes[kind - 1][batched != 0] = t;
     g_shapes_set[kind - 1][batched != 0] = true;
     return PAIRS_OK;

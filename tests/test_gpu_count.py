@@ -50,9 +50,9 @@ def forced_shape():
     """Force one single-set tile shape for a kind; restores the defaults after."""
     kinds = []
 
-    def force(kind, rows_per_lane, chunk):
+    def force(kind, rows_per_lane, chunk, form=P.FORM_BROADCAST):
         kinds.append(kind)
-        P.pairs_set_shapes(kind, False, [(0, rows_per_lane, chunk)])
+        P.pairs_set_shapes(kind, False, [(0, rows_per_lane, chunk, form)])
 
     yield force
     for k in kinds:
@@ -70,6 +70,25 @@ def test_count_i32_every_shape(forced_shape, K, U):
         assert P.count_i32(*dev(*s.arrays())) == oracle.count_i32(*s.arrays()), (K, U, n)
 
 
+@pytest.mark.parametrize("U", [64, 128, 1024])
+def test_count_i32_matrix_form(forced_shape, U):
+    """The matrix-core form (16-row tiles on v_mfma_f64_16x16x4f64) at tile
+    edges, ragged tails, the band's two edges and the even-n extra step."""
+    forced_shape(P.KIND_COUNT_I32, 1, U, P.FORM_MATRIX)
+    for n in (2, 3, 15, 16, 17, 63, 64, 65, 127, 128, 129, 2 * U + 1, 2500, 8193, 16384):
+        for kind, gen in (("dense", dense_i32), ("sparse", sparse_i32)):
+            s = gen(n, 11 * n + U)
+            announce("count_i32 matrix form", kind, U, n)
+            assert P.count_i32(*dev(*s.arrays())) == oracle.count_i32(*s.arrays()), (kind, U, n)
+
+
+def test_count_i32_matrix_form_config1(forced_shape):
+    forced_shape(P.KIND_COUNT_I32, 1, 512, P.FORM_MATRIX)
+    s = w.config1()
+    announce("count_i32 matrix form config1")
+    assert P.count_i32(*dev(*s.arrays())) == oracle.count_i32(*s.arrays())
+
+
 LO, HI, RMAX = -(2 ** 30), 2 ** 30 - 1, 2 ** 30   # the exact domain
 
 
@@ -80,13 +99,14 @@ def domain_set(n, seed, lo, hi, rmax):
     return x, y, z, r
 
 
-@pytest.mark.parametrize("K", [1, 2, 4, 8])
+@pytest.mark.parametrize("K", [1, 2, 4, 8, "matrix"])
 @pytest.mark.parametrize("L", [2 ** 22, 2 ** 24, 2 ** 29, 2 ** 30])
 def test_count_i32_domain_edges(forced_shape, K, L):
     """Coordinates in [-L, L) and radii in [0, L] up to the domain's edges,
-    with no flag: the plain Gram tests hold up to 2^24 (double form, K >= 4)
-    and 2^29 (integer form, K <= 2); beyond, waves switch to the wide test."""
-    forced_shape(P.KIND_COUNT_I32, K, 256)
+    with no flag: the plain Gram tests hold up to 2^24 (double form, K >= 4,
+    and the matrix form) and 2^29 (integer form, K <= 2); beyond, waves
+    switch to the wide test."""
+    K = force_k_or_matrix(forced_shape, K, 256)
     n = 3001
     x, y, z, r = domain_set(n, 5 + K, -L, L - 1, L)
     # pin a few objects to the extreme corners
@@ -105,12 +125,22 @@ def test_count_i32_domain_edges(forced_shape, K, L):
         assert P.count_i32(*dev(a, zero, zero, rr)) == expect, (gap, L)
 
 
-@pytest.mark.parametrize("K", [1, 2, 4, 8])
+def force_k_or_matrix(forced_shape, K, U):
+    """Force K rows per lane in the broadcast form, or the matrix form for
+    K = "matrix"; returns an integer standing for K in seeds."""
+    if K == "matrix":
+        forced_shape(P.KIND_COUNT_I32, 1, U, P.FORM_MATRIX)
+        return 16
+    forced_shape(P.KIND_COUNT_I32, K, U)
+    return K
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 8, "matrix"])
 def test_count_i32_extreme_pairs(forced_shape, K):
     """Pairs at the largest distances and radii of the domain, decided at exact
     equality: the squared distance 3 (2^31 - 1)^2 and the squared radius sum
     2^62 sit at the edges of the wide test's modulo-2^64 window."""
-    forced_shape(P.KIND_COUNT_I32, K, 64)
+    K = force_k_or_matrix(forced_shape, K, 64)
     pts = []
     # opposite corners: d^2 = 3 (2^31 - 1)^2 > (2^31)^2, never touching
     pts.append(((LO, LO, LO, RMAX), (HI, HI, HI, RMAX)))
@@ -142,11 +172,11 @@ def test_count_i32_extreme_pairs(forced_shape, K):
     assert P.count_i32(*dev(x, y, z, r)) == oracle.count_i32(x, y, z, r)
 
 
-@pytest.mark.parametrize("K", [1, 2, 4, 8])
+@pytest.mark.parametrize("K", [1, 2, 4, 8, "matrix"])
 def test_count_i32_mixed_boxes(forced_shape, K):
     """Dense objects inside the plain tests' boxes with a few far outside:
     tasks and partner groups take the plain and the wide test side by side."""
-    forced_shape(P.KIND_COUNT_I32, K, 128)
+    K = force_k_or_matrix(forced_shape, K, 128)
     n = 5000
     s = dense_i32(n, 90 + K)
     x, y, z, r = [a.copy() for a in s.arrays()]

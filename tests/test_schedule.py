@@ -117,6 +117,26 @@ def test_step_shapes_rejected():
     P.pairs_set_shapes(P.KIND_COUNT_I32, True, None)
 
 
+def test_matrix_shapes_rejected():
+    """The matrix form takes single-set int32 count tables only, with one row
+    per lane and chunks that are multiples of 64."""
+    M = P.FORM_MATRIX
+    for kind, batched, entry in ((P.KIND_COUNT_I32, True, (0, 1, 256, M)),
+                                 (P.KIND_COUNT_F32, False, (0, 1, 256, M)),
+                                 (P.KIND_ENERGY_F32, False, (0, 1, 256, M)),
+                                 (P.KIND_COUNT_I32, False, (0, 2, 256, M)),
+                                 (P.KIND_COUNT_I32, False, (0, 1, 96, M)),
+                                 (P.KIND_COUNT_I32, False, (0, 1, 32, M)),
+                                 (P.KIND_COUNT_I32, False, (0, 1, 2 ** 23, M))):
+        with pytest.raises(P.PairsError):
+            P.pairs_set_shapes(kind, batched, [entry])
+    table = [(65536, 8, 1024, P.FORM_BROADCAST), (0, 1, 512, M)]
+    P.pairs_set_shapes(P.KIND_COUNT_I32, False, table)
+    assert P.pairs_get_shapes(P.KIND_COUNT_I32, False) == table
+    P.pairs_set_shapes(P.KIND_COUNT_I32, False, None)
+    assert all(e[3] == P.FORM_BROADCAST for e in P.pairs_get_shapes(P.KIND_COUNT_I32, False))
+
+
 # The window indexing of a stepping task, emulated lane by lane exactly as the
 # kernel computes it (segments of w lanes, K-interleaved window of S entries
 # per residue, sweep positions split into the unmasked core and the masked
