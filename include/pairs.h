@@ -539,7 +539,10 @@ pairs_status_t pairs_debug_step_ranges(int n, int rows_per_lane, int chunk, int3
  * of n <= PAIRS_MAX_SET_SIZE objects decoded as the single-set kernels decode
  * it: out[3k] = first row, out[3k+1] = u0, out[3k+2] = u1.  rows_per_lane in
  * {1, 2, 4, 8}; chunk a multiple of 64 in [64, 2^22].  For sets too large to
- * list every task with pairs_debug_task_ranges.
+ * list every task with pairs_debug_task_ranges.  The kernels' order: the row
+ * blocks form 16 groups of R = ceil(blocks / 16) consecutive blocks (the last
+ * may be smaller), and inside a group task index g*R*chunks + c*R_g + j is
+ * chunk c of the group's block j (R_g = the group's block count).
  */
 pairs_status_t pairs_debug_task_at(int64_t n, int rows_per_lane, int chunk,
                                    const int64_t *tasks, int64_t count, int64_t *out);

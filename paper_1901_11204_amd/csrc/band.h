@@ -107,6 +107,27 @@ PAIRS_HD void task_at(const Band &b, const Tiling &t, int64_t task, int *ra, int
     task_range(b, t, block, c, ra, u0, u1);
 }
 
+// The single-set launch order of the same tasks.  The row blocks form
+// kTaskGroups groups of R = ceil(nblocks / kTaskGroups) consecutive blocks
+// (the last group may be smaller); a group's tasks are enumerated chunk by
+// chunk across its blocks, block fastest.  Tasks that run at the same time
+// then read one narrow window of partners (a group's blocks are R*64K rows
+// apart at most, and neighbouring chunks are U partners apart), which an
+// L2 cache of a few MB holds, where the block-major order has every chunk of
+// the set in flight.  A bijection on [0, tasks()).
+constexpr int kTaskGroups = 16;
+
+PAIRS_HD void task_at_grouped(const Band &b, const Tiling &t, int64_t task, int *ra, int *u0,
+                              int *u1) {
+    const int R = (t.nblocks + kTaskGroups - 1) / kTaskGroups;
+    const int64_t per_group = (int64_t)R * t.nchunks;
+    const int g = (int)(task / per_group);
+    const int64_t w = task - (int64_t)g * per_group;
+    const int rg = t.nblocks - g * R < R ? t.nblocks - g * R : R;  // blocks in group g
+    const int c = (int)(w / rg), block = g * R + (int)(w % rg);
+    task_range(b, t, block, c, ra, u0, u1);
+}
+
 // Row-stepping decomposition (the paper's own form: row i visits partners
 // (i + s) mod n for s = 1, 2, ...).  A stepping task holds K consecutive rows
 // per lane, rows [r0, r0 + 64K), and runs the steps [s0, s0 + T) for all its

@@ -235,16 +235,28 @@ __global__ void k_validate_offsets(const int64_t *off, int64_t n_sets, int64_t n
 
 constexpr int64_t kMaxSingleBlocks = (int64_t)1 << 22;
 
+// The dispatcher deals workgroups to gfx950's eight XCDs in turn (workgroup w
+// to XCD w % 8), and each XCD has an L2 cache of its own.  Numbering the
+// workgroups XCD by XCD gives each XCD one contiguous range of the task
+// order, so tasks that share partners share an L2.  A bijection on
+// [0, blocks): XCDs x < blocks % 8 hold one workgroup more than the others.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_major_block(int64_t w, int64_t blocks) {
+    const int64_t q = blocks / kXcds, r = blocks % kXcds, x = w % kXcds, i = w / kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 // Runs f(ra, u0, u1) for every non-empty task of the tiling owned by the
-// calling wave.
+// calling wave, in the grouped order of task_at_grouped.
 template <typename F>
 __device__ __forceinline__ void for_each_task(const Band &band, const Tiling &til, F &&f) {
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t ntasks = til.tasks();
-    for (int64_t task = (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); task < ntasks;
-         task += stride) {
+    for (int64_t task = xcd_major_block(blockIdx.x, gridDim.x) * kWavesPerBlock + wave_id();
+         task < ntasks; task += stride) {
         int ra, u0, u1;
-        task_at(band, til, task, &ra, &u0, &u1);
+        task_at_grouped(band, til, task, &ra, &u0, &u1);
         if (u0 < u1) f(ra, u0, u1);
     }
 }
@@ -2548,7 +2560,7 @@ pairs_status_t pairs_debug_task_at(int64_t n, int rows_per_lane, int chunk,
         if (tasks[k] < 0 || tasks[k] >= til.tasks()) return PAIRS_ERR_INVALID_ARG;
     for (int64_t k = 0; k < count; ++k) {
         int ra, u0, u1;
-        task_at(band, til, tasks[k], &ra, &u0, &u1);
+        task_at_grouped(band, til, tasks[k], &ra, &u0, &u1);
         out[3 * k] = ra;
         out[3 * k + 1] = u0;
         out[3 * k + 2] = u1;

@@ -279,6 +279,37 @@ def test_single_launch_rejects_bad_kind_and_size():
         P.pairs_debug_single_launch(P.KIND_COUNT_I32, 2 ** 30 + 1)
 
 
+def grouped_indices(nblocks, nchunks, b):
+    """Task indices of row block b's chunks 0..nchunks-1 in the single-set
+    kernels' order: 16 groups of R = ceil(nblocks / 16) blocks, chunk-major
+    inside a group."""
+    R = -(-nblocks // 16)
+    g, j = divmod(b, R)
+    rg = min(R, nblocks - g * R)
+    return g * R * nchunks + np.arange(nchunks, dtype=np.int64) * rg + j
+
+
+@pytest.mark.parametrize("n,K,U", [(2, 1, 64), (7, 1, 64), (1000, 1, 64), (5000, 2, 128),
+                                   (12345, 8, 512), (70001, 4, 256), (2 ** 17, 8, 1024),
+                                   (17 * 512 + 3, 8, 64)])
+def test_grouped_task_order_is_a_permutation(n, K, U):
+    """The kernels' grouped order decodes every task of the block-major list
+    exactly once, and groups of consecutive indices stay inside one group of
+    row blocks, chunk by chunk."""
+    listed = P.pairs_debug_task_ranges(n, K, U).astype(np.int64)
+    total = len(listed)
+    got = P.pairs_debug_task_at(n, K, U, np.arange(total))
+    key = lambda t: sorted(map(tuple, t.tolist()))
+    assert key(got) == key(listed)
+    rows = 64 * K
+    nblocks = -(-n // rows)
+    nchunks = total // nblocks
+    assert nblocks * nchunks == total
+    for b in sorted({0, nblocks // 2, nblocks - 1}):
+        t = P.pairs_debug_task_at(n, K, U, grouped_indices(nblocks, nchunks, b))
+        np.testing.assert_array_equal(t, listed[b * nchunks:(b + 1) * nchunks])
+
+
 @pytest.mark.parametrize("n", [2 ** 27, 2 ** 27 + 1, 2 ** 30 - 1, 2 ** 30])
 @pytest.mark.parametrize("K,U", [(8, 1024), (1, 64)])
 def test_task_decode_at_the_size_limit(n, K, U):
@@ -294,7 +325,7 @@ def test_task_decode_at_the_size_limit(n, K, U):
     for b in picks:
         if K == 1 and b not in (0, nblocks - 1):
             continue   # 2^23 chunks per block at K = 1: the two ends suffice
-        t = P.pairs_debug_task_at(n, K, U, np.arange(b * nchunks, (b + 1) * nchunks))
+        t = P.pairs_debug_task_at(n, K, U, grouped_indices(nblocks, nchunks, b))
         ra = b * rows
         rlast = min(ra + rows, n) - 1
         uend = rlast + steps(n, rlast) + 1
