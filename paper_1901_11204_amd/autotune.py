@@ -49,9 +49,18 @@ def arch() -> str:
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
-def _time(fn, reps: int = 3, warmup: int = 1) -> float:
+def _time(fn, reps: int = 3, warmup_s: float = 0.25) -> float:
+    """Mean milliseconds of `reps` back-to-back calls, after about warmup_s
+    seconds of calls: the engine clock of an idle GPU takes that long to
+    reach its running speed, and millisecond-scale calls timed straight
+    after an idle spell read up to 15 % slow."""
     import torch
-    for _ in range(warmup):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    one = time.perf_counter() - t0
+    for _ in range(max(0, min(400, int(warmup_s / max(one, 1e-5))) - 1)):
         fn()
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
@@ -64,7 +73,7 @@ def _time(fn, reps: int = 3, warmup: int = 1) -> float:
     return t0.elapsed_time(t1) / reps
 
 
-def time_batched(kind, table, offsets, inputs, outputs, eps2=1e-4, reps=3) -> float:
+def time_batched(kind, table, offsets, inputs, outputs, eps2=1e-4, reps=10) -> float:
     """Milliseconds of one plan execution of the batch under `table`."""
     pairs_set_shapes(kind, True, table)
     plan = Plan(kind, offsets)

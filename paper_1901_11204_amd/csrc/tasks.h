@@ -541,6 +541,19 @@ struct EnergyResult {
     uint32_t count;  // collisions among the task's pairs (WithCount)
 };
 
+// Sum of v[0..K) as a pairwise tree.  The partner side of a pair sums one
+// term per row of the lane; a tree keeps each add waiting on two results
+// that are already some instructions old, where a running sum would chain
+// every add to the reciprocal square root just issued.
+template <typename T, int K>
+__device__ __forceinline__ T tree_sum(T (&v)[K]) {
+#pragma unroll
+    for (int w = 1; w < K; w *= 2)
+#pragma unroll
+        for (int k = 0; k + w < K; k += 2 * w) v[k] = v[k] + v[k + w];
+    return v[0];
+}
+
 template <int K, bool PerObject, bool WithCount, bool Masked>
 __device__ __forceinline__ void energy_group(const float (&xr)[K], const float (&yr)[K],
                                              const float (&zr)[K], const float (&rr)[K],
@@ -558,7 +571,7 @@ __device__ __forceinline__ void energy_group(const float (&xr)[K], const float (
             float jr = 0.0f;
             if (WithCount) jr = win[3 * kWave + t];
             const int u = g0 + t;
-            float js = 0.0f;
+            float es[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float dx = xr[k] - jx, dy = yr[k] - jy, dz = zr[k] - jz;
@@ -585,9 +598,9 @@ __device__ __forceinline__ void energy_group(const float (&xr)[K], const float (
                 // not added to zero (an add of 0 is no IEEE identity, so the
                 // compiler keeps it)
                 part[k] = tt == 0 ? e : part[k] + e;
-                if (PerObject) js = k == 0 ? e : js + e;
+                es[k] = e;
             }
-            if (PerObject) js_all[tt] = js;
+            if (PerObject) js_all[tt] = tree_sum(es);
         }
         if (PerObject) {
             // all 4 lanes of a group store the same value to the same slot
@@ -706,7 +719,7 @@ __device__ __forceinline__ void force_group(const float (&xr)[K], const float (&
             const int t = t0 + tt;
             const float jx = win[t], jy = win[kWave + t], jz = win[2 * kWave + t];
             const int u = g0 + t;
-            float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+            float sx[K], sy[K], sz[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float dx = xr[k] - jx, dy = yr[k] - jy, dz = zr[k] - jz;
@@ -721,13 +734,13 @@ __device__ __forceinline__ void force_group(const float (&xr)[K], const float (&
                 part[0][k] = tt == 0 ? fx : part[0][k] + fx;
                 part[1][k] = tt == 0 ? fy : part[1][k] + fy;
                 part[2][k] = tt == 0 ? fz : part[2][k] + fz;
-                sx = k == 0 ? fx : sx + fx;
-                sy = k == 0 ? fy : sy + fy;
-                sz = k == 0 ? fz : sz + fz;
+                sx[k] = fx;
+                sy[k] = fy;
+                sz[k] = fz;
             }
-            sx_all[tt] = sx;
-            sy_all[tt] = sy;
-            sz_all[tt] = sz;
+            sx_all[tt] = tree_sum(sx);
+            sy_all[tt] = tree_sum(sy);
+            sz_all[tt] = tree_sum(sz);
         }
         // all 4 lanes of a group store the same value to the same slot
         win[3 * kWave + t0 + slot] = reduce_scatter16(sx_all);
@@ -855,7 +868,7 @@ __device__ __forceinline__ void energy64_group(const double (&xr)[K], const doub
             const int t = t0 + tt;
             const double jx = win[t], jy = win[kWave + t], jz = win[2 * kWave + t];
             const int u = g0 + t;
-            double js = 0.0;
+            double es[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const double dx = xr[k] - jx, dy = yr[k] - jy, dz = zr[k] - jz;
@@ -865,9 +878,9 @@ __device__ __forceinline__ void energy64_group(const double (&xr)[K], const doub
                 double e = rsq_f64(d2);
                 if (Masked) e = owns(u, row[k], nsteps[k]) ? e : 0.0;
                 acc[k] += e;
-                if (PerObject) js = k == 0 ? e : js + e;
+                es[k] = e;
             }
-            if (PerObject) js_all[tt] = js;
+            if (PerObject) js_all[tt] = tree_sum(es);
         }
         if (PerObject) win[3 * kWave + t0 + slot] = reduce_scatter16_f64(js_all);
     }
