@@ -426,6 +426,44 @@ def wave_timeline(L, torch, np, variant, x, y, z, r, n, K, out, stream):
             "start_order_vs_block_order_rank_corr": rank_corr}
 
 
+SIZE_SLICES = ((2, 16), (17, 32), (33, 64), (65, 128), (129, 256), (257, 512), (513, 1024),
+               (1025, 2048), (2049, 8192))
+
+
+def config4_size_slices(P, w, torch, np, dev, steps):
+    """Config 4's sets split by size, each slice timed alone as its own batch
+    (a plan and the unplanned call): where the batched count's time goes."""
+    b = w.config4()
+    off, sizes = b.offsets, np.diff(b.offsets)
+    arrays = b.objs.arrays()
+    out = []
+    for lo, hi in SIZE_SLICES:
+        sel = np.nonzero((sizes >= lo) & (sizes <= hi))[0]
+        idx = np.concatenate([np.arange(off[s], off[s + 1]) for s in sel])
+        offs = np.concatenate([[0], np.cumsum(sizes[sel])]).astype(np.int64)
+        x, y, z, r = (torch.from_numpy(np.ascontiguousarray(a[idx])).to(dev) for a in arrays)
+        counts = torch.empty(len(sel), dtype=torch.int64, device=dev)
+        pairs = int((sizes[sel] * (sizes[sel] - 1) // 2).sum())
+        plan = P.Plan(P.KIND_COUNT_I32, offs)
+        sclk_during(lambda: plan.execute((x, y, z, r), (counts,)))
+        mp = float(np.mean(timed_steps(lambda: plan.execute((x, y, z, r), (counts,)),
+                                       max(10, steps), 2)[0]))
+        plan.close()
+        toff = torch.from_numpy(offs).to(dev)
+        ws = torch.empty(P.pairs_batched_workspace_size(len(sel), int(offs[-1])),
+                         dtype=torch.uint8, device=dev)
+        sclk_during(lambda: P.pairs_count_i32_batched(x, y, z, r, toff, counts, ws))
+        mu = float(np.mean(timed_steps(lambda: P.pairs_count_i32_batched(x, y, z, r, toff,
+                                                                          counts, ws),
+                                       max(10, steps), 2)[0]))
+        frac = lambda m: pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK
+        out.append({"sizes": [lo, hi], "sets": int(len(sel)), "pair_tests": pairs,
+                    "plan_ms": mp, "plan_valu_frac": frac(mp),
+                    "unplanned_ms": mu, "unplanned_valu_frac": frac(mu)})
+        log(f"[bench] config 4 sets of {lo}..{hi} objects: plan {mp:.4f} ms")
+    return out
+
+
 def bench_batched(P, w, torch, np, dev, steps):
     """Batched lines: the binned int32 batch (one persistent launch through a
     plan, and the unplanned call), and the float32 repeated-step loop captured
@@ -588,6 +626,8 @@ def main():
                     help="only the binned counts of the 2^20 set and of config 4 (for profiling)")
     ap.add_argument("--binned-workload", choices=["2p20", "config4", "all"], default="all",
                     help="with --binned-only: which binned workloads")
+    ap.add_argument("--config4-slices", action="store_true",
+                    help="only config 4's sets split by size, each slice timed alone")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
@@ -619,6 +659,10 @@ def main():
 
     if a.batched_only:
         print(json.dumps({"batched": bench_batched(P, w, torch, np, dev, a.steps)}), flush=True)
+        return
+    if a.config4_slices:
+        print(json.dumps({"config4_size_slices": config4_size_slices(P, w, torch, np, dev,
+                                                                      a.steps)}), flush=True)
         return
     if a.lattice_only:
         print(json.dumps({"lattice": bench_lattice(P, w, torch, np, dev, a.steps)}), flush=True)
