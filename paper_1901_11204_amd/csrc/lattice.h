@@ -602,14 +602,22 @@ __global__ __launch_bounds__(kBlock) void k_lattice_near(IO io, int tlog, int de
                 want |= (valid[k] && j == 4 + (j & 3)) ? 1u << k : 0u;  // an empty slot
                 pend |= (valid[k] && j >= 4) ? 1u << k : 0u;            // not found
             }
+            // A claim lost to another key (distinct sites sharing a home
+            // bucket race for its first empty slot) moves on to the bucket's
+            // next slot, so that slots still fill in order; only a bead that
+            // loses the bucket's last slot is left to the per-lane probes.
 #pragma unroll
             for (int k = 0; k < BPT; ++k) {
-                const bool w = want & (1u << k);
-                if (__builtin_amdgcn_ballot_w64(w)) {
-                    const uint32_t g = atomicCAS(&keys[slot[k]], w ? 0u : kNever32, key[k]);
+                bool w = want & (1u << k);
+                uint32_t sl = slot[k];
+                for (int a = 0; a < 4 && __builtin_amdgcn_ballot_w64(w); ++a) {
+                    const uint32_t g = atomicCAS(&keys[sl], w ? 0u : kNever32, key[k]);
                     const bool mine = w && (g == 0 || g == key[k]);
                     pend &= mine ? ~(1u << k) : ~0u;
+                    w = w && !mine && (sl & 3u) != 3u;
+                    sl += w ? 1u : 0u;
                 }
+                slot[k] = sl;
             }
             uint32_t before[BPT];
 #pragma unroll
