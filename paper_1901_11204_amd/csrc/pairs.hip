@@ -105,14 +105,16 @@ ClassTable default_table(int kind, bool batched) {
         return make_table(4, lo, K, U, form);
     }
     // single sets: measured on MI355X by autotune.tune_single at n = 4096,
-    // 16384, 65536 and 262144 (the largest class is the N = 2^20 optimum)
+    // 16384, 65536 and 262144 (the largest class is the N = 2^20 optimum);
+    // with tasks in row-block groups (task_at_grouped) the largest classes
+    // gain a little from longer chunks
     if (kind == PAIRS_KIND_ENERGY_F32) {
         const int lo[4] = {65536, 16384, 4096, 0}, K[4] = {8, 8, 4, 4},
-                  U[4] = {256, 128, 128, 64};
+                  U[4] = {1024, 128, 128, 64};
         return make_table(4, lo, K, U, nullptr);
     }
     const int lo[4] = {524288, 65536, 8192, 0}, K[4] = {8, 4, 4, 1},
-              U[4] = {1024, 512, 128, 64};
+              U[4] = {2048, 512, 128, 64};
     return make_table(4, lo, K, U, nullptr);
 }
 
