@@ -30,15 +30,15 @@ SCLK_HZ = 2.4e9
 VALU_PEAK = N_CU * VALU_LANES_PER_CU * SCLK_HZ          # lane-operations per second
 # Algorithmic VALU work per pair test of each kernel (lane-operations):
 #   exact int32 count, Gram form: 4 32x32->64-bit multiply-adds + 1 compare
-#   float32 energy with per-object sums: 3 sub + 3 fma + 2 adds; the
-#     reciprocal square root issues to the separate transcendental pipe and
-#     takes no VALU slot (total-only energy runs above the VALU bound that a
-#     slot for it would impose)
+#   float32 energy with per-object sums: 3 sub + 3 fma + 2 adds (the total
+#     alone: 1 add); the reciprocal square root issues to the separate
+#     transcendental pipe and takes no VALU slot (total-only energy runs
+#     above the VALU bound that a slot for it would impose)
 #   float32 energy with the pinned collision count: 3 sub + 1 mul + 2 fma
 #     (pinned squared distance) + add, mul, compare (radius test) + add
 #     (softening) + add
-C_ALG = {"count_i32": 5, "energy_f32": 8, "energy_count_f32": 11, "force_f32": 18,
-         "energy_f64": 13}
+C_ALG = {"count_i32": 5, "energy_f32": 8, "energy_total_f32": 7, "energy_count_f32": 11,
+         "force_f32": 18, "energy_f64": 13}
 PLAIN_DEF_OPS = 12   # operations of the plain definition per pair (either kind)
 
 
@@ -780,9 +780,16 @@ def main():
                                   "max_rel_err_per_particle_vs_fp64_oracle":
                                       float(np.max(np.abs(got_rows - want_rows) / want_rows)),
                                   "sampled_particles": len(ge["rows"])}
+        mhz3b = sclk_during(lambda: P.pairs_energy_f32(*t3, 1e-4, None, tot))
         ms3b, _ = timed_steps(lambda: P.pairs_energy_f32(*t3, 1e-4, None, tot), max(3, a.steps // 2), 1)
         m3b = float(np.mean(ms3b))
-        sec["energy_f32_2^18_total_only"] = {"ms": m3b, "G_pairs_per_s": pp3 / m3b / 1e6}
+        frac3b = pp3 / (m3b * 1e-3) * C_ALG["energy_total_f32"] / VALU_PEAK
+        sec["energy_f32_2^18_total_only"] = {
+            "ms": m3b, "G_pairs_per_s": pp3 / m3b / 1e6, "valu_frac": frac3b,
+            "per_pair_ops": C_ALG["energy_total_f32"], "sclk_mhz_measured": mhz3b,
+            "valu_frac_at_measured_sclk": at_sclk(frac3b, mhz3b),
+            "rel_err_total_vs_fp64_oracle": abs(float(tot.item()) - golden()["config3_energy_total"])
+                                            / golden()["config3_energy_total"]}
         log(f"[bench] energy_f64 N={n3}")
         t3d = [v.to(torch.float64) for v in t3]
         ms5, _ = timed_steps(lambda: P.pairs_energy_f64(*t3d, float(np.float32(1e-4)), E, tot),

@@ -377,11 +377,18 @@ pairs_status_t pairs_graph_destroy(pairs_graph_t graph);
  *   is 1; chunk as for the broadcast form.  The default tables do not use
  *   it: on gfx950 it runs slower than the broadcast form.
  *
- * Tables are per kind (PAIRS_KIND_*) and per mode (batched = 0: single-set
- * calls, 1: batched calls and plans).  A plan keeps the table of its
+ * Tables are per kind (PAIRS_KIND_*) and per mode, the `batched` argument:
+ * PAIRS_SHAPES_SINGLE (0) single-set calls, PAIRS_SHAPES_BATCHED (1) batched
+ * calls and plans, and PAIRS_SHAPES_TOTAL_ONLY (2) single-set calls of
+ * pairs_energy_f32 with d_energy = NULL (kind PAIRS_KIND_ENERGY_F32 only: a
+ * total alone has no partner-side sums, and runs best with one row per lane).
+ * Other values give PAIRS_ERR_INVALID_ARG.  A plan keeps the table of its
  * creation.  set(NULL) restores the defaults.  Results never depend on the
  * shapes; only the speed does.
  */
+#define PAIRS_SHAPES_SINGLE 0
+#define PAIRS_SHAPES_BATCHED 1
+#define PAIRS_SHAPES_TOTAL_ONLY 2
 #define PAIRS_FORM_BROADCAST 0
 #define PAIRS_FORM_STEPPING 1
 #define PAIRS_FORM_MATRIX 2

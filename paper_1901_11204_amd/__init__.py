@@ -24,6 +24,7 @@ __all__ = [
     "pairs_force_f32_batched", "pairs_energy_f64_batched",
     "pairs_jitter_f32", "pairs_debug_task_ranges",
     "pairs_debug_step_ranges", "pairs_debug_single_launch", "pairs_debug_task_at", "FORM_BROADCAST", "FORM_STEPPING", "FORM_MATRIX",
+    "SHAPES_SINGLE", "SHAPES_BATCHED", "SHAPES_TOTAL_ONLY",
     "KIND_ENERGY_F64", "KIND_FORCE_F32",
     "Plan", "Graph", "ShapeTable", "pairs_get_shapes", "pairs_set_shapes",
     "count_i32", "count_f32", "energy_f32",
@@ -80,6 +81,7 @@ _int = ctypes.c_int
 FORM_BROADCAST = 0
 FORM_STEPPING = 1
 FORM_MATRIX = 2
+SHAPES_SINGLE, SHAPES_BATCHED, SHAPES_TOTAL_ONLY = 0, 1, 2
 
 
 class ShapeTable(ctypes.Structure):
@@ -534,19 +536,27 @@ def pairs_debug_single_launch(kind: int, n: int):
     return int(t.value), int(b.value), int(w.value)
 
 
-def pairs_get_shapes(kind: int, batched: bool):
-    """The tile-shape table as a list of (min_n, rows_per_lane, chunk, form)."""
+def _shape_mode(batched) -> int:
+    """False/True (single-set or batched calls) or a SHAPES_* mode."""
+    return int(batched) if isinstance(batched, int) and not isinstance(batched, bool) \
+        else int(bool(batched))
+
+
+def pairs_get_shapes(kind: int, batched):
+    """The tile-shape table as a list of (min_n, rows_per_lane, chunk, form);
+    batched: False/True or SHAPES_SINGLE, SHAPES_BATCHED, SHAPES_TOTAL_ONLY."""
     t = ShapeTable()
-    _check(lib().pairs_get_shapes(kind, int(bool(batched)), ctypes.byref(t)), "pairs_get_shapes")
+    _check(lib().pairs_get_shapes(kind, _shape_mode(batched), ctypes.byref(t)),
+           "pairs_get_shapes")
     return [(t.min_n[c], t.rows_per_lane[c], t.chunk[c], t.form[c]) for c in range(t.count)]
 
 
-def pairs_set_shapes(kind: int, batched: bool, entries) -> None:
+def pairs_set_shapes(kind: int, batched, entries) -> None:
     """Set the tile-shape table from (min_n, rows_per_lane, chunk[, form])
     entries, largest sets first (form defaults to FORM_BROADCAST); None
-    restores the defaults."""
+    restores the defaults.  batched as for pairs_get_shapes."""
     if entries is None:
-        _check(lib().pairs_set_shapes(kind, int(bool(batched)), None), "pairs_set_shapes")
+        _check(lib().pairs_set_shapes(kind, _shape_mode(batched), None), "pairs_set_shapes")
         return
     t = ShapeTable()
     t.count = len(entries)
@@ -554,7 +564,7 @@ def pairs_set_shapes(kind: int, batched: bool, entries) -> None:
         lo, k, u = e[:3]
         form = e[3] if len(e) > 3 else FORM_BROADCAST
         t.min_n[c], t.rows_per_lane[c], t.chunk[c], t.form[c] = int(lo), int(k), int(u), int(form)
-    _check(lib().pairs_set_shapes(kind, int(bool(batched)), ctypes.byref(t)), "pairs_set_shapes")
+    _check(lib().pairs_set_shapes(kind, _shape_mode(batched), ctypes.byref(t)), "pairs_set_shapes")
 
 
 class Plan:

@@ -23,7 +23,8 @@ import sys
 import time
 
 from . import (FORM_BROADCAST, FORM_MATRIX, FORM_STEPPING, KIND_COUNT_F32, KIND_COUNT_I32,
-               KIND_ENERGY_F32, Plan, pairs_get_shapes, pairs_set_shapes)
+               KIND_ENERGY_F32, SHAPES_BATCHED, SHAPES_SINGLE, SHAPES_TOTAL_ONLY, Plan,
+               pairs_get_shapes, pairs_set_shapes)
 
 ROWS = (1, 2, 4, 8)
 CHUNKS = (128, 256, 512, 1024, 2048, 4096, 8192)
@@ -41,6 +42,7 @@ def candidates(batched: bool):
     return out
 KIND_NAMES = {KIND_COUNT_I32: "count_i32", KIND_COUNT_F32: "count_f32",
               KIND_ENERGY_F32: "energy_f32"}
+MODE_NAMES = {SHAPES_SINGLE: "single", SHAPES_BATCHED: "batched", SHAPES_TOTAL_ONLY: "total_only"}
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_shapes.json")
 
 
@@ -149,10 +151,11 @@ def single_candidates(kind, rows=ROWS, chunks=CHUNKS):
 
 
 def tune_single(kind, n_values, make_call, start=None, log=print, rows=ROWS, chunks=CHUNKS,
-                trace=None):
+                trace=None, mode=SHAPES_SINGLE):
     """For each size n (largest first) pick the (K, U, form) with the fastest
-    single-set call; make_call(n) returns a zero-argument callable.  Returns
-    the table and the best time of each size."""
+    single-set call; make_call(n) returns a zero-argument callable.  mode:
+    SHAPES_SINGLE, or SHAPES_TOTAL_ONLY for float32 energies without
+    per-object output.  Returns the table and the best time of each size."""
     entries, times = [], []
     ns = sorted(n_values, reverse=True)
     if not 1 <= len(ns) <= 4:
@@ -162,7 +165,7 @@ def tune_single(kind, n_values, make_call, start=None, log=print, rows=ROWS, chu
         best = None
         lo = ns[i + 1] if i + 1 < len(ns) else 0
         for k, u, form in single_candidates(kind, rows, chunks):
-            pairs_set_shapes(kind, False, entries + [(lo, k, u, form)])
+            pairs_set_shapes(kind, mode, entries + [(lo, k, u, form)])
             ms = _time(call)
             if trace:
                 trace(f"    n={n} K={k} U={u} form={form}: {ms:.3f} ms")
@@ -171,7 +174,7 @@ def tune_single(kind, n_values, make_call, start=None, log=print, rows=ROWS, chu
         entries.append((lo,) + best[1:])
         times.append(best[0])
         log(f"n={n}: K={best[1]} U={best[2]} form={best[3]} {best[0]:.3f} ms")
-    pairs_set_shapes(kind, False, entries)
+    pairs_set_shapes(kind, mode, entries)
     return entries, times
 
 
@@ -192,16 +195,19 @@ def load_cache(path=None, apply=True):
             if d_arch != a:
                 continue
             kind = {v: k for k, v in KIND_NAMES.items()}[kind_name]
-            pairs_set_shapes(kind, mode == "batched", [_entry(e) for e in entry["table"]])
+            mode = {v: k for k, v in MODE_NAMES.items()}[mode]
+            pairs_set_shapes(kind, mode, [_entry(e) for e in entry["table"]])
     return data
 
 
 def save_cache(path, kind, batched, table, note, ms):
+    """Store a table under arch/kind/mode; batched: False/True or a SHAPES_* mode."""
     data = {"tables": {}}
     if os.path.exists(path):
         with open(path) as f:
             data = json.load(f)
-    key = f"{arch()}/{KIND_NAMES[kind]}/{'batched' if batched else 'single'}"
+    mode = int(batched)
+    key = f"{arch()}/{KIND_NAMES[kind]}/{MODE_NAMES[mode]}"
     data.setdefault("tables", {})[key] = {"table": [list(e) for e in table], "workload": note,
                                           "ms": ms, "when": time.strftime("%Y-%m-%d")}
     with open(path, "w") as f:
@@ -218,7 +224,7 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["binned-int32", "particles-f32", "single-int32",
-                                           "single-energy"],
+                                           "single-energy", "single-energy-total"],
                     default="binned-int32")
     ap.add_argument("--out", default=DEFAULT_CACHE)
     ap.add_argument("--rounds", type=int, default=1)
@@ -232,6 +238,7 @@ def main(argv=None):
     if a.workload.startswith("single"):
         from . import count_i32, energy_f32
         ns = [int(v) for v in a.sizes.split(",")]
+        mode = SHAPES_SINGLE
         if a.workload == "single-int32":
             kind, note = KIND_COUNT_I32, "single int32 sets, centres in [0,2^24)^3, radii [1,2^14]"
 
@@ -239,14 +246,21 @@ def main(argv=None):
                 t = [torch.from_numpy(v).to(dev) for v in w.spheres_i32(n, 2, 2 ** 24,
                                                                           2 ** 14).arrays()]
                 return lambda: count_i32(*t)
-        else:
+        elif a.workload == "single-energy":
             kind, note = KIND_ENERGY_F32, "single float32 particle sets in the unit cube"
 
             def make_call(n):
                 t = [torch.from_numpy(v).to(dev) for v in w.particles_f32(n, 4).arrays()]
                 return lambda: energy_f32(*t)
-        table, times = tune_single(kind, ns, make_call, log=say, trace=trace)
-        save_cache(a.out, kind, False, table, note + f"; sizes {ns}", times)
+        else:
+            kind, mode = KIND_ENERGY_F32, SHAPES_TOTAL_ONLY
+            note = "single float32 particle sets in the unit cube, total only"
+
+            def make_call(n):
+                t = [torch.from_numpy(v).to(dev) for v in w.particles_f32(n, 4).arrays()]
+                return lambda: energy_f32(*t, per_particle=False)
+        table, times = tune_single(kind, ns, make_call, log=say, trace=trace, mode=mode)
+        save_cache(a.out, kind, mode, table, note + f"; sizes {ns}", times)
         print(json.dumps({"kind": KIND_NAMES[kind], "table": table, "ms": times}), flush=True)
         return 0
     if a.workload == "binned-int32":

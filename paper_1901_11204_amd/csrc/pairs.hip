@@ -95,8 +95,22 @@ ClassTable make_table(int count, const int *lo, const int *K, const int *U, cons
     return t;
 }
 
-// Default tile shapes by kind (index kind - 1) for single sets and batches.
-ClassTable default_table(int kind, bool batched) {
+// Shape-table modes: single-set calls, batched calls and plans, and
+// single-set float32 energies without per-object output.
+constexpr int kModeSingle = 0, kModeBatched = 1, kModeTotalOnly = 2, kShapeModes = 3;
+
+// Default tile shapes by kind (index kind - 1) and mode.
+ClassTable default_table(int kind, int mode) {
+    if (mode == kModeTotalOnly) {
+        // a total alone has no partner-side sums to amortise over the rows
+        // of a lane, so large sets run one row per lane (measured by
+        // autotune.tune_single at n = 4096, 16384, 262144 and 2^20); long
+        // chunks keep the per-task atomics on the total few
+        const int lo[4] = {65536, 16384, 4096, 0}, K[4] = {1, 1, 2, 4},
+                  U[4] = {2048, 2048, 512, 128};
+        return make_table(4, lo, K, U, nullptr);
+    }
+    const bool batched = mode == kModeBatched;
     if (batched) {
         const int lo[4] = {4096, 1024, 256, 0}, K[4] = {2, 2, 2, 2},
                   U[4] = {272, 272, 272, 272},
@@ -128,13 +142,12 @@ static_assert(step_window_entries(1, 64, 287, 1) <= 64 * step_iters<1>(), "K=1 s
 static_assert(step_window_entries(2, 64, 271, 1) <= 64 * step_iters<2>(), "K=2 staging slots");
 
 std::mutex g_shape_mutex;
-ClassTable g_shapes[3][2];
-bool g_shapes_set[3][2];
+ClassTable g_shapes[3][kShapeModes];
+bool g_shapes_set[3][kShapeModes];
 
-ClassTable shapes(int kind, bool batched) {
+ClassTable shapes(int kind, int mode) {
     std::lock_guard<std::mutex> lock(g_shape_mutex);
-    return g_shapes_set[kind - 1][batched] ? g_shapes[kind - 1][batched]
-                                           : default_table(kind, batched);
+    return g_shapes_set[kind - 1][mode] ? g_shapes[kind - 1][mode] : default_table(kind, mode);
 }
 
 bool valid_table(const ClassTable &t, bool batched, int kind) {
@@ -1224,9 +1237,10 @@ struct Shape {
 // The double-precision energy and the forces run the float32 energy's shapes
 // with at most 4 rows per lane: their rows and partner sums take twice the
 // registers.
-Shape single_set_shape(int kind, int64_t n) {
+Shape single_set_shape(int kind, int64_t n, bool total_only = false) {
     const bool wide = kind == PAIRS_KIND_ENERGY_F64 || kind == PAIRS_KIND_FORCE_F32;
-    const ClassTable t = shapes(wide ? PAIRS_KIND_ENERGY_F32 : kind, false);
+    const ClassTable t = shapes(wide ? PAIRS_KIND_ENERGY_F32 : kind,
+                                !wide && total_only ? kModeTotalOnly : kModeSingle);
     const int c = t.class_of((int)n);
     return {wide ? std::min(t.K[c], 4) : t.K[c], t.U[c], t.form[c]};
 }
@@ -1404,7 +1418,7 @@ pairs_status_t batched_common(int kind, const BatchIO &io, int64_t n_sets, void 
     const ClassTable ct = shapes(kind == kCountI32   ? PAIRS_KIND_COUNT_I32
                                  : kind == kCountF32 ? PAIRS_KIND_COUNT_F32
                                                      : PAIRS_KIND_ENERGY_F32,
-                                 true);
+                                 kModeBatched);
     const unsigned nb = (unsigned)L.nb;
     k_sched_count<<<nb, kSchedBlock, 0, s>>>(io.off, n_sets, io.n_total, ct, blk);
     k_sched_scan<<<1, kSchedBlock, 0, s>>>(blk, L.nb, hdr);
@@ -1863,7 +1877,7 @@ pairs_status_t pairs_energy_f32(const float *x, const float *y, const float *z, 
     const double emax = energy_term_bound(eps2), dn = (double)n;
     const SumSink E = sink(d_energy, det, (dn - 1.0) * emax);
     const SumSink T = sink(d_total, det, 0.5 * dn * (dn - 1.0) * emax);
-    Shape sh = single_set_shape(PAIRS_KIND_ENERGY_F32, n);
+    Shape sh = single_set_shape(PAIRS_KIND_ENERGY_F32, n, d_energy == nullptr);
     switch (sh.K) {
         case 1: launch_energy<1>(x, y, z, (int)n, sh.U, eps2, E, T, s); break;
         case 2: launch_energy<2>(x, y, z, (int)n, sh.U, eps2, E, T, s); break;
@@ -2109,7 +2123,7 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
     PAIRS_TRY(current_device(&dev));
     DeviceState *st;
     PAIRS_TRY(device_state(&st));
-    const ClassTable ct = shapes(kind, true);
+    const ClassTable ct = shapes(kind, kModeBatched);
     const int kmax = max_rows(ct);
     const int kk = kind == PAIRS_KIND_COUNT_I32 ? kCountI32
                    : kind == PAIRS_KIND_COUNT_F32 ? kCountF32 : kEnergyF32;
@@ -2497,10 +2511,18 @@ pairs_status_t pairs_graph_destroy(pairs_graph_t graph) {
     return PAIRS_OK;
 }
 
+// A shape mode exists for every kind but the total-only one, which only the
+// float32 energy has.
+bool valid_mode(int kind, int mode) {
+    return mode == kModeSingle || mode == kModeBatched ||
+           (mode == kModeTotalOnly && kind == PAIRS_KIND_ENERGY_F32);
+}
+
 pairs_status_t pairs_get_shapes(int kind, int batched, pairs_shape_table_t *out) {
-    if (!out || kind < PAIRS_KIND_COUNT_I32 || kind > PAIRS_KIND_ENERGY_F32)
+    if (!out || kind < PAIRS_KIND_COUNT_I32 || kind > PAIRS_KIND_ENERGY_F32 ||
+        !valid_mode(kind, batched))
         return PAIRS_ERR_INVALID_ARG;
-    const ClassTable t = shapes(kind, batched != 0);
+    const ClassTable t = shapes(kind, batched);
     out->count = t.count;
     for (int c = 0; c < 4; ++c) {
         out->min_n[c] = t.lo[c];
@@ -2512,18 +2534,19 @@ pairs_status_t pairs_get_shapes(int kind, int batched, pairs_shape_table_t *out)
 }
 
 pairs_status_t pairs_set_shapes(int kind, int batched, const pairs_shape_table_t *table) {
-    if (kind < PAIRS_KIND_COUNT_I32 || kind > PAIRS_KIND_ENERGY_F32) return PAIRS_ERR_INVALID_ARG;
+    if (kind < PAIRS_KIND_COUNT_I32 || kind > PAIRS_KIND_ENERGY_F32 || !valid_mode(kind, batched))
+        return PAIRS_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(g_shape_mutex);
     if (!table) {
-        g_shapes_set[kind - 1][batched != 0] = false;
+        g_shapes_set[kind - 1][batched] = false;
         return PAIRS_OK;
     }
     if (table->count < 1 || table->count > kMaxClasses) return PAIRS_ERR_INVALID_ARG;
     ClassTable t = make_table(table->count, table->min_n, table->rows_per_lane, table->chunk,
                               table->form);
-    if (!valid_table(t, batched != 0, kind)) return PAIRS_ERR_INVALID_ARG;
-    g_shapes[kind - 1][batched != 0] = t;
-    g_shapes_set[kind - 1][batched != 0] = true;
+    if (!valid_table(t, batched == kModeBatched, kind)) return PAIRS_ERR_INVALID_ARG;
+    g_shapes[kind - 1][batched] = t;
+    g_shapes_set[kind - 1][batched] = true;
     return PAIRS_OK;
 }
 

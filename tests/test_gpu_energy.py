@@ -52,6 +52,27 @@ def test_energy_every_shape(K, U):
         P.pairs_set_shapes(P.KIND_ENERGY_F32, False, None)
 
 
+@pytest.mark.parametrize("K,U", [(1, 64), (1, 2048), (2, 256), (8, 1024)])
+def test_energy_total_only_every_shape(K, U):
+    """The total-only table (mode SHAPES_TOTAL_ONLY) drives calls without
+    per-object output, and only those."""
+    P.pairs_set_shapes(P.KIND_ENERGY_F32, P.SHAPES_TOTAL_ONLY, [(0, K, U)])
+    try:
+        assert P.pairs_get_shapes(P.KIND_ENERGY_F32, P.SHAPES_TOTAL_ONLY) == \
+            [(0, K, U, P.FORM_BROADCAST)]
+        for n in (2, 64 * K - 1, 64 * K + 1, 2 * 64 * K + 5, 3001, 20000):
+            p = w.particles_f32(n, 300 + n)
+            announce("energy_f32 total only", K, U, n)
+            _, tot = P.energy_f32(*dev(*p.arrays()), eps2=float(EPS2), per_particle=False)
+            want_tot = oracle.energy_total(*p.arrays(), EPS2)
+            assert abs(tot - want_tot) <= TOL_TOTAL * want_tot, (K, U, n)
+            _, tot_r = P.energy_f32(*dev(*p.arrays()), eps2=float(EPS2), per_particle=False,
+                                    deterministic=True)
+            assert abs(tot_r - want_tot) <= TOL_TOTAL * want_tot, (K, U, n)
+    finally:
+        P.pairs_set_shapes(P.KIND_ENERGY_F32, P.SHAPES_TOTAL_ONLY, None)
+
+
 @pytest.mark.parametrize("n", [0, 1])
 def test_energy_no_pairs(n):
     p = w.particles_f32(n, 1)

@@ -117,6 +117,32 @@ def test_step_shapes_rejected():
     P.pairs_set_shapes(P.KIND_COUNT_I32, True, None)
 
 
+def test_total_only_shape_mode():
+    """Mode 2 holds the float32 energy's total-only table (one row per lane
+    for large sets by default); other kinds and modes beyond 2 are rejected."""
+    E = P.KIND_ENERGY_F32
+    default = P.pairs_get_shapes(E, P.SHAPES_TOTAL_ONLY)
+    assert default[0][1] == 1 and default[0][0] >= 65536
+    assert P.pairs_get_shapes(E, P.SHAPES_SINGLE) != default
+    P.pairs_set_shapes(E, P.SHAPES_TOTAL_ONLY, [(0, 2, 512)])
+    assert P.pairs_get_shapes(E, P.SHAPES_TOTAL_ONLY) == [(0, 2, 512, P.FORM_BROADCAST)]
+    assert P.pairs_get_shapes(E, P.SHAPES_SINGLE) != [(0, 2, 512, P.FORM_BROADCAST)]
+    P.pairs_set_shapes(E, P.SHAPES_TOTAL_ONLY, None)
+    assert P.pairs_get_shapes(E, P.SHAPES_TOTAL_ONLY) == default
+    for kind in (P.KIND_COUNT_I32, P.KIND_COUNT_F32):
+        with pytest.raises(P.PairsError):
+            P.pairs_get_shapes(kind, P.SHAPES_TOTAL_ONLY)
+        with pytest.raises(P.PairsError):
+            P.pairs_set_shapes(kind, P.SHAPES_TOTAL_ONLY, [(0, 1, 256)])
+    for mode in (3, -1):
+        with pytest.raises(P.PairsError):
+            P.pairs_get_shapes(E, mode)
+        with pytest.raises(P.PairsError):
+            P.pairs_set_shapes(E, mode, None)
+    with pytest.raises(P.PairsError):   # the stepping form is for batches only
+        P.pairs_set_shapes(E, P.SHAPES_TOTAL_ONLY, [(0, 1, 64, P.FORM_STEPPING)])
+
+
 def test_matrix_shapes_rejected():
     """The matrix form takes single-set int32 count tables only, with one row
     per lane and chunks that are multiples of 64."""
