@@ -2264,24 +2264,52 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
     if (n_waves < 1) n_waves = 1;
     n_waves = std::min<int64_t>(n_waves, std::max<int64_t>(ntasks, 1));
 
-    // longest processing time first: each task, largest first, goes to the
-    // wave with the least work so far
+    // Wave list w runs as workgroup w, which the dispatcher deals to XCD
+    // w % kXcds; each XCD has its own L2.  All tasks of one set go to the
+    // lists of one XCD, so that a set's objects are fetched into one L2 only:
+    // sets (and packs) are dealt to the XCDs by longest processing time first,
+    // then within each XCD every task, largest first, goes to the list with
+    // the least work so far.
+    const int groups = n_waves >= kXcds ? kXcds : 1;
     std::vector<int32_t> order((size_t)ntasks);
     for (int64_t k = 0; k < ntasks; ++k) order[(size_t)k] = (int32_t)k;
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return cost[(size_t)a] > cost[(size_t)b]; });
+    std::vector<int8_t> group_of((size_t)ntasks, 0);
+    if (groups > 1) {
+        // a unit is a set split into row-block tasks, or one pack
+        std::map<int64_t, int64_t> unit_cost;
+        auto unit = [&](int64_t t) -> int64_t {
+            const TaskDesc &d = tasks[(size_t)t];
+            return d.set >= 0 ? (int64_t)d.set : n_sets + d.base;
+        };
+        for (int64_t t = 0; t < ntasks; ++t) unit_cost[unit(t)] += cost[(size_t)t];
+        std::vector<std::pair<int64_t, int64_t>> units(unit_cost.begin(), unit_cost.end());
+        std::stable_sort(units.begin(), units.end(),
+                         [](const std::pair<int64_t, int64_t> &a,
+                            const std::pair<int64_t, int64_t> &b) { return a.second > b.second; });
+        std::map<int64_t, int8_t> unit_group;
+        int64_t load[kXcds] = {0};
+        for (const auto &u : units) {
+            const int g = (int)(std::min_element(load, load + groups) - load);
+            load[g] += u.second;
+            unit_group[u.first] = (int8_t)g;
+        }
+        for (int64_t t = 0; t < ntasks; ++t) group_of[(size_t)t] = unit_group[unit(t)];
+    }
     std::vector<int32_t> owner((size_t)ntasks);
     std::vector<int32_t> per_wave((size_t)n_waves, 0);
     {
         typedef std::pair<int64_t, int32_t> Load;  // (work, wave)
-        std::vector<Load> heap;
-        heap.reserve((size_t)n_waves);
-        for (int64_t w = 0; w < n_waves; ++w) heap.push_back(Load(0, (int32_t)w));
         auto cmp = [](const Load &a, const Load &b) { return a > b; };  // min-heap
+        std::vector<std::vector<Load>> heaps((size_t)groups);
+        for (int64_t w = 0; w < n_waves; ++w)
+            heaps[(size_t)(w % groups)].push_back(Load(0, (int32_t)w));
         for (int64_t k = 0; k < ntasks; ++k) {
+            const int32_t t = order[(size_t)k];
+            std::vector<Load> &heap = heaps[(size_t)group_of[(size_t)t]];
             std::pop_heap(heap.begin(), heap.end(), cmp);
             Load &l = heap.back();
-            const int32_t t = order[(size_t)k];
             owner[(size_t)t] = l.second;
             per_wave[(size_t)l.second]++;
             l.first += cost[(size_t)t];
