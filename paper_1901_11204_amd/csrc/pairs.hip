@@ -868,9 +868,11 @@ __device__ __forceinline__ void run_task(const BatchIO &io, int64_t base, const 
 // Plans: wave w runs the tasks descs[wave_start[w] .. wave_start[w+1]), a list
 // balanced across the waves on the host; the next descriptor is fetched while
 // the current task runs.
-// Wave lists of a plan per resident wave, and blocks of an unplanned call per
+// Wave lists of a plan per resident wave (short lists: the hardware starts a
+// waiting workgroup as soon as a resident one finishes, which evens out what
+// the host's cost estimate misses), and blocks of an unplanned call per
 // resident block.
-constexpr int kPlanWaveFactor = 16;
+constexpr int kPlanWaveFactor = 64;
 constexpr int kScanBlockFactor = 16;
 
 // Waves per SIMD the batched kernels are compiled for: four where the
@@ -2128,9 +2130,9 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
     const int kk = kind == PAIRS_KIND_COUNT_I32 ? kCountI32
                    : kind == PAIRS_KIND_COUNT_F32 ? kCountF32 : kEnergyF32;
     int64_t n_waves = 0;
-    // Task lists for sixteen times the resident waves: the lists are balanced
-    // by a cost estimate, and as resident waves finish, the hardware starts
-    // the waiting ones, which evens out what the estimate misses.
+    // Task lists for kPlanWaveFactor times the resident waves: the lists are
+    // balanced by a cost estimate, and as resident waves finish, the hardware
+    // starts the waiting ones, which evens out what the estimate misses.
     with_plan_kernel(kk, kmax, [&](auto kern) {
         n_waves = resident_blocks(st, kern, kBatchBlock) * kBatchWaves * kPlanWaveFactor;
     });
