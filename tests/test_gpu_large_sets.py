@@ -71,6 +71,24 @@ def test_count_i32_grid_stride_small_tiles(small_tiles):
     assert P.count_i32(*dev(x, y, z, r2)) == 3 * m * m * (m - 1) + 26
 
 
+def test_count_i32_matrix_form_grid_stride():
+    """The matrix-core form with 64-partner chunks: 405 224 objects need the
+    grid stride; the lattice's closed form with one grown sphere."""
+    P.pairs_set_shapes(P.KIND_COUNT_I32, False, [(0, 1, 64, P.FORM_MATRIX)])
+    try:
+        m = 74
+        x, y, z = cubic_lattice(m, 6, np.int32, 4)
+        r = np.full(m ** 3, 3, np.int32)
+        assert strides(P.KIND_COUNT_I32, m ** 3)
+        announce("count_i32 matrix form grid stride", m)
+        assert P.count_i32(*dev(x, y, z, r)) == 3 * m * m * (m - 1)
+        centre = int(np.flatnonzero((x == 40 * 6) & (y == 20 * 6) & (z == 50 * 6))[0])
+        r[centre] = 9
+        assert P.count_i32(*dev(x, y, z, r)) == 3 * m * m * (m - 1) + 26
+    finally:
+        P.pairs_set_shapes(P.KIND_COUNT_I32, False, None)
+
+
 def test_count_f32_grid_stride_small_tiles(small_tiles):
     small_tiles(P.KIND_COUNT_F32)
     m = 74
