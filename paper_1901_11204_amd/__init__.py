@@ -537,9 +537,12 @@ def pairs_debug_single_launch(kind: int, n: int):
 
 
 def _shape_mode(batched) -> int:
-    """False/True (single-set or batched calls) or a SHAPES_* mode."""
-    return int(batched) if isinstance(batched, int) and not isinstance(batched, bool) \
-        else int(bool(batched))
+    """False/True (single-set or batched calls) or a SHAPES_* mode (any
+    integral type)."""
+    import numbers
+    if isinstance(batched, numbers.Integral):   # bool is integral too: 0 or 1
+        return int(batched)
+    return int(bool(batched))
 
 
 def pairs_get_shapes(kind: int, batched):
