@@ -49,7 +49,7 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 // The batched kernels run one wave per workgroup: a wave's LDS window is its
 // workgroup's, so a wave that finishes early frees its slot at once rather
 // than when the slowest wave of a four-wave workgroup is done (the unplanned
-// config-4 call: 1.49 -> 1.43 ms).
+// count of 200 000 binned sets of lognormal sizes: 1.49 -> 1.43 ms).
 constexpr int kBatchWaves = 1;
 constexpr int kBatchBlock = kWave * kBatchWaves;
 
