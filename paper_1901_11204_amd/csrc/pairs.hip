@@ -504,7 +504,7 @@ __global__ __launch_bounds__(kSchedBlock) void k_sched_count(const int64_t *__re
 // class bases and the totals.
 __global__ __launch_bounds__(kSchedBlock) void k_sched_scan(int64_t *blk, int64_t nb,
                                                             SchedHeader *hdr) {
-    __shared__ int64_t part[kSchedBlock];
+    __shared__ int64_t wave_tot[kSchedBlock / kWave + 1];
     __shared__ int64_t total[2 * kMaxClasses];
     const int tid = threadIdx.x;
     const int64_t chunk = (nb + kSchedBlock - 1) / kSchedBlock;
@@ -512,26 +512,18 @@ __global__ __launch_bounds__(kSchedBlock) void k_sched_scan(int64_t *blk, int64_
     for (int q = 0; q < 2 * kMaxClasses; ++q) {
         int64_t sum = 0;
         for (int64_t b = b0; b < b1; ++b) sum += blk[b * 2 * kMaxClasses + q];
-        part[tid] = sum;
-        __syncthreads();
-        if (tid == 0) {  // exclusive scan of the thread sums
-            int64_t run = 0;
-            for (int k = 0; k < kSchedBlock; ++k) {
-                const int64_t v = part[k];
-                part[k] = run;
-                run += v;
-            }
-            total[q] = run;
-        }
-        __syncthreads();
-        int64_t run = part[tid];
+        // exclusive scan of the thread sums across the block (wave shuffles,
+        // then the wave totals)
+        int64_t tot;
+        int64_t run = block_exclusive_scan<kSchedBlock>(sum, wave_tot, &tot);
+        if (tid == 0) total[q] = tot;
         for (int64_t b = b0; b < b1; ++b) {
             const int64_t v = blk[b * 2 * kMaxClasses + q];
             blk[b * 2 * kMaxClasses + q] = run;
             run += v;
         }
-        __syncthreads();
     }
+    __syncthreads();
     if (tid == 0) {
         int64_t ls = 0, ts = 0;
         for (int c = 0; c < kMaxClasses; ++c) {
