@@ -85,7 +85,7 @@ def log(*a):
 
 
 class SclkSampler:
-    """Mean engine clock (MHz) while a region runs, read every few ms from the
+    """Engine clock (MHz) while a region runs, read every few ms from the
     amdgpu driver's sysfs table (the current level is the one marked '*');
     None where the box does not expose it."""
 
@@ -128,29 +128,36 @@ class SclkSampler:
             self.thread.join()
 
     def mean_mhz(self):
+        """The mean of samples taken at a fixed period: the time average of a
+        clock that moves between levels while the region runs."""
         return sum(self.samples) / len(self.samples) if self.samples else None
 
 
-def timed_steps(fn, steps, warmup):
+def timed_steps(fn, steps, warmup, sampler=None):
+    """Milliseconds of each of `steps` calls after `warmup` untimed ones; a
+    SclkSampler given as `sampler` reads the clock over the timed calls only
+    (the first calls after an idle spell run while the clock ramps up)."""
+    import contextlib
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    t0 = time.perf_counter()
-    for k in range(steps):
-        starts[k].record()
-        fn()
-        ends[k].record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    with sampler if sampler is not None else contextlib.nullcontext():
+        t0 = time.perf_counter()
+        for k in range(steps):
+            starts[k].record()
+            fn()
+            ends[k].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     return ms, wall
 
 
 def sclk_during(fn, seconds=0.25):
-    """Mean engine clock (MHz) while fn runs back to back for about `seconds`
+    """Engine clock (MHz) while fn runs back to back for about `seconds`
     (None where the clock is not exposed): the VALU fraction of a kernel at
     the clock it actually ran at.  Run before a line's timed steps, it is
     also their warm-up: a millisecond-scale call timed after two warm-up
@@ -688,8 +695,8 @@ def main():
     out = torch.empty(1, dtype=torch.int64, device=dev)
     pairs = n * (n - 1) // 2
     log(f"[bench] count_i32 N={n}: {a.warmup} warmup + {a.steps} timed steps")
-    with SclkSampler() as sclk:
-        ms, wall = timed_steps(lambda: P.pairs_count_i32(x, y, z, r, out), a.steps, a.warmup)
+    sclk = SclkSampler()
+    ms, wall = timed_steps(lambda: P.pairs_count_i32(x, y, z, r, out), a.steps, a.warmup, sclk)
     ms_step = float(np.mean(ms))
     sclk_mhz = sclk.mean_mhz()
     value = pairs / (ms_step * 1e-3) / 1e9
@@ -731,7 +738,8 @@ def main():
                      "frac_at_measured_sclk": (achieved / (N_CU * VALU_LANES_PER_CU *
                                                            sclk_mhz * 1e6)
                                                if sclk_mhz else None),
-                     "sclk_source": ("amdgpu sysfs pp_dpm_sclk, sampled during the timed steps"
+                     "sclk_source": ("amdgpu sysfs pp_dpm_sclk, mean of samples every 2 ms "
+                                     "during the timed steps"
                                      if sclk_mhz else "not exposed on this box")},
     }
 
