@@ -635,6 +635,10 @@ def main():
                     help="with --binned-only: which binned workloads")
     ap.add_argument("--config4-slices", action="store_true",
                     help="only config 4's sets split by size, each slice timed alone")
+    ap.add_argument("--count-form", choices=["broadcast", "broadcast-k1", "matrix"],
+                    help="only the N=2^20 count with one single-set shape (for profiling): "
+                         "the default table, or 64-row tasks of 4096 partners on the VALU "
+                         "or on the matrix cores")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
@@ -666,6 +670,20 @@ def main():
 
     if a.batched_only:
         print(json.dumps({"batched": bench_batched(P, w, torch, np, dev, a.steps)}), flush=True)
+        return
+    if a.count_form:
+        t = tuple(torch.from_numpy(v).to(dev) for v in w.config2(2 ** 20).arrays())
+        out = torch.empty(1, dtype=torch.int64, device=dev)
+        shapes = {"broadcast-k1": [(0, 1, 4096, P.FORM_BROADCAST)],
+                  "matrix": [(0, 1, 4096, P.FORM_MATRIX)]}.get(a.count_form)
+        if shapes:
+            P.pairs_set_shapes(P.KIND_COUNT_I32, False, shapes)
+        ms, _ = timed_steps(lambda: P.pairs_count_i32(*t, out), a.steps, a.warmup)
+        P.pairs_set_shapes(P.KIND_COUNT_I32, False, None)
+        pairs = 2 ** 20 * (2 ** 20 - 1) // 2
+        print(json.dumps({"count_form": a.count_form, "ms": float(np.mean(ms)),
+                          "G_pairs_per_s": pairs / float(np.mean(ms)) / 1e6,
+                          "count": int(out.item())}), flush=True)
         return
     if a.config4_slices:
         print(json.dumps({"config4_size_slices": config4_size_slices(P, w, torch, np, dev,
