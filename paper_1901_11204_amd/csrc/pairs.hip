@@ -2271,25 +2271,35 @@ pairs_status_t pairs_plan_create(int kind, const int64_t *h_offsets, int64_t n_s
                      [&](int32_t a, int32_t b) { return cost[(size_t)a] > cost[(size_t)b]; });
     std::vector<int8_t> group_of((size_t)ntasks, 0);
     if (groups > 1) {
-        // a unit is a set split into row-block tasks, or one pack
-        std::map<int64_t, int64_t> unit_cost;
+        // a unit is a set split into row-block tasks (id: the set), or one
+        // pack (id: n_sets + its first entry in pack_base)
+        const int64_t nunits = n_sets + (int64_t)pack_base.size();
         auto unit = [&](int64_t t) -> int64_t {
             const TaskDesc &d = tasks[(size_t)t];
             return d.set >= 0 ? (int64_t)d.set : n_sets + d.base;
         };
-        for (int64_t t = 0; t < ntasks; ++t) unit_cost[unit(t)] += cost[(size_t)t];
-        std::vector<std::pair<int64_t, int64_t>> units(unit_cost.begin(), unit_cost.end());
-        std::stable_sort(units.begin(), units.end(),
-                         [](const std::pair<int64_t, int64_t> &a,
-                            const std::pair<int64_t, int64_t> &b) { return a.second > b.second; });
-        std::map<int64_t, int8_t> unit_group;
-        int64_t load[kXcds] = {0};
-        for (const auto &u : units) {
-            const int g = (int)(std::min_element(load, load + groups) - load);
-            load[g] += u.second;
-            unit_group[u.first] = (int8_t)g;
+        std::vector<int64_t> unit_cost;
+        std::vector<int64_t> units;
+        std::vector<int8_t> unit_group;
+        try {
+            unit_cost.assign((size_t)nunits, 0);
+            unit_group.assign((size_t)nunits, 0);
+            for (int64_t t = 0; t < ntasks; ++t) unit_cost[(size_t)unit(t)] += cost[(size_t)t];
+            for (int64_t u = 0; u < nunits; ++u)
+                if (unit_cost[(size_t)u] > 0) units.push_back(u);
+        } catch (const std::bad_alloc &) {
+            return PAIRS_ERR_NO_MEMORY;
         }
-        for (int64_t t = 0; t < ntasks; ++t) group_of[(size_t)t] = unit_group[unit(t)];
+        std::stable_sort(units.begin(), units.end(), [&](int64_t a, int64_t b) {
+            return unit_cost[(size_t)a] > unit_cost[(size_t)b];
+        });
+        int64_t load[kXcds] = {0};
+        for (const int64_t u : units) {
+            const int g = (int)(std::min_element(load, load + groups) - load);
+            load[g] += unit_cost[(size_t)u];
+            unit_group[(size_t)u] = (int8_t)g;
+        }
+        for (int64_t t = 0; t < ntasks; ++t) group_of[(size_t)t] = unit_group[(size_t)unit(t)];
     }
     std::vector<int32_t> owner((size_t)ntasks);
     std::vector<int32_t> per_wave((size_t)n_waves, 0);
