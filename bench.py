@@ -70,7 +70,7 @@ def recorded_traffic():
         return None
 
 
-GOLDEN = os.path.join(ROOT, "tests", "golden", "config_values.json")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "workload_values.json")
 
 
 def golden():
@@ -212,7 +212,7 @@ def valu_probe(torch):
 def cpu_baseline(sample_n):
     import oracle
     import workloads as w
-    s = w.config2(2 ** 20)
+    s = w.spheres_2p24(2 ** 20)
     arrs = [a[:sample_n].copy() for a in s.arrays()]
     threads = oracle.threads(0)
     t = time.perf_counter()
@@ -241,13 +241,13 @@ def cpu_serial(oracle, w):
     pair count (every pair costs the same)."""
     import numpy as np
     out = {}
-    a1 = w.config1().arrays()
+    a1 = w.spheres_4096().arrays()
     t = time.perf_counter()
     oracle.count_i32(*a1, threads=1)
     dt = time.perf_counter() - t
     p1 = 4096 * 4095 // 2
     out["count_i32_4096"] = {"seconds": dt, "G_pairs_per_s": p1 / dt / 1e9}
-    s2 = w.config2(2 ** 20).arrays()
+    s2 = w.spheres_2p24(2 ** 20).arrays()
     rows, cols = 2 ** 12, 2 ** 17
     a = [v[:rows].copy() for v in s2]
     b = [v[rows:rows + cols].copy() for v in s2]
@@ -258,7 +258,7 @@ def cpu_serial(oracle, w):
     p2 = 2 ** 20 * (2 ** 20 - 1) // 2
     out["count_i32_2^20"] = {"sample": f"{rows} rows x {cols} partners", "seconds": dt,
                              "G_pairs_per_s": rate / 1e9, "extrapolated_full_s": p2 / rate}
-    x3, y3, z3 = w.config3().arrays()
+    x3, y3, z3 = w.particles_unit_cube().arrays()
     rows3 = 2 ** 8
     t = time.perf_counter()
     oracle.energy_rows(x3, y3, z3, np.float32(1e-4), np.arange(rows3), threads=1)
@@ -437,10 +437,10 @@ SIZE_SLICES = ((2, 16), (17, 32), (33, 64), (65, 128), (129, 256), (257, 512), (
                (1025, 2048), (2049, 8192))
 
 
-def config4_size_slices(P, w, torch, np, dev, steps):
-    """Config 4's sets split by size, each slice timed alone as its own batch
+def size_slices(P, w, torch, np, dev, steps):
+    """The 200 000 binned sets split by size, each slice timed alone as its own batch
     (a plan and the unplanned call): where the batched count's time goes."""
-    b = w.config4()
+    b = w.binned_sets()
     off, sizes = b.offsets, np.diff(b.offsets)
     arrays = b.objs.arrays()
     out = []
@@ -467,7 +467,7 @@ def config4_size_slices(P, w, torch, np, dev, steps):
         out.append({"sizes": [lo, hi], "sets": int(len(sel)), "pair_tests": pairs,
                     "plan_ms": mp, "plan_valu_frac": frac(mp),
                     "unplanned_ms": mu, "unplanned_valu_frac": frac(mu)})
-        log(f"[bench] config 4 sets of {lo}..{hi} objects: plan {mp:.4f} ms")
+        log(f"[bench] binned sets of {lo}..{hi} objects: plan {mp:.4f} ms")
     return out
 
 
@@ -476,7 +476,7 @@ def bench_batched(P, w, torch, np, dev, steps):
     plan, and the unplanned call), and the float32 repeated-step loop captured
     in one HIP graph of 100 steps."""
     out = {}
-    b = w.config4()
+    b = w.binned_sets()
     x, y, z, r = (torch.from_numpy(v).to(dev) for v in b.objs.arrays())
     sizes = np.diff(b.offsets)
     pairs = int((sizes * (sizes - 1) // 2).sum())
@@ -493,7 +493,7 @@ def bench_batched(P, w, torch, np, dev, steps):
         "valu_frac": frac, "sclk_mhz_measured": mhz, "valu_frac_at_measured_sclk": at_sclk(frac, mhz),
         "n_tasks": plan.info()["n_tasks"], "total_count": int(counts.sum().item()),
         "matches_oracle": hashlib.sha256(counts.cpu().numpy().astype("<u8").tobytes()).hexdigest()
-                          == golden()["config4_counts"]["sha256_le_u64"]}
+                          == golden()["binned_sets_200k_counts"]["sha256_le_u64"]}
     toff = torch.from_numpy(b.offsets).to(dev)
     ws = torch.empty(P.pairs_batched_workspace_size(b.n_sets, b.n_total), dtype=torch.uint8,
                      device=dev)
@@ -502,16 +502,16 @@ def bench_batched(P, w, torch, np, dev, steps):
                         max(10, steps), 2)
     m = float(np.mean(ms))
     frac = pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK
-    out.update(bench_binned_config4(P, torch, np, dev, b, (x, y, z, r), toff))
+    out.update(bench_binned_sets(P, torch, np, dev, b, (x, y, z, r), toff))
     out["count_i32_binned_200k_sets_unplanned"] = {
         "ms": m, "G_pairs_per_s": pairs / m / 1e6,
         "valu_frac": frac, "sclk_mhz_measured": mhz, "valu_frac_at_measured_sclk": at_sclk(frac, mhz),
         "matches_oracle": hashlib.sha256(counts.cpu().numpy().astype("<u8").tobytes()).hexdigest()
-                          == golden()["config4_counts"]["sha256_le_u64"]}
+                          == golden()["binned_sets_200k_counts"]["sha256_le_u64"]}
     plan.close()
     del x, y, z, r, ws
 
-    b5 = w.config5()
+    b5 = w.moving_sets()
     x, y, z, r = (torch.from_numpy(v).to(dev) for v in b5.objs.arrays())
     sizes = np.diff(b5.offsets)
     pairs5 = int((sizes * (sizes - 1) // 2).sum())
@@ -533,7 +533,7 @@ def bench_batched(P, w, torch, np, dev, steps):
         t.copy_(torch.from_numpy(v).to(dev))
     g.launch()
     torch.cuda.synchronize()
-    g5 = golden()["config5_sampled_sets"]
+    g5 = golden()["moving_sets_50k_sampled"]
     En, Cn = E.cpu().numpy(), C.cpu().numpy()
     errs, exact = [], True
     for i, st in enumerate(g5["sets"]):
@@ -555,8 +555,8 @@ def bench_batched(P, w, torch, np, dev, steps):
     return out
 
 
-def bench_binned_config4(P, torch, np, dev, b, xyzr, toff):
-    """Config 4's objects through the binned path: all 22.5 M as one set in
+def bench_binned_sets(P, torch, np, dev, b, xyzr, toff):
+    """The 200 000 binned sets' objects through the binned path: all 22.5 M as one set in
     cells of 2^14 (the sets' own grid cells, up to 8192 objects, so big cells
     and their neighbours go through the work items) and of 1024 (about twice
     the largest radius), and the 200 000 sets binned per set as a CSR batch
@@ -569,7 +569,7 @@ def bench_binned_config4(P, torch, np, dev, b, xyzr, toff):
         log(f"[bench] binned count of the {n4} objects as one set, cells of {cell}")
         msb, _ = timed_steps(lambda: P.pairs_count_i32_binned(*xyzr, cell, outb, wsb), 3, 1)
         out[f"count_i32_binned_one_set_cell{cell}"] = {
-            "workload": f"config 4's {n4} objects as one set, cells of {cell}",
+            "workload": f"the 200 000 binned sets' {n4} objects as one set, cells of {cell}",
             "ms": float(np.median(msb)), "count": int(outb.item())}
     countsb = torch.empty(b.n_sets, dtype=torch.int64, device=dev)
     for cell in (1 << 14, 4096):
@@ -577,10 +577,10 @@ def bench_binned_config4(P, torch, np, dev, b, xyzr, toff):
         msb, _ = timed_steps(lambda: P.pairs_count_i32_binned_batched(*xyzr, toff, cell, countsb,
                                                                       wsb), 3, 1)
         out[f"count_i32_binned_batched_200k_sets_cell{cell}"] = {
-            "workload": f"config 4's {b.n_sets} sets binned per set, cells of {cell}",
+            "workload": f"the {b.n_sets} sets, each binned on its own, cells of {cell}",
             "ms": float(np.median(msb)),
             "matches_oracle": hashlib.sha256(countsb.cpu().numpy().astype("<u8").tobytes())
-                              .hexdigest() == golden()["config4_counts"]["sha256_le_u64"]}
+                              .hexdigest() == golden()["binned_sets_200k_counts"]["sha256_le_u64"]}
     return out
 
 
@@ -604,7 +604,7 @@ def bench_binned(P, torch, np, dev, xyzr, steps, ms_all_pairs=None):
     bpo = 26 + 49 + 10 + 38 + 20 + 44 + 28
     res = {"ms": mb, "cell": 1 << 15, "count": int(outb.item()),
            "workspace_bytes_per_object": wsb.numel() / n,
-           "matches_oracle": int(outb.item()) == golden()["config2_even_count"],
+           "matches_oracle": int(outb.item()) == golden()["spheres_2p20_count"],
            "roofline": {"bound": "hbm", "achieved": n * bpo / (mb * 1e-3) / 1e9,
                         "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                         "frac": n * bpo / (mb * 1e-3) / HBM_PEAK, "bytes_per_object": bpo}}
@@ -630,11 +630,11 @@ def main():
     ap.add_argument("--lattice-only", action="store_true",
                     help="only the lattice-bead counts (for profiling)")
     ap.add_argument("--binned-only", action="store_true",
-                    help="only the binned counts of the 2^20 set and of config 4 (for profiling)")
-    ap.add_argument("--binned-workload", choices=["2p20", "config4", "all"], default="all",
+                    help="only the binned counts of the 2^20 set and of the 200 000 binned sets (for profiling)")
+    ap.add_argument("--binned-workload", choices=["2p20", "sets200k", "all"], default="all",
                     help="with --binned-only: which binned workloads")
-    ap.add_argument("--config4-slices", action="store_true",
-                    help="only config 4's sets split by size, each slice timed alone")
+    ap.add_argument("--size-slices", action="store_true",
+                    help="only the 200 000 binned sets split by size, each slice timed alone")
     ap.add_argument("--count-form", choices=["broadcast", "broadcast-k1", "matrix"],
                     help="only the N=2^20 count with one single-set shape (for profiling): "
                          "the default table, or 64-row tasks of 4096 partners on the VALU "
@@ -672,7 +672,7 @@ def main():
         print(json.dumps({"batched": bench_batched(P, w, torch, np, dev, a.steps)}), flush=True)
         return
     if a.count_form:
-        t = tuple(torch.from_numpy(v).to(dev) for v in w.config2(2 ** 20).arrays())
+        t = tuple(torch.from_numpy(v).to(dev) for v in w.spheres_2p24(2 ** 20).arrays())
         out = torch.empty(1, dtype=torch.int64, device=dev)
         shapes = {"broadcast-k1": [(0, 1, 4096, P.FORM_BROADCAST)],
                   "matrix": [(0, 1, 4096, P.FORM_MATRIX)]}.get(a.count_form)
@@ -685,8 +685,8 @@ def main():
                           "G_pairs_per_s": pairs / float(np.mean(ms)) / 1e6,
                           "count": int(out.item())}), flush=True)
         return
-    if a.config4_slices:
-        print(json.dumps({"config4_size_slices": config4_size_slices(P, w, torch, np, dev,
+    if a.size_slices:
+        print(json.dumps({"size_slices": size_slices(P, w, torch, np, dev,
                                                                       a.steps)}), flush=True)
         return
     if a.lattice_only:
@@ -695,20 +695,20 @@ def main():
     if a.binned_only:
         res = {}
         if a.binned_workload in ("2p20", "all"):
-            xyzr = tuple(torch.from_numpy(v).to(dev) for v in w.config2(2 ** 20).arrays())
+            xyzr = tuple(torch.from_numpy(v).to(dev) for v in w.spheres_2p24(2 ** 20).arrays())
             res["count_i32_binned_2^20"] = bench_binned(P, torch, np, dev, xyzr, a.steps)
             del xyzr
-        if a.binned_workload in ("config4", "all"):
-            b4 = w.config4()
+        if a.binned_workload in ("sets200k", "all"):
+            b4 = w.binned_sets()
             xyzr = tuple(torch.from_numpy(v).to(dev) for v in b4.objs.arrays())
-            res.update(bench_binned_config4(P, torch, np, dev, b4, xyzr,
+            res.update(bench_binned_sets(P, torch, np, dev, b4, xyzr,
                                             torch.from_numpy(b4.offsets).to(dev)))
         print(json.dumps({"binned": res}), flush=True)
         return
 
     # headline workload
     n = 2 ** 20
-    s = w.config2(n)
+    s = w.spheres_2p24(n)
     x, y, z, r = (torch.from_numpy(v).to(dev) for v in s.arrays())
     out = torch.empty(1, dtype=torch.int64, device=dev)
     pairs = n * (n - 1) // 2
@@ -737,7 +737,7 @@ def main():
         "config": {"workload": "single set, N=2^20 int32 spheres, centres in [0,2^24)^3, "
                                "radii in [1,2^14], seed 2; exact collision count",
                    "n": n, "pair_tests": pairs, "parallelism": "single GPU"},
-        "result": {"count": count, "matches_oracle": count == golden()["config2_even_count"]},
+        "result": {"count": count, "matches_oracle": count == golden()["spheres_2p20_count"]},
         "paper_context": PAPER_CONTEXT,
         "timing": {"ms_min": float(np.min(ms)), "ms_median": float(np.median(ms)),
                    "ms_iqr": float(np.percentile(ms, 75) - np.percentile(ms, 25)),
@@ -764,7 +764,7 @@ def main():
     if not a.no_secondary:
         sec = {}
         n2 = 2 ** 20 - 1
-        s2 = w.config2(n2)
+        s2 = w.spheres_2p24(n2)
         t2 = [torch.from_numpy(v).to(dev) for v in s2.arrays()]
         p2 = n2 * (n2 - 1) // 2
         log(f"[bench] count_i32 N={n2}")
@@ -774,7 +774,7 @@ def main():
                                        "valu_frac": p2 / (m2 * 1e-3) * C_ALG["count_i32"] / VALU_PEAK,
                                        "count": int(out.item())}
         del t2
-        s1 = w.config1()
+        s1 = w.spheres_4096()
         t1 = [torch.from_numpy(v).to(dev) for v in s1.arrays()]
         p1 = 4096 * 4095 // 2
         log("[bench] count_i32 N=4096")
@@ -782,7 +782,7 @@ def main():
         m1 = float(np.median(ms1))
         sec["count_i32_4096"] = {"ms": m1, "G_pairs_per_s": p1 / m1 / 1e6, "count": int(out.item())}
         sec["count_i32_4096"]["graph_of_1000_calls"] = graph_per_call(torch, P, t1, out, 1000)
-        p3 = w.config3()
+        p3 = w.particles_unit_cube()
         t3 = [torch.from_numpy(v).to(dev) for v in p3.arrays()]
         n3 = p3.n
         E = torch.empty(n3, dtype=torch.float64, device=dev)
@@ -793,7 +793,7 @@ def main():
         ms3, _ = timed_steps(lambda: P.pairs_energy_f32(*t3, 1e-4, E, tot), max(3, a.steps // 2), 1)
         m3 = float(np.mean(ms3))
         frac3 = pp3 / (m3 * 1e-3) * C_ALG["energy_f32"] / VALU_PEAK
-        ge = golden()["config3_energy_rows"]
+        ge = golden()["particles_2p18_energy_rows"]
         got_rows = E[torch.tensor(ge["rows"], device=dev)].cpu().numpy()
         want_rows = np.array(ge["E"])
         sec["energy_f32_2^18"] = {"ms": m3, "G_pairs_per_s": pp3 / m3 / 1e6,
@@ -801,8 +801,8 @@ def main():
                                   "valu_frac_at_measured_sclk": at_sclk(frac3, mhz3),
                                   "total": float(tot.item()),
                                   "rel_err_total_vs_fp64_oracle":
-                                      abs(float(tot.item()) - golden()["config3_energy_total"])
-                                      / golden()["config3_energy_total"],
+                                      abs(float(tot.item()) - golden()["particles_2p18_energy_total"])
+                                      / golden()["particles_2p18_energy_total"],
                                   "max_rel_err_per_particle_vs_fp64_oracle":
                                       float(np.max(np.abs(got_rows - want_rows) / want_rows)),
                                   "sampled_particles": len(ge["rows"])}
@@ -814,8 +814,8 @@ def main():
             "ms": m3b, "G_pairs_per_s": pp3 / m3b / 1e6, "valu_frac": frac3b,
             "per_pair_ops": C_ALG["energy_total_f32"], "sclk_mhz_measured": mhz3b,
             "valu_frac_at_measured_sclk": at_sclk(frac3b, mhz3b),
-            "rel_err_total_vs_fp64_oracle": abs(float(tot.item()) - golden()["config3_energy_total"])
-                                            / golden()["config3_energy_total"]}
+            "rel_err_total_vs_fp64_oracle": abs(float(tot.item()) - golden()["particles_2p18_energy_total"])
+                                            / golden()["particles_2p18_energy_total"]}
         log(f"[bench] energy_f64 N={n3}")
         t3d = [v.to(torch.float64) for v in t3]
         ms5, _ = timed_steps(lambda: P.pairs_energy_f64(*t3d, float(np.float32(1e-4)), E, tot),
@@ -825,9 +825,9 @@ def main():
                                   "valu_frac": pp3 / (m5 * 1e-3) * C_ALG["energy_f64"] / VALU_PEAK,
                                   "per_pair_ops": C_ALG["energy_f64"],
                                   "rel_err_total_vs_fp64_oracle":
-                                      abs(float(tot.item()) - golden()["config3_energy_total"])
-                                      / golden()["config3_energy_total"],
-                                  "inputs": "config 3's float32 positions promoted to double"}
+                                      abs(float(tot.item()) - golden()["particles_2p18_energy_total"])
+                                      / golden()["particles_2p18_energy_total"],
+                                  "inputs": "the 2^18 float32 particles promoted to double"}
         del t3d
         log(f"[bench] force_f32 N={n3}")
         Fxyz = [torch.empty(n3, dtype=torch.float64, device=dev) for _ in range(3)]
@@ -835,7 +835,7 @@ def main():
         ms4, _ = timed_steps(lambda: P.pairs_force_f32(*t3, 1e-4, *Fxyz), max(3, a.steps // 2), 1)
         m4 = float(np.mean(ms4))
         frac4 = pp3 / (m4 * 1e-3) * C_ALG["force_f32"] / VALU_PEAK
-        gf = golden()["config3_force_rows"]
+        gf = golden()["particles_2p18_force_rows"]
         got = np.stack([f[torch.tensor(gf["rows"], device=dev)].cpu().numpy() for f in Fxyz], 1)
         err = float((np.abs(got - np.array(gf["F"])).max(axis=1) / np.array(gf["S"])).max())
         sec["force_f32_2^18"] = {"ms": m4, "G_pairs_per_s": pp3 / m4 / 1e6,

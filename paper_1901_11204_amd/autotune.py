@@ -264,12 +264,12 @@ def main(argv=None):
         print(json.dumps({"kind": KIND_NAMES[kind], "table": table, "ms": times}), flush=True)
         return 0
     if a.workload == "binned-int32":
-        b = w.config4()
+        b = w.binned_sets()
         ins = tuple(torch.from_numpy(v).to(dev) for v in b.objs.arrays())
         outs = (torch.empty(b.n_sets, dtype=torch.int64, device=dev),)
         kind, note = KIND_COUNT_I32, "200000 binned int32 sets, lognormal(4,1.2) sizes, seed 5"
     else:
-        b = w.config5()
+        b = w.moving_sets()
         ins = tuple(torch.from_numpy(v).to(dev) for v in b.objs.arrays())
         outs = (torch.empty(b.n_sets, dtype=torch.float64, device=dev),
                 torch.empty(b.n_sets, dtype=torch.int64, device=dev))

@@ -1,9 +1,9 @@
-"""Write tests/golden/config_values.json: expected results of the full-size
+"""Write tests/golden/workload_values.json: expected results of the full-size
 workloads, computed by the CPU oracle only (oracle/) on inputs from workloads/.
 
     python tests/golden/make_golden.py [--threads T] [--only KEY ...]
 
-Config 2 (two sets of about 2^20 spheres, 5.5e11 pair tests each) takes tens of
+The two sets of about 2^20 spheres (5.5e11 pair tests each) take tens of
 minutes on 8 cores; the others take seconds to minutes.  Existing keys are kept
 unless recomputed.
 """
@@ -23,38 +23,38 @@ import numpy as np  # noqa: E402
 import oracle  # noqa: E402
 import workloads as w  # noqa: E402
 
-OUT = os.path.join(HERE, "config_values.json")
+OUT = os.path.join(HERE, "workload_values.json")
 FORCE_ROWS = [0, 1, 4096, 65535, 131072, 200000, 262142, 262143]
-# config 3 per-particle energies: both ends, around n/2, and 56 seeded rows
+# the 2^18 particles' per-particle energies: both ends, around n/2, and 56 seeded rows
 ENERGY_ROWS = sorted(set([0, 1, 131071, 131072, 262142, 262143] +
                          np.random.default_rng(33).integers(0, 2 ** 18, 58).tolist()))
 
 
 def compute(key, threads):
-    if key == "config1_count":
-        return oracle.count_i32(*w.config1().arrays(), threads=threads)
-    if key == "config2_even_count":
-        return oracle.count_i32(*w.config2(2 ** 20).arrays(), threads=threads)
-    if key == "config2_odd_count":
-        return oracle.count_i32(*w.config2(2 ** 20 - 1).arrays(), threads=threads)
-    if key == "config3_energy_total":
-        return oracle.energy_total(*w.config3().arrays(), np.float32(1e-4), threads=threads)
-    if key == "config4_counts":
-        b = w.config4()
+    if key == "spheres_4096_count":
+        return oracle.count_i32(*w.spheres_4096().arrays(), threads=threads)
+    if key == "spheres_2p20_count":
+        return oracle.count_i32(*w.spheres_2p24(2 ** 20).arrays(), threads=threads)
+    if key == "spheres_2p20m1_count":
+        return oracle.count_i32(*w.spheres_2p24(2 ** 20 - 1).arrays(), threads=threads)
+    if key == "particles_2p18_energy_total":
+        return oracle.energy_total(*w.particles_unit_cube().arrays(), np.float32(1e-4), threads=threads)
+    if key == "binned_sets_200k_counts":
+        b = w.binned_sets()
         c = oracle.count_i32_batched(*b.objs.arrays(), b.offsets, threads=threads)
         return {"total": int(c.sum()),
                 "sha256_le_u64": hashlib.sha256(c.astype("<u8").tobytes()).hexdigest(),
                 "first16": [int(v) for v in c[:16]]}
-    if key == "config3_energy_rows":
+    if key == "particles_2p18_energy_rows":
         rows = np.array(ENERGY_ROWS, np.int64)
-        E = oracle.energy_rows(*w.config3().arrays(), np.float32(1e-4), rows=rows,
+        E = oracle.energy_rows(*w.particles_unit_cube().arrays(), np.float32(1e-4), rows=rows,
                                threads=threads)
         return {"rows": ENERGY_ROWS, "E": E.tolist()}
-    if key == "config5_sampled_sets":
-        # 24 seeded sets of config 5, jittered by the oracle through 100 steps
+    if key == "moving_sets_50k_sampled":
+        # 24 seeded sets of the 50 000 moving sets, jittered by the oracle through 100 steps
         # (seed 6, sigma 1e-3); per-set energy and pinned-float32 count after
         # steps 0, 49 and 99
-        b = w.config5()
+        b = w.moving_sets()
         x, y, z, r = b.objs.arrays()
         sets = sorted(np.random.default_rng(55).choice(b.n_sets, 24, replace=False).tolist())
         out = {"sets": sets, "steps": [0, 49, 99], "energy": [], "count": []}
@@ -70,9 +70,9 @@ def compute(key, threads):
             out["energy"].append(en)
             out["count"].append(cn)
         return out
-    if key == "config3_force_rows":
+    if key == "particles_2p18_force_rows":
         rows = np.array(FORCE_ROWS, np.int64)
-        F, S = oracle.force_rows(*w.config3().arrays(), np.float32(1e-4), rows=rows,
+        F, S = oracle.force_rows(*w.particles_unit_cube().arrays(), np.float32(1e-4), rows=rows,
                                  threads=threads)
         return {"rows": FORCE_ROWS, "F": F.tolist(), "S": S.tolist()}
     if key in ("lattice_paper_counts", "lattice_large_counts", "lattice_short_counts"):
@@ -86,10 +86,10 @@ def compute(key, threads):
     raise KeyError(key)
 
 
-KEYS = ["config1_count", "config4_counts", "config3_energy_total", "config2_odd_count",
-        "config2_even_count", "lattice_paper_counts", "lattice_large_counts",
-        "config3_force_rows", "lattice_short_counts", "config3_energy_rows",
-        "config5_sampled_sets"]
+KEYS = ["spheres_4096_count", "binned_sets_200k_counts", "particles_2p18_energy_total", "spheres_2p20m1_count",
+        "spheres_2p20_count", "lattice_paper_counts", "lattice_large_counts",
+        "particles_2p18_force_rows", "lattice_short_counts", "particles_2p18_energy_rows",
+        "moving_sets_50k_sampled"]
 
 
 def main():

@@ -43,8 +43,8 @@ def test_ab_counts_match_oracle(variant, K):
         assert ab_count(variant, s.arrays(), K) == oracle.count_i32(*s.arrays()), (variant, K, n)
 
 
-def test_ab_variants_agree_on_config1():
-    s = w.config1()
+def test_ab_variants_agree_on_spheres_4096():
+    s = w.spheres_4096()
     want = oracle.count_i32(*s.arrays())
     for variant in (0, 1):
         for K in (1, 8):

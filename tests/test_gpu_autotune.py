@@ -32,7 +32,7 @@ def restore_shapes():
 
 def test_tune_batched_save_and_reload(tmp_path, restore_shapes):
     import torch
-    b = w.config4(n_sets=600, seed=51)
+    b = w.binned_sets(n_sets=600, seed=51)
     ins = tuple(dev(*b.objs.arrays()))
     out = torch.empty(b.n_sets, dtype=torch.int64, device="cuda")
     shapes = [(2, 272, P.FORM_STEPPING), (1, 288, P.FORM_STEPPING), (4, 512, P.FORM_BROADCAST)]

@@ -56,7 +56,7 @@ def test_batched_count_i32_edge_sizes(planned):
 
 @pytest.mark.parametrize("planned", [False, True])
 def test_batched_count_i32_lognormal(planned):
-    b = w.config4(n_sets=3000, seed=17)
+    b = w.binned_sets(n_sets=3000, seed=17)
     announce("batched count_i32 lognormal 3000 sets", planned)
     got = run_count_i32(*b.objs.arrays(), b.offsets, planned)
     want = oracle.count_i32_batched(*b.objs.arrays(), b.offsets)
@@ -117,7 +117,7 @@ def test_batched_equals_single_set_calls():
 
 def test_batched_count_f32():
     T = torch()
-    b = w.config5(n_sets=500, seed=21, size_hi=3000, radius=0.02)
+    b = w.moving_sets(n_sets=500, seed=21, size_hi=3000, radius=0.02)
     x, y, z, r = b.objs.arrays()
     counts = T.empty(b.n_sets, dtype=T.int64, device="cuda")
     (toff,) = dev(b.offsets)
@@ -130,7 +130,7 @@ def test_batched_count_f32():
 @pytest.mark.parametrize("planned", [False, True])
 def test_batched_energy(with_count, planned):
     T = torch()
-    b = w.config5(n_sets=700, seed=22, size_hi=5000, radius=0.02)
+    b = w.moving_sets(n_sets=700, seed=22, size_hi=5000, radius=0.02)
     x, y, z, r = b.objs.arrays()
     energy = T.empty(b.n_sets, dtype=T.float64, device="cuda")
     counts = T.empty(b.n_sets, dtype=T.int64, device="cuda") if with_count else None
@@ -180,17 +180,17 @@ def test_batched_validation():
                                   oracle.count_i32_batched(*s.arrays(), off))
 
 
-def test_config4_full_size():
-    b = w.config4()
-    announce("config4 full size (plan)")
+def test_binned_sets_200k_full_size():
+    b = w.binned_sets()
+    announce("200 000 binned sets, full size (plan)")
     got = run_count_i32(*b.objs.arrays(), b.offsets, True)
     want = oracle.count_i32_batched(*b.objs.arrays(), b.offsets)
     np.testing.assert_array_equal(got, want)
-    with open(os.path.join(os.path.dirname(__file__), "golden", "config_values.json")) as f:
-        g = json.load(f)["config4_counts"]
+    with open(os.path.join(os.path.dirname(__file__), "golden", "workload_values.json")) as f:
+        g = json.load(f)["binned_sets_200k_counts"]
     assert int(got.sum()) == g["total"]
     assert hashlib.sha256(got.astype("<u8").tobytes()).hexdigest() == g["sha256_le_u64"]
-    announce("config4 full size (unplanned)")
+    announce("200 000 binned sets, full size (unplanned)")
     got2 = run_count_i32(*b.objs.arrays(), b.offsets, False)
     np.testing.assert_array_equal(got2, want)
 
@@ -248,7 +248,7 @@ def check_steps(b, E, C, sets, steps, ref, n_sets):
 
 def test_graph_steps_small():
     T = torch()
-    b = w.config5(n_sets=400, seed=23, size_hi=2000)
+    b = w.moving_sets(n_sets=400, seed=23, size_hi=2000)
     x, y, z, r = b.objs.arrays()
     tx = dev(x, y, z, r)
     steps = 6
@@ -288,9 +288,9 @@ def test_graph_steps_small():
     plan.close()
 
 
-def test_config5_full_graph_sampled():
+def test_moving_sets_50k_full_graph_sampled():
     T = torch()
-    b = w.config5()
+    b = w.moving_sets()
     x, y, z, r = b.objs.arrays()
     tx = dev(x, y, z, r)
     steps = 100
@@ -299,7 +299,7 @@ def test_config5_full_graph_sampled():
     plan = P.Plan(P.KIND_ENERGY_F32, b.offsets)
     g = plan.capture_steps(tx[0], tx[1], tx[2], tx[3], seed=6, sigma=1e-3, first_step=0,
                            n_steps=steps, eps2=float(EPS2), energy=E, counts=C)
-    announce("config5 full graph, 100 steps")
+    announce("50 000 moving sets, full graph, 100 steps")
     g.launch()
     T.cuda.synchronize()
     En, Cn = E.cpu().numpy(), C.cpu().numpy()

@@ -55,7 +55,7 @@ def test_forces_batched_match_oracle(seed):
 
 
 def test_forces_batched_lognormal_and_deterministic():
-    b = w.config5(n_sets=800, seed=44, size_hi=2000)
+    b = w.moving_sets(n_sets=800, seed=44, size_hi=2000)
     a = list(b.objs.arrays()[:3])
     announce("batched forces, 800 lognormal sets")
     got = gpu_forces(b.offsets, a)

@@ -122,12 +122,12 @@ def test_validation():
     assert binned(b, 64, flags=P.FLAG_VALIDATE) == oracle.count_i32(*b)
 
 
-def test_config2_full_size(golden_dir):
+def test_spheres_2p20_full_size(golden_dir):
     # N = 2^20 spheres with radii up to 2^14: cells of 2^15
-    with open(os.path.join(golden_dir, "config_values.json")) as f:
-        want = json.load(f)["config2_even_count"]
-    s = w.config2(2 ** 20)
-    announce("binned config 2")
+    with open(os.path.join(golden_dir, "workload_values.json")) as f:
+        want = json.load(f)["spheres_2p20_count"]
+    s = w.spheres_2p24(2 ** 20)
+    announce("binned 2^20 spheres")
     assert binned(s.arrays(), 1 << 15) == want
 
 
@@ -204,17 +204,17 @@ def test_batched_one_set_equals_single_call():
     assert binned_batched(a, off, 256)[0] == binned(a, 256) == oracle.count_i32(*a)
 
 
-def test_batched_config4_full_size(golden_dir):
-    """Config 4's 200 000 sets, each the content of one 2^14 cell, binned
+def test_batched_binned_sets_200k_full_size(golden_dir):
+    """The 200 000 binned sets, each the content of one 2^14 cell, binned
     again inside each set: cells of 2^14 (one cell per set, so every set of
     more than 64 objects is a work item) and of 4096 (up to 64 cells per
     set); the per-set counts equal the stored oracle counts."""
     import hashlib
-    with open(os.path.join(golden_dir, "config_values.json")) as f:
-        g = json.load(f)["config4_counts"]
-    b = w.config4()
+    with open(os.path.join(golden_dir, "workload_values.json")) as f:
+        g = json.load(f)["binned_sets_200k_counts"]
+    b = w.binned_sets()
     for cell in (1 << 14, 4096):
-        announce("binned batched config 4", cell)
+        announce("binned batched 200 000 sets", cell)
         got = binned_batched(b.objs.arrays(), b.offsets, cell)
         assert int(got.sum()) == g["total"]
         assert hashlib.sha256(got.astype("<u8").tobytes()).hexdigest() == g["sha256_le_u64"]

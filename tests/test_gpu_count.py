@@ -39,9 +39,9 @@ def test_count_i32_matches_oracle(n):
         assert got == expect, (kind, n)
 
 
-def test_count_i32_config1():
-    s = w.config1()
-    announce("count_i32 config1")
+def test_count_i32_spheres_4096():
+    s = w.spheres_4096()
+    announce("count_i32 4096 spheres")
     assert P.count_i32(*dev(*s.arrays())) == oracle.count_i32(*s.arrays())
 
 
@@ -82,10 +82,10 @@ def test_count_i32_matrix_form(forced_shape, U):
             assert P.count_i32(*dev(*s.arrays())) == oracle.count_i32(*s.arrays()), (kind, U, n)
 
 
-def test_count_i32_matrix_form_config1(forced_shape):
+def test_count_i32_matrix_form_spheres_4096(forced_shape):
     forced_shape(P.KIND_COUNT_I32, 1, 512, P.FORM_MATRIX)
-    s = w.config1()
-    announce("count_i32 matrix form config1")
+    s = w.spheres_4096()
+    announce("count_i32 matrix form 4096 spheres")
     assert P.count_i32(*dev(*s.arrays())) == oracle.count_i32(*s.arrays())
 
 
@@ -228,18 +228,18 @@ def test_count_i32_invariances_and_partition():
 
 
 def golden():
-    with open(os.path.join(os.path.dirname(__file__), "golden", "config_values.json")) as f:
+    with open(os.path.join(os.path.dirname(__file__), "golden", "workload_values.json")) as f:
         return json.load(f)
 
 
-@pytest.mark.parametrize("n,key", [(2 ** 20, "config2_even_count"),
-                                   (2 ** 20 - 1, "config2_odd_count")])
-def test_count_i32_config2_full_size(n, key):
+@pytest.mark.parametrize("n,key", [(2 ** 20, "spheres_2p20_count"),
+                                   (2 ** 20 - 1, "spheres_2p20m1_count")])
+def test_count_i32_spheres_2p20_full_size(n, key):
     g = golden()
     if key not in g:
-        pytest.skip(f"{key} not yet in tests/golden/config_values.json")
-    s = w.config2(n)
-    announce("count_i32 config2", n)
+        pytest.skip(f"{key} not yet in tests/golden/workload_values.json")
+    s = w.spheres_2p24(n)
+    announce("count_i32 spheres", n)
     assert P.count_i32(*dev(*s.arrays())) == g[key]
 
 
@@ -286,7 +286,7 @@ def test_count_i32_calls_captured_in_a_graph():
     hold them: each replay, with eager calls on other data in between, gives
     the oracle's count."""
     import torch
-    s = w.config1()
+    s = w.spheres_4096()
     want = oracle.count_i32(*s.arrays())
     t = dev(*s.arrays())
     other = dev(*w.spheres_i32(777, 5, 32, 3, radius_lo=0).arrays())

@@ -145,7 +145,7 @@ def batched_energy(arrays, off, flags, planned, counts=True):
 
 @pytest.mark.parametrize("planned", [False, True])
 def test_batched_energy_reproducible(planned):
-    b = w.config5(n_sets=3000, seed=41, size_hi=3000)
+    b = w.moving_sets(n_sets=3000, seed=41, size_hi=3000)
     a = b.objs.arrays()
     announce("deterministic batched energy", planned)
     E0, C0 = batched_energy(a, b.offsets, DET, planned)
@@ -168,7 +168,7 @@ def test_graph_replay_equals_eager_deterministic():
     between, against eager jitter + execute on a copy of the positions: every
     step's set energies are bit-identical."""
     torch = T()
-    b = w.config5(n_sets=500, seed=43, size_hi=1500)
+    b = w.moving_sets(n_sets=500, seed=43, size_hi=1500)
     x, y, z, r = b.objs.arrays()
     steps = 3
     kind = P.KIND_ENERGY_F32 | P.PLAN_DETERMINISTIC

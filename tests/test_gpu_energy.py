@@ -90,11 +90,11 @@ def test_energy_coincident_closed_form():
     np.testing.assert_allclose(E.cpu().numpy(), (n - 1) * inv, rtol=TOL_PARTICLE)
 
 
-def test_energy_config3_full_size():
-    with open(os.path.join(os.path.dirname(__file__), "golden", "config_values.json")) as f:
+def test_energy_particles_2p18_full_size():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "workload_values.json")) as f:
         g = json.load(f)
-    p = w.config3()
-    announce("energy_f32 config3")
+    p = w.particles_unit_cube()
+    announce("energy_f32 2^18 particles")
     E, tot = P.energy_f32(*dev(*p.arrays()), eps2=float(EPS2))
     got_E = E.cpu().numpy()
     rows = np.random.default_rng(4).choice(p.n, 384, replace=False)
@@ -103,6 +103,6 @@ def test_energy_config3_full_size():
     assert np.max(np.abs(got_E[rows] - want) / want) <= TOL_PARTICLE
     # the per-particle sums add to twice the total
     assert math.fsum(got_E.tolist()) == pytest.approx(2 * tot, rel=1e-9)
-    if "config3_energy_total" in g:
-        want_tot = g["config3_energy_total"]
+    if "particles_2p18_energy_total" in g:
+        want_tot = g["particles_2p18_energy_total"]
         assert abs(tot - want_tot) <= TOL_TOTAL * want_tot

@@ -77,9 +77,9 @@ def test_softening_values(eps2):
     check(got, F, S)
 
 
-def test_config3_size_sampled_rows():
+def test_particles_2p18_sampled_rows():
     # N = 2^18 particles of the energy workload; 257 rows checked one by one
-    p = w.config3()
+    p = w.particles_unit_cube()
     announce("force 2^18")
     got = gpu_forces(p.arrays())
     rows = np.unique(np.r_[0, 1, 2 ** 17, p.n - 1,

@@ -207,7 +207,7 @@ def test_large_workload_matches_stored_oracle_values(golden_dir):
     import hashlib
     import json
     import os
-    with open(os.path.join(golden_dir, "config_values.json")) as f:
+    with open(os.path.join(golden_dir, "workload_values.json")) as f:
         g = json.load(f)["lattice_large_counts"]
     b = w.lattice_large()
     announce("lattice large stored values")

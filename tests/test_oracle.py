@@ -214,7 +214,7 @@ def test_f32_count_equals_integer_count_on_dyadic_inputs(seed):
 
 
 def test_f32_count_orientation_and_permutation():
-    b = w.config5(n_sets=1, seed=9, size_hi=4096)
+    b = w.moving_sets(n_sets=1, seed=9, size_hi=4096)
     x, y, z, r = b.objs.arrays()
     c = oracle.count_f32(x, y, z, r)
     perm = np.random.default_rng(2).permutation(len(x))
@@ -309,7 +309,7 @@ def test_batched_equals_single_sets_with_edge_sizes():
 
 
 def test_energy_count_batched_equals_single_sets():
-    b = w.config5(n_sets=40, seed=12, size_hi=300)
+    b = w.moving_sets(n_sets=40, seed=12, size_hi=300)
     x, y, z, r = b.objs.arrays()
     e, c = oracle.energy_count_f32_batched(x, y, z, r, b.offsets, EPS2)
     for k in range(b.n_sets):

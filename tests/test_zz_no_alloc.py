@@ -28,7 +28,7 @@ def both(arrays, off):
 
 
 def test_noalloc_two_calls_second_smaller():
-    big = w.config4(n_sets=20_000, seed=31)
+    big = w.binned_sets(n_sets=20_000, seed=31)
     announce("noalloc batched count, 20000 sets")
     got, ref = both(big.objs.arrays(), big.offsets)
     np.testing.assert_array_equal(got, ref)

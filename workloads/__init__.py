@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "Spheres", "Particles", "Batch",
     "spheres_i32", "particles_f32",
-    "config1", "config2", "config3", "config4", "config5",
+    "spheres_4096", "spheres_2p24", "particles_unit_cube", "binned_sets", "moving_sets",
     "lognormal_sizes", "offsets_from_sizes",
     "Beads", "lattice_walks", "lattice_normal", "lattice_paper", "lattice_large",
     "lattice_short",
@@ -94,12 +94,12 @@ def particles_f32(n: int, seed: int) -> Particles:
     return Particles(*_soa(xyz))
 
 
-def config1(seed: int = 1) -> Spheres:
+def spheres_4096(seed: int = 1) -> Spheres:
     """N=4096 int32 spheres: centres in [0, 2^16)^3, radii in [1, 2^9]."""
     return spheres_i32(4096, seed, 2 ** 16, 2 ** 9)
 
 
-def config2(n: int = 2 ** 20, seed: int | None = None) -> Spheres:
+def spheres_2p24(n: int = 2 ** 20, seed: int | None = None) -> Spheres:
     """N=2^20 (seed 2) or N=2^20-1 (seed 3) int32 spheres: centres in [0, 2^24)^3,
     radii in [1, 2^14]."""
     if seed is None:
@@ -107,7 +107,7 @@ def config2(n: int = 2 ** 20, seed: int | None = None) -> Spheres:
     return spheres_i32(n, seed, 2 ** 24, 2 ** 14)
 
 
-def config3(n: int = 2 ** 18, seed: int = 4) -> Particles:
+def particles_unit_cube(n: int = 2 ** 18, seed: int = 4) -> Particles:
     """N=2^18 float32 particles uniform in the unit cube."""
     return particles_f32(n, seed)
 
@@ -125,7 +125,7 @@ def offsets_from_sizes(sizes: np.ndarray) -> np.ndarray:
     return off
 
 
-def config4(n_sets: int = 200_000, seed: int = 5, size_hi: int = 8192) -> Batch:
+def binned_sets(n_sets: int = 200_000, seed: int = 5, size_hi: int = 8192) -> Batch:
     """Binned int32 spheres: set s is the content of one 2^14-sided cell of a 64^3 grid
     over [0, 2^20)^3.  Sizes lognormal(4, 1.2) clipped to [2, size_hi]; radii in [1, 2^8]."""
     rng = np.random.default_rng(seed)
@@ -142,8 +142,8 @@ def config4(n_sets: int = 200_000, seed: int = 5, size_hi: int = 8192) -> Batch:
     return Batch(off, Spheres(x, y, z, r))
 
 
-def config5(n_sets: int = 50_000, seed: int = 6, size_hi: int = 4096,
-            radius: float = 0.01) -> Batch:
+def moving_sets(n_sets: int = 50_000, seed: int = 6, size_hi: int = 4096,
+                radius: float = 0.01) -> Batch:
     """float32 particle sets, each in its own unit cube; sizes lognormal(5, 1) clipped to
     [2, size_hi]; a common collision radius (0.01) stored per object."""
     rng = np.random.default_rng(seed)
