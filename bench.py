@@ -87,7 +87,7 @@ def log(*a):
 class SclkSampler:
     """Engine clock (MHz) while a region runs, read every few ms from the
     amdgpu driver's sysfs table (the current level is the one marked '*');
-    None where the box does not expose it."""
+    None where the system does not expose it."""
 
     def __init__(self, period_s=0.002):
         import glob
@@ -758,7 +758,7 @@ def main():
                                                if sclk_mhz else None),
                      "sclk_source": ("amdgpu sysfs pp_dpm_sclk, mean of samples every 2 ms "
                                      "during the timed steps"
-                                     if sclk_mhz else "not exposed on this box")},
+                                     if sclk_mhz else "not exposed by the system")},
     }
 
     if not a.no_secondary:
