@@ -52,6 +52,11 @@ constexpr int kBlock = kWave * kWavesPerBlock;
 // count of 200 000 binned sets of lognormal sizes: 1.49 -> 1.43 ms).
 constexpr int kBatchWaves = 1;
 constexpr int kBatchBlock = kWave * kBatchWaves;
+// The wave's index in a batched kernel's workgroup.  With one wave per
+// workgroup it is the constant 0, which keeps the wave's LDS window at a
+// fixed address: the sweeps' LDS reads then take their addresses with no
+// per-iteration add of a window base.
+__device__ __forceinline__ int batch_wave() { return kBatchWaves == 1 ? 0 : wave_id(); }
 
 thread_local hipError_t g_last_hip_error = hipSuccess;
 
@@ -882,7 +887,7 @@ __global__ __launch_bounds__(kBatchBlock, (batched_min_waves<KindV, KMAX>())) vo
                                                          int64_t n_waves) {
     constexpr int kLdsBytes = batched_lds_bytes<KindV>();
     __shared__ __align__(16) unsigned char lds[kBatchWaves * kLdsBytes];
-    const int wave = wave_id();
+    const int wave = batch_wave();
     void *win = lds + wave * kLdsBytes;
     const int64_t w = (int64_t)blockIdx.x * kBatchWaves + wave;
     if (w >= n_waves) return;
@@ -911,7 +916,7 @@ __global__ __launch_bounds__(kBatchBlock, (batched_min_waves<KindV, KMAX>())) vo
                                                          ClassTable ct) {
     constexpr int kLdsBytes = batched_lds_bytes<KindV>();
     __shared__ __align__(16) unsigned char lds[kBatchWaves * kLdsBytes];
-    const int wave = wave_id();
+    const int wave = batch_wave();
     void *win = lds + wave * kLdsBytes;
     const int64_t stride = (int64_t)gridDim.x * kBatchWaves;
     const int64_t ntasks = src.hdr->T, B = src.hdr->B;
@@ -1013,7 +1018,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_xbatched_scan(XBatchIO io, Scan
                                                           ClassTable ct) {
     constexpr int kLdsBytes = KindV == kForceF32 ? kForceLds * 4 : kEnergy64Lds * 8;
     __shared__ __align__(16) unsigned char lds[kBatchWaves * kLdsBytes];
-    const int wave = wave_id();
+    const int wave = batch_wave();
     void *win = lds + wave * kLdsBytes;
     const int64_t stride = (int64_t)gridDim.x * kBatchWaves;
     const int64_t ntasks = src.hdr->T, B = src.hdr->B;
