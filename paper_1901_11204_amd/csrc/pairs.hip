@@ -2514,7 +2514,7 @@ pairs_status_t pairs_plan_capture_steps(pairs_plan_t plan, float *x, float *y, f
     e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
     if (st != PAIRS_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return st;
     }
     if (e != hipSuccess) return hip_fail(e);
