@@ -484,7 +484,9 @@ def bench_batched(P, w, torch, np, dev, steps):
     plan = P.Plan(P.KIND_COUNT_I32, b.offsets)
     log(f"[bench] batched count_i32: {b.n_sets} sets, {pairs} pair tests")
     mhz = sclk_during(lambda: plan.execute((x, y, z, r), (counts,)))
-    ms, _ = timed_steps(lambda: plan.execute((x, y, z, r), (counts,)), max(10, steps), 2)
+    # millisecond calls: a window of 100 calls, so that a transient slow spell
+    # of the engine clock (a few calls up to a quarter slower) weighs less
+    ms, _ = timed_steps(lambda: plan.execute((x, y, z, r), (counts,)), max(100, steps), 2)
     m = float(np.mean(ms))
     frac = pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK
     out["count_i32_binned_200k_sets"] = {
@@ -499,7 +501,7 @@ def bench_batched(P, w, torch, np, dev, steps):
                      device=dev)
     mhz = sclk_during(lambda: P.pairs_count_i32_batched(x, y, z, r, toff, counts, ws))
     ms, _ = timed_steps(lambda: P.pairs_count_i32_batched(x, y, z, r, toff, counts, ws),
-                        max(10, steps), 2)
+                        max(100, steps), 2)
     m = float(np.mean(ms))
     frac = pairs / (m * 1e-3) * C_ALG["count_i32"] / VALU_PEAK
     out.update(bench_binned_sets(P, torch, np, dev, b, (x, y, z, r), toff))
